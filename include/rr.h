@@ -1,0 +1,218 @@
+/*
+ * rr.h -- C ABI of the MI355X (gfx950) range-retrieval library.
+ *
+ * The library answers range queries (Definition 2.1 of Manohar, Kim,
+ * Blelloch, "Range Retrieval with Graph-Based Indices": every base point p
+ * with d(p, q) <= r) by searching a DiskANN/Vamana proximity graph with the
+ * paper's algorithms: beam search (Algorithm 1), the d_visited early stop
+ * (Algorithm 5), in-ball greedy expansion (Algorithm 2), doubling search
+ * (Algorithm 3) and the end-to-end adaptive search (Algorithm 6).  A dense
+ * brute-force scan (MFMA) gives exact ground truth and radii.
+ *
+ * Conventions shared by every entry point:
+ *  - every function is extern "C", never throws, and returns rr_status;
+ *    on failure rr_last_error() returns a thread-local message;
+ *  - distances are squared L2.  uint8/int8 data: exact integers (int32).
+ *    float32 data: accumulated in FP64, reported as float32;
+ *  - membership is inclusive: d <= r;
+ *  - every result list is ordered by (distance, id) ascending;
+ *  - pointers named *_host are host memory, *_dev device memory on the
+ *    current HIP device; `stream` is a hipStream_t (NULL = default stream);
+ *  - base vectors are row-major n x d without padding on input; the library
+ *    keeps its own padded device copy;
+ *  - ids are int32 in [0, n), so n < 2^31.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RR_OK = 0,
+    RR_EINVAL = 1, /* bad argument (sizes, dtype, NaN radius, malformed graph) */
+    RR_ENOMEM = 2, /* host or device allocation failed (allocator returned NULL) */
+    RR_EHIP = 3,   /* a HIP runtime call failed; message has hipGetErrorString */
+    RR_EIO = 4,    /* file I/O or format error */
+    RR_ESTATE = 5  /* call not valid in the object's state (e.g. not uploaded) */
+} rr_status;
+
+typedef enum { RR_U8 = 0, RR_I8 = 1, RR_F32 = 2 } rr_dtype;
+
+/* Search modes.
+ *  RR_PLAIN    Algorithm 1 without a stopping rule; returns the in-range
+ *              points of the final beam B (at most b of them).
+ *  RR_ES       Algorithm 1 with Algorithm 5; returns the in-range points of B.
+ *  RR_ADAPTIVE Algorithm 6: beam search (with Algorithm 5 when es_enable),
+ *              N = in-range points of B; if |N| >= lambda*b the result is
+ *              Algorithm 2 (GreedySearch) seeded with N, else N.
+ *  RR_DOUBLING Algorithm 3: beam search from S u V with b doubled until
+ *              |N| < lambda*b (Algorithm 5 inside when es_enable). */
+typedef enum { RR_PLAIN = 0, RR_ES = 1, RR_ADAPTIVE = 2, RR_DOUBLING = 3 } rr_mode;
+
+/* Distance arithmetic of the search on float32 data.
+ *  RR_EXACT         FP64 accumulation of float32 rows (integer data: exact).
+ *  RR_BF16_RECHECK  traversal on a bfloat16 copy with FP32 accumulation;
+ *                   a point whose approximate distance lies within a band of
+ *                   the radius is re-decided from its float32 row in FP64, so
+ *                   every membership decision of a returned point is exact. */
+typedef enum { RR_EXACT = 0, RR_BF16_RECHECK = 1 } rr_precision;
+
+typedef struct rr_index rr_index;
+typedef struct rr_results rr_results;
+
+/* Device-memory provider.  alloc returns device memory of at least `bytes`
+ * usable on `stream` (NULL on failure -> RR_ENOMEM); free releases it.  A
+ * NULL allocator means the library calls hipMalloc/hipFree itself. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} rr_allocator;
+
+/* DiskANN/Vamana construction parameters (the index the paper searches,
+ * Section 4.1; its appendix uses R=64, L=128, alpha=1.15 for most data). */
+typedef struct {
+    int32_t R;            /* maximum out-degree                        */
+    int32_t L;            /* beam width of the construction searches   */
+    double alpha;         /* pruning slack on the unsquared distance   */
+    int32_t passes;       /* 1: one pass with alpha; 2: alpha=1 then alpha */
+    int32_t threads;      /* host threads (0 = all cores)              */
+    uint64_t seed;        /* insertion order seed when order == NULL   */
+    const int64_t *order; /* optional insertion order (permutation of n) */
+} rr_build_params;
+
+typedef struct {
+    int32_t mode;           /* rr_mode                                     */
+    int32_t beam;           /* b >= 1                                      */
+    int32_t es_enable;      /* Algorithm 5 in RR_ADAPTIVE / RR_DOUBLING    */
+    int32_t es_visit_limit; /* vl >= 1                                     */
+    double es_radius;       /* esr, squared-distance units                 */
+    double lambda;          /* expansion threshold fraction (paper: 1)     */
+    int32_t precision;      /* rr_precision                                */
+    double recheck_margin;  /* band half-width, relative to the unsquared radius */
+    int64_t max_results_per_query; /* greedy/doubling cap; sets `truncated` */
+    int64_t max_beam;       /* doubling cap on b; sets `truncated`          */
+    int64_t result_capacity;/* results the greedy/doubling phases may hold for the
+                               whole batch (0 = auto); exceeding it is reported */
+    int32_t cache_slots;    /* LDS visited-cache entries per query (pow2, 0 = auto) */
+    int32_t waves_per_group;/* waves per workgroup of the beam kernel (0 = auto) */
+} rr_search_params;
+
+/* Per-query counters written by the search kernels. */
+typedef struct {
+    int32_t visits;        /* |V| of the beam phase (all rounds for doubling) */
+    int32_t evals;         /* distance evaluations of the beam phase          */
+    int32_t greedy_visits; /* |V| of the greedy phase                         */
+    int32_t greedy_evals;  /* distance evaluations of the greedy phase        */
+    int32_t count;         /* results returned                                */
+    int32_t final_beam;    /* b at the end (doubling), else the beam          */
+    int16_t es_fired;      /* Algorithm 5 stopped the beam phase              */
+    int16_t expanded;      /* greedy phase ran                                */
+    int16_t truncated;     /* a cap was reached; the result is incomplete     */
+    int16_t cache_overflow;/* visited cache forgot entries (evals may repeat) */
+    int32_t rechecked;     /* points re-decided in FP64 (RR_BF16_RECHECK)     */
+    int32_t rounds;        /* doubling rounds                                 */
+} rr_query_stats;
+
+typedef struct {
+    int64_t nq, total_results;
+    int64_t visits, evals, greedy_visits, greedy_evals, rechecked;
+    int64_t es_fired, expanded, truncated, cache_overflow;
+    int64_t bytes_algorithmic; /* query + adjacency + row + output bytes */
+} rr_batch_stats;
+
+const char *rr_last_error(void);
+const char *rr_version(void);
+
+void rr_default_build_params(rr_build_params *p);
+void rr_default_search_params(rr_search_params *p);
+
+/* ---------------- index ---------------- */
+
+/* build_graph: DiskANN/Vamana construction of base_host (n x d, row-major)
+ * on the host.  The index copies the vectors; it is not on the device until
+ * rr_index_to_device.  Errors: RR_EINVAL (n < 1, d < 1, R < 1, L < 1,
+ * alpha < 1, passes not 1/2, order not a permutation), RR_ENOMEM. */
+rr_status rr_index_build(const void *base_host, rr_dtype dtype, int64_t n, int32_t d,
+                         const rr_build_params *bp, rr_index **out);
+
+/* Adopt an existing graph: adj_host is n x R int32, -1 padded at the end of
+ * each row, no self loops, no repeated ids; entry in [0, n).  The index
+ * copies base and graph.  Errors: RR_EINVAL on any malformed row. */
+rr_status rr_index_from_graph(const void *base_host, rr_dtype dtype, int64_t n, int32_t d,
+                              const int32_t *adj_host, int32_t R, int32_t entry,
+                              rr_index **out);
+
+/* Copy the graph out (adj_host may be NULL to query R and entry only). */
+rr_status rr_index_graph(const rr_index *idx, int32_t *adj_host, int32_t *R_out,
+                         int32_t *entry_out);
+
+rr_status rr_index_info(const rr_index *idx, int64_t *n, int32_t *d, int32_t *dtype,
+                        int32_t *R, int32_t *entry);
+
+/* Save / load vectors, graph and metadata (little-endian binary file). */
+rr_status rr_index_save(const rr_index *idx, const char *path);
+rr_status rr_index_load(const char *path, rr_index **out);
+
+/* Upload padded vectors (and a bfloat16 copy for float32 data), the graph
+ * and the entry to the current device.  Memory comes from `alloc`.  The
+ * index is immutable afterwards; concurrent searches on several streams are
+ * allowed.  Errors: RR_ENOMEM, RR_EHIP. */
+rr_status rr_index_to_device(rr_index *idx, const rr_allocator *alloc, void *stream);
+
+void rr_index_free(rr_index *idx);
+
+/* ---------------- search (Algorithms 1, 2, 3, 5, 6) ---------------- */
+
+/* range_search: one batched search of nq queries (queries_dev: nq x d in the
+ * index dtype, unpadded).  The radius is `radius` for every query, or
+ * radius_dev[q] (nq doubles on the device) when radius_dev != NULL.  All work
+ * is enqueued on `stream`; *out owns the per-query results until
+ * rr_results_free.  Queries must stay valid until the stream reaches the
+ * end of the call's work.  nq = 0 is valid (no results).
+ * Errors: RR_EINVAL (beam < 1, vl < 1 with early stopping, NaN radius, mode
+ * or precision unknown, BF16 precision on integer data), RR_ESTATE (index
+ * not on the device), RR_ENOMEM, RR_EHIP. */
+rr_status rr_range_search(const rr_index *idx, const void *queries_dev, int64_t nq,
+                          double radius, const double *radius_dev,
+                          const rr_search_params *sp, const rr_allocator *alloc, void *stream,
+                          rr_results **out);
+
+/* Exact range search by a dense scan (Definition 2.1), for ground truth.
+ * Same arguments and result layout as rr_range_search. */
+rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t nq,
+                         double radius, const double *radius_dev, const rr_allocator *alloc,
+                         void *stream, rr_results **out);
+
+/* Squared distance from every query to its nearest base point (nq doubles on
+ * the device).  Used to choose radii. */
+rr_status rr_nn_dist(const rr_index *idx, const void *queries_dev, int64_t nq,
+                     double *nn_dev, void *stream);
+
+/* ---------------- results ---------------- */
+
+/* Total number of results (synchronizes with the stream of the search). */
+rr_status rr_results_total(const rr_results *res, int64_t *total);
+
+/* Write CSR output on `stream`: offsets_dev (nq+1 int64), ids_dev (total
+ * int32) and dists_dev (total int32 for integer data, float32 for float
+ * data), each query's list ordered by (distance, id). */
+rr_status rr_results_copy(const rr_results *res, int32_t *ids_dev, void *dists_dev,
+                          int64_t *offsets_dev, void *stream);
+
+/* Per-query counters (host array of nq, may be NULL) and their sums
+ * (may be NULL).  Synchronizes. */
+rr_status rr_results_stats(const rr_results *res, rr_query_stats *per_query_host,
+                           rr_batch_stats *agg);
+
+void rr_results_free(rr_results *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RR_H */

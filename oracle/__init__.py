@@ -75,6 +75,7 @@ def _load():
         lib.orc_brute_force.argtypes = [vp, C.c_int, i64, i32, vp, i64, dp, C.c_int,
                                         C.POINTER(_Result)]
         lib.orc_nn_dist.argtypes = [vp, C.c_int, i64, i32, vp, i64, C.c_int, dp]
+        lib.orc_pair_dists.argtypes = [vp, C.c_int, i64, i32, vp, i64, C.c_int, dp]
         lib.orc_range_search.argtypes = [vp, C.c_int, i64, i32, C.POINTER(C.c_int32), i32, i32,
                                          vp, i64, dp, C.POINTER(_Params), C.c_int,
                                          C.POINTER(_Result)]
@@ -275,17 +276,23 @@ def range_recall(truth: Result, found: Result) -> float:
     return float("nan") if tot == 0 else hit / tot
 
 
+def pair_dists(base, queries, threads=None) -> np.ndarray:
+    """All query-base squared distances as an nq x n float64 matrix."""
+    base, queries = _c(base), _c(queries)
+    out = np.empty((queries.shape[0], base.shape[0]), dtype=np.float64)
+    rc = _load().orc_pair_dists(base.ctypes.data, _dtype_code(base), base.shape[0], base.shape[1],
+                                queries.ctypes.data, queries.shape[0], _threads(threads),
+                                out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise ValueError("orc_pair_dists: invalid arguments")
+    return out
+
+
 def percentile_radius(base, queries, p, threads=None) -> float:
     """Inverted-CDF radius: the k-th smallest of all nq*n squared distances,
-    k = ceil(p * nq * n).  Enumerates every pair (small inputs only)."""
-    base, queries = _c(base), _c(queries)
-    n, nq = base.shape[0], queries.shape[0]
-    total = n * nq
-    k = max(1, math.ceil(p * total))
-    ds = np.empty(total, dtype=np.float64)
-    for i in range(nq):
-        for j in range(n):
-            ds[i * n + j] = dist(base[j], queries[i])
+    k = ceil(p * nq * n).  Enumerates every pair (moderate inputs only)."""
+    ds = pair_dists(base, queries, threads).ravel()
+    k = max(1, math.ceil(p * ds.size))
     return float(np.partition(ds, k - 1)[k - 1])
 
 

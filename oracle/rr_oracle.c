@@ -514,6 +514,29 @@ int orc_brute_force(const void *base, int dtype, int64_t n, int32_t d, const voi
     return 0;
 }
 
+/* all query-base squared distances, row-major nq x n (used to pick radii) */
+typedef struct {
+    points_t P;
+    const void *queries;
+    double *out;
+} pd_ctx_t;
+
+static void pd_body(void *arg, int64_t qi, int tid) {
+    (void)tid;
+    pd_ctx_t *c = (pd_ctx_t *)arg;
+    const void *q = (const char *)c->queries + (size_t)qi * (size_t)c->P.d * elem_size(c->P.dtype);
+    for (int64_t i = 0; i < c->P.n; i++)
+        c->out[qi * c->P.n + i] = dist_rows(c->P.dtype, row_ptr(&c->P, i), q, c->P.d);
+}
+
+int orc_pair_dists(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
+                   int64_t nq, int threads, double *out) {
+    if (n < 1 || d < 1 || nq < 0) return -1;
+    pd_ctx_t c = {{base, dtype, n, d}, queries, out};
+    parallel_for(nq, threads, pd_body, &c);
+    return 0;
+}
+
 /* per-query nearest-neighbour squared distance (used to pick radii) */
 typedef struct {
     points_t P;

@@ -62,6 +62,9 @@ double orc_dist(int dtype, const void *a, const void *b, int32_t d);
 int orc_brute_force(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
                     int64_t nq, const double *radius, int threads, orc_result *res);
 
+int orc_pair_dists(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
+                   int64_t nq, int threads, double *out);
+
 int orc_nn_dist(const void *base, int dtype, int64_t n, int32_t d, const void *queries, int64_t nq,
                 int threads, double *out);
 

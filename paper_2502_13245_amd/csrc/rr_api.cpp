@@ -1,0 +1,763 @@
+// rr_api.cpp -- C ABI of the range-retrieval library (host side).
+//
+// Index management, argument validation, device buffers and the order of
+// kernel launches for one batched search.  All arithmetic of the search runs
+// in the HIP kernels (rr_kernels.hip, rr_scan.hip).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rr_internal.h"
+
+namespace rr {
+hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
+                              hipStream_t s);
+hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s);
+rr_status vamana_build(const void *base, int dtype, int64_t n, int32_t d, const rr_build_params *bp,
+                       std::vector<int32_t> &adj, int32_t *entry);
+} // namespace rr
+
+using namespace rr;
+
+// --------------------------------------------------------------------------
+// errors
+// --------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static rr_status fail(rr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(RR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+    } while (0)
+
+extern "C" const char *rr_last_error(void) { return g_err.c_str(); }
+extern "C" const char *rr_version(void) { return "rr 0.1 (gfx950)"; }
+
+// --------------------------------------------------------------------------
+// layout helpers
+// --------------------------------------------------------------------------
+
+namespace rr {
+
+int32_t padded_row_bytes(int64_t bytes) {
+    if (bytes <= 64) return 64;
+    int64_t p = 64;
+    while (true) {
+        if (bytes <= p) return (int32_t)p;
+        if (bytes <= p * 3 / 2 && (p * 3 / 2) % 64 == 0) return (int32_t)(p * 3 / 2);
+        p *= 2;
+        if (p > (1 << 20)) return -1;
+    }
+}
+
+void row_split(int32_t row_bytes, int32_t *cpl, int32_t *g) {
+    const int32_t chunks = row_bytes / 16;
+    // chunks = 4 * 2^k  or  12 * 2^k
+    if ((chunks & (chunks - 1)) == 0) {
+        if (chunks <= 64) {
+            *cpl = 1;
+            *g = chunks;
+        } else {
+            *g = 64;
+            *cpl = chunks / 64;
+        }
+    } else {
+        // 3 * 2^k with 2^k >= 4
+        if (chunks <= 192) {
+            *cpl = 3;
+            *g = chunks / 3;
+        } else {
+            *g = 64;
+            *cpl = chunks / 64;
+        }
+    }
+}
+
+void *Allocator::alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (has_user) return user.alloc(bytes, stream, user.ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void Allocator::release(void *p) {
+    if (!p) return;
+    if (has_user) user.free(p, stream, user.ctx);
+    else (void)hipFree(p);
+}
+
+static int device_cus() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+} // namespace rr
+
+// --------------------------------------------------------------------------
+// index
+// --------------------------------------------------------------------------
+
+struct rr_index {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t dtype = 0;
+    int32_t R = 0;
+    int32_t entry = 0;
+    std::vector<uint8_t> base; // n x d x esize, unpadded
+    std::vector<int32_t> adj;  // n x R
+    // device
+    bool on_device = false;
+    int device = -1;
+    rr::Allocator alloc;
+    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr;
+    DevIndex dev;
+};
+
+static int esize(int dtype) { return dtype == RR_F32 ? 4 : 1; }
+
+static rr_status check_dtype(int dtype) {
+    if (dtype != RR_U8 && dtype != RR_I8 && dtype != RR_F32)
+        return fail(RR_EINVAL, "unknown dtype %d", dtype);
+    return RR_OK;
+}
+
+static rr_status validate_graph(const int32_t *adj, int64_t n, int32_t R, int32_t entry) {
+    if (R < 0 || R > 64) return fail(RR_EINVAL, "R must be in [0, 64] (got %d)", R);
+    if (entry < 0 || entry >= n) return fail(RR_EINVAL, "entry %d out of range", entry);
+    std::vector<int32_t> row(R);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *a = adj + i * (int64_t)R;
+        int32_t deg = 0;
+        while (deg < R && a[deg] >= 0) ++deg;
+        for (int32_t j = deg; j < R; ++j)
+            if (a[j] != -1) return fail(RR_EINVAL, "row %lld: -1 padding must end the row", (long long)i);
+        for (int32_t j = 0; j < deg; ++j) {
+            if (a[j] >= n) return fail(RR_EINVAL, "row %lld: id %d out of range", (long long)i, a[j]);
+            if (a[j] == i) return fail(RR_EINVAL, "row %lld: self loop", (long long)i);
+            row[j] = a[j];
+        }
+        std::sort(row.begin(), row.begin() + deg);
+        for (int32_t j = 1; j < deg; ++j)
+            if (row[j] == row[j - 1]) return fail(RR_EINVAL, "row %lld: repeated id %d", (long long)i, row[j]);
+    }
+    return RR_OK;
+}
+
+extern "C" void rr_default_build_params(rr_build_params *p) {
+    if (!p) return;
+    p->R = 64;
+    p->L = 128;
+    p->alpha = 1.2;
+    p->passes = 2;
+    p->threads = 0;
+    p->seed = 0;
+    p->order = nullptr;
+}
+
+extern "C" void rr_default_search_params(rr_search_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->mode = RR_ADAPTIVE;
+    p->beam = 32;
+    p->es_enable = 0;
+    p->es_visit_limit = 20;
+    p->es_radius = 0.0;
+    p->lambda = 1.0;
+    p->precision = RR_EXACT;
+    p->recheck_margin = 0.02;
+    p->max_results_per_query = 1 << 20;
+    p->max_beam = 1 << 14;
+    p->result_capacity = 0;
+    p->cache_slots = 0;
+    p->waves_per_group = 0;
+}
+
+static rr_status new_index(const void *base, int dtype, int64_t n, int32_t d, rr_index **out) {
+    if (!out) return fail(RR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (check_dtype(dtype) != RR_OK) return RR_EINVAL;
+    if (!base) return fail(RR_EINVAL, "base is NULL");
+    if (n < 1 || n >= (1ll << 31) - 1) return fail(RR_EINVAL, "n must be in [1, 2^31-1)");
+    if (d < 1 || d > 65536) return fail(RR_EINVAL, "d must be in [1, 65536]");
+    if (padded_row_bytes((int64_t)d * esize(dtype)) < 0) return fail(RR_EINVAL, "rows too long");
+    rr_index *ix = new (std::nothrow) rr_index();
+    if (!ix) return fail(RR_ENOMEM, "host allocation failed");
+    try {
+        ix->base.assign((const uint8_t *)base, (const uint8_t *)base + (size_t)n * d * esize(dtype));
+    } catch (...) {
+        delete ix;
+        return fail(RR_ENOMEM, "host allocation failed");
+    }
+    ix->n = n;
+    ix->d = d;
+    ix->dtype = dtype;
+    *out = ix;
+    return RR_OK;
+}
+
+extern "C" rr_status rr_index_build(const void *base_host, rr_dtype dtype, int64_t n, int32_t d,
+                                    const rr_build_params *bp, rr_index **out) {
+    if (!bp) return fail(RR_EINVAL, "build params are NULL");
+    if (bp->R < 1 || bp->R > 64) return fail(RR_EINVAL, "R must be in [1, 64]");
+    if (bp->L < 1) return fail(RR_EINVAL, "L must be >= 1");
+    if (!(bp->alpha >= 1.0)) return fail(RR_EINVAL, "alpha must be >= 1");
+    if (bp->passes != 1 && bp->passes != 2) return fail(RR_EINVAL, "passes must be 1 or 2");
+    rr_index *ix = nullptr;
+    rr_status st = new_index(base_host, dtype, n, d, &ix);
+    if (st != RR_OK) return st;
+    if (bp->order) {
+        std::vector<uint8_t> seen(n, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t v = bp->order[i];
+            if (v < 0 || v >= n || seen[v]) {
+                delete ix;
+                return fail(RR_EINVAL, "order is not a permutation of [0, n)");
+            }
+            seen[v] = 1;
+        }
+    }
+    int32_t entry = 0;
+    st = rr::vamana_build(ix->base.data(), dtype, n, d, bp, ix->adj, &entry);
+    if (st != RR_OK) {
+        delete ix;
+        return st;
+    }
+    ix->R = bp->R;
+    ix->entry = entry;
+    *out = ix;
+    return RR_OK;
+}
+
+extern "C" rr_status rr_index_from_graph(const void *base_host, rr_dtype dtype, int64_t n, int32_t d,
+                                         const int32_t *adj_host, int32_t R, int32_t entry,
+                                         rr_index **out) {
+    if (!adj_host && R > 0) return fail(RR_EINVAL, "adj is NULL");
+    if (out) *out = nullptr;
+    if (n >= 1 && validate_graph(adj_host, n, R, entry) != RR_OK) return RR_EINVAL;
+    rr_index *ix = nullptr;
+    rr_status st = new_index(base_host, dtype, n, d, &ix);
+    if (st != RR_OK) return st;
+    try {
+        ix->adj.assign(adj_host, adj_host + (size_t)n * R);
+    } catch (...) {
+        delete ix;
+        return fail(RR_ENOMEM, "host allocation failed");
+    }
+    ix->R = R;
+    ix->entry = entry;
+    *out = ix;
+    return RR_OK;
+}
+
+extern "C" rr_status rr_index_graph(const rr_index *ix, int32_t *adj_host, int32_t *R_out,
+                                    int32_t *entry_out) {
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (R_out) *R_out = ix->R;
+    if (entry_out) *entry_out = ix->entry;
+    if (adj_host) std::memcpy(adj_host, ix->adj.data(), ix->adj.size() * sizeof(int32_t));
+    return RR_OK;
+}
+
+extern "C" rr_status rr_index_info(const rr_index *ix, int64_t *n, int32_t *d, int32_t *dtype,
+                                   int32_t *R, int32_t *entry) {
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (n) *n = ix->n;
+    if (d) *d = ix->d;
+    if (dtype) *dtype = ix->dtype;
+    if (R) *R = ix->R;
+    if (entry) *entry = ix->entry;
+    return RR_OK;
+}
+
+static const char kMagic[8] = {'R', 'R', 'I', 'D', 'X', '0', '0', '1'};
+
+extern "C" rr_status rr_index_save(const rr_index *ix, const char *path) {
+    if (!ix || !path) return fail(RR_EINVAL, "index or path is NULL");
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(RR_EIO, "cannot open %s for writing", path);
+    int64_t hdr[5] = {ix->n, ix->d, ix->dtype, ix->R, ix->entry};
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+              std::fwrite(ix->base.data(), 1, ix->base.size(), f) == ix->base.size() &&
+              std::fwrite(ix->adj.data(), sizeof(int32_t), ix->adj.size(), f) == ix->adj.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(RR_EIO, "write to %s failed", path);
+    return RR_OK;
+}
+
+extern "C" rr_status rr_index_load(const char *path, rr_index **out) {
+    if (!path || !out) return fail(RR_EINVAL, "path or out is NULL");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(RR_EIO, "cannot open %s", path);
+    char magic[8];
+    int64_t hdr[5];
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, kMagic, 8) != 0 ||
+        std::fread(hdr, sizeof hdr, 1, f) != 1) {
+        std::fclose(f);
+        return fail(RR_EIO, "%s is not an index file", path);
+    }
+    const int64_t n = hdr[0];
+    const int32_t d = (int32_t)hdr[1], dtype = (int32_t)hdr[2], R = (int32_t)hdr[3],
+                  entry = (int32_t)hdr[4];
+    if (check_dtype(dtype) != RR_OK || n < 1 || d < 1 || R < 0 || R > 64 || entry < 0 || entry >= n) {
+        std::fclose(f);
+        return fail(RR_EIO, "%s: corrupt header", path);
+    }
+    std::vector<uint8_t> base;
+    std::vector<int32_t> adj;
+    try {
+        base.resize((size_t)n * d * esize(dtype));
+        adj.resize((size_t)n * R);
+    } catch (...) {
+        std::fclose(f);
+        return fail(RR_ENOMEM, "host allocation failed");
+    }
+    bool ok = std::fread(base.data(), 1, base.size(), f) == base.size() &&
+              std::fread(adj.data(), sizeof(int32_t), adj.size(), f) == adj.size();
+    std::fclose(f);
+    if (!ok) return fail(RR_EIO, "%s: truncated", path);
+    return rr_index_from_graph(base.data(), (rr_dtype)dtype, n, d, adj.data(), R, entry, out);
+}
+
+static void free_device(rr_index *ix) {
+    if (!ix->on_device) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (ix->device >= 0) (void)hipSetDevice(ix->device);
+    ix->alloc.release(ix->d_base);
+    ix->alloc.release(ix->d_bf16);
+    ix->alloc.release(ix->d_adj);
+    ix->d_base = ix->d_bf16 = ix->d_adj = nullptr;
+    ix->on_device = false;
+    if (cur >= 0) (void)hipSetDevice(cur);
+}
+
+static uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40); // NaN
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc, void *stream) {
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    free_device(ix);
+    hipStream_t s = (hipStream_t)stream;
+    ix->alloc = rr::Allocator();
+    if (alloc && alloc->alloc && alloc->free) {
+        ix->alloc.user = *alloc;
+        ix->alloc.has_user = true;
+    }
+    ix->alloc.stream = stream;
+    HIP_TRY(hipGetDevice(&ix->device));
+    const int es = esize(ix->dtype);
+    const int32_t rb = padded_row_bytes((int64_t)ix->d * es);
+    std::vector<uint8_t> pad((size_t)ix->n * rb, 0);
+    for (int64_t i = 0; i < ix->n; ++i)
+        std::memcpy(pad.data() + (size_t)i * rb, ix->base.data() + (size_t)i * ix->d * es,
+                    (size_t)ix->d * es);
+    ix->d_base = ix->alloc.alloc(pad.size());
+    if (!ix->d_base) return fail(RR_ENOMEM, "device allocation of %zu bytes failed", pad.size());
+    ix->on_device = true;
+    HIP_TRY(hipMemcpyAsync(ix->d_base, pad.data(), pad.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t rb16 = 0;
+    float maxn = 0.f;
+    if (ix->dtype == RR_F32) {
+        rb16 = padded_row_bytes((int64_t)ix->d * 2);
+        std::vector<uint16_t> h((size_t)ix->n * (rb16 / 2), 0);
+        const float *x = (const float *)ix->base.data();
+        for (int64_t i = 0; i < ix->n; ++i) {
+            double nn = 0;
+            for (int32_t j = 0; j < ix->d; ++j) {
+                float v = x[(size_t)i * ix->d + j];
+                h[(size_t)i * (rb16 / 2) + j] = f32_to_bf16_rne(v);
+                nn += (double)v * v;
+            }
+            maxn = std::max(maxn, (float)std::sqrt(nn));
+        }
+        ix->d_bf16 = ix->alloc.alloc(h.size() * 2);
+        if (!ix->d_bf16) return fail(RR_ENOMEM, "device allocation failed");
+        HIP_TRY(hipMemcpyAsync(ix->d_bf16, h.data(), h.size() * 2, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const size_t adj_bytes = std::max<size_t>(ix->adj.size() * sizeof(int32_t), 4);
+    ix->d_adj = ix->alloc.alloc(adj_bytes);
+    if (!ix->d_adj) return fail(RR_ENOMEM, "device allocation failed");
+    if (!ix->adj.empty()) {
+        HIP_TRY(hipMemcpyAsync(ix->d_adj, ix->adj.data(), ix->adj.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    DevIndex &dv = ix->dev;
+    dv.n = ix->n;
+    dv.d = ix->d;
+    dv.dtype = ix->dtype;
+    dv.R = ix->R;
+    dv.entry = ix->entry;
+    dv.row_bytes = rb;
+    dv.row_bytes_bf16 = rb16;
+    dv.base = (const uint8_t *)ix->d_base;
+    dv.base_bf16 = (const uint8_t *)ix->d_bf16;
+    dv.adj = (const int32_t *)ix->d_adj;
+    dv.max_norm = maxn;
+    return RR_OK;
+}
+
+extern "C" void rr_index_free(rr_index *ix) {
+    if (!ix) return;
+    free_device(ix);
+    delete ix;
+}
+
+// --------------------------------------------------------------------------
+// results
+// --------------------------------------------------------------------------
+
+struct rr_results {
+    int64_t nq = 0;
+    int32_t dtype = 0;
+    int32_t precision = 0;
+    int32_t R = 0;
+    int32_t row_bytes = 0;
+    int32_t d = 0;
+    int32_t es = 1;
+    hipStream_t stream = nullptr;
+    rr::Allocator alloc;
+    void *block = nullptr; // one allocation carved into the buffers below
+    SearchBufs sb;
+    int64_t *offsets = nullptr; // [nq + 1] scanned counts
+    void *scan_tmp = nullptr;
+    DevIndex ix;
+    bool stats_valid = true;
+};
+
+extern "C" void rr_results_free(rr_results *res) {
+    if (!res) return;
+    res->alloc.release(res->block);
+    delete res;
+}
+
+struct Carver {
+    size_t off = 0;
+    template <typename T> size_t take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        size_t o = off;
+        off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        return o;
+    }
+};
+
+static int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static rr_status make_results(const rr_index *ix, int64_t nq, const rr_search_params *sp,
+                              bool with_greedy, int64_t arena_cap, int64_t item_cap,
+                              int64_t hash_cap, const rr_allocator *alloc, void *stream,
+                              rr_results **out) {
+    rr_results *res = new (std::nothrow) rr_results();
+    if (!res) return fail(RR_ENOMEM, "host allocation failed");
+    res->nq = nq;
+    res->dtype = ix->dtype;
+    res->precision = sp ? sp->precision : 0;
+    res->R = ix->R;
+    res->row_bytes = ix->dev.row_bytes;
+    res->d = ix->d;
+    res->es = esize(ix->dtype);
+    res->stream = (hipStream_t)stream;
+    res->ix = ix->dev;
+    if (alloc && alloc->alloc && alloc->free) {
+        res->alloc.user = *alloc;
+        res->alloc.has_user = true;
+    }
+    res->alloc.stream = stream;
+    const size_t dsz = ix->dtype == RR_F32 ? 8 : 4;
+    Carver c;
+    size_t o_qpad = c.take<uint8_t>(nq * (int64_t)ix->dev.row_bytes);
+    size_t o_qth = c.take<QThresh>(nq);
+    size_t o_ctr = c.take<unsigned long long>(CTR_COUNT);
+    size_t o_roff = c.take<int64_t>(nq);
+    size_t o_rcnt = c.take<int32_t>(nq);
+    size_t o_stats = c.take<rr_query_stats>(nq);
+    size_t o_aid = c.take<int32_t>(arena_cap);
+    size_t o_ad = c.take<uint8_t>(arena_cap * (int64_t)dsz);
+    size_t o_off = c.take<int64_t>(nq + 1);
+    size_t o_scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
+    size_t o_tq = 0, o_tc = 0, o_te = 0, o_it = 0, o_ii = 0, o_idist = 0, o_lvl = 0, o_hash = 0,
+           o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0;
+    const int32_t max_levels = 4096;
+    if (with_greedy) {
+        o_tq = c.take<int32_t>(nq);
+        o_tc = c.take<unsigned long long>(nq);
+        o_te = c.take<unsigned long long>(nq);
+        o_it = c.take<int32_t>(item_cap);
+        o_ii = c.take<int32_t>(item_cap);
+        o_idist = c.take<uint8_t>(item_cap * (int64_t)dsz);
+        o_lvl = c.take<unsigned long long>(max_levels);
+        o_hash = c.take<unsigned long long>(hash_cap);
+        o_soff = c.take<int64_t>(nq + 1);
+        o_scur = c.take<unsigned long long>(nq);
+        o_sid = c.take<int32_t>(item_cap);
+        o_sd = c.take<uint8_t>(item_cap * (int64_t)dsz);
+    }
+    const size_t total = c.take<uint8_t>(1);
+    res->block = res->alloc.alloc(total);
+    if (!res->block) {
+        delete res;
+        return fail(RR_ENOMEM, "device allocation of %zu bytes failed", total);
+    }
+    uint8_t *b = (uint8_t *)res->block;
+    SearchBufs &sb = res->sb;
+    sb.qpad = b + o_qpad;
+    sb.qth = (QThresh *)(b + o_qth);
+    sb.counters = (unsigned long long *)(b + o_ctr);
+    sb.res_off = (int64_t *)(b + o_roff);
+    sb.res_cnt = (int32_t *)(b + o_rcnt);
+    sb.stats = (rr_query_stats *)(b + o_stats);
+    sb.arena_ids = (int32_t *)(b + o_aid);
+    sb.arena_dists = b + o_ad;
+    sb.arena_cap = arena_cap;
+    res->offsets = (int64_t *)(b + o_off);
+    res->scan_tmp = b + o_scan;
+    if (with_greedy) {
+        sb.task_q = (int32_t *)(b + o_tq);
+        sb.task_cnt = (unsigned long long *)(b + o_tc);
+        sb.task_evals = (unsigned long long *)(b + o_te);
+        sb.item_task = (int32_t *)(b + o_it);
+        sb.item_id = (int32_t *)(b + o_ii);
+        sb.item_dist = b + o_idist;
+        sb.item_cap = item_cap;
+        sb.level_cnt = (unsigned long long *)(b + o_lvl);
+        sb.max_levels = max_levels;
+        sb.hash = (unsigned long long *)(b + o_hash);
+        sb.hash_cap = hash_cap;
+        sb.seg_off = (int64_t *)(b + o_soff);
+        sb.seg_cur = (unsigned long long *)(b + o_scur);
+        sb.seg_ids = (int32_t *)(b + o_sid);
+        sb.seg_dists = b + o_sd;
+    }
+    *out = res;
+    return RR_OK;
+}
+
+static rr_status check_radius(double r) {
+    if (std::isnan(r)) return fail(RR_EINVAL, "radius is NaN");
+    return RR_OK;
+}
+
+extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                     double radius, const double *radius_dev,
+                                     const rr_search_params *sp, const rr_allocator *alloc,
+                                     void *stream, rr_results **out) {
+    if (!out) return fail(RR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ix || !sp) return fail(RR_EINVAL, "index or params are NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
+    if (nq > 0 && !queries_dev) return fail(RR_EINVAL, "queries are NULL");
+    if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
+    if (sp->mode < RR_PLAIN || sp->mode > RR_DOUBLING) return fail(RR_EINVAL, "unknown mode %d", sp->mode);
+    if (sp->mode == RR_DOUBLING) return fail(RR_EINVAL, "doubling search is not available in this build");
+    if (sp->beam < 1 || sp->beam > 4096) return fail(RR_EINVAL, "beam must be in [1, 4096]");
+    const bool es = sp->mode == RR_ES || (sp->mode == RR_ADAPTIVE && sp->es_enable);
+    if (es && sp->es_visit_limit < 1) return fail(RR_EINVAL, "es_visit_limit must be >= 1");
+    if (es && std::isnan(sp->es_radius)) return fail(RR_EINVAL, "es_radius is NaN");
+    if (!(sp->lambda >= 0.0)) return fail(RR_EINVAL, "lambda must be >= 0");
+    if (sp->precision != RR_EXACT && sp->precision != RR_BF16_RECHECK)
+        return fail(RR_EINVAL, "unknown precision %d", sp->precision);
+    if (sp->precision == RR_BF16_RECHECK)
+        return fail(RR_EINVAL, "bf16 precision is not available in this build");
+    if (ix->dev.dtype != ix->dtype) return fail(RR_ESTATE, "index state is inconsistent");
+
+    SearchCfg cfg{};
+    cfg.mode = sp->mode;
+    cfg.beam = sp->beam;
+    cfg.es_enable = es ? 1 : 0;
+    cfg.vl = sp->es_visit_limit;
+    cfg.expand_thresh = (int32_t)std::min<double>(std::ceil(sp->lambda * sp->beam), 1e9);
+    cfg.precision = sp->precision;
+    int cs = sp->cache_slots > 0 ? sp->cache_slots : 2048;
+    if (cs & (cs - 1)) return fail(RR_EINVAL, "cache_slots must be a power of two");
+    if (cs < 64 || cs > 16384) return fail(RR_EINVAL, "cache_slots must be in [64, 16384]");
+    cfg.cache_slots = cs;
+    int waves = sp->waves_per_group > 0 ? sp->waves_per_group : 4;
+    if (waves > 8) return fail(RR_EINVAL, "waves_per_group must be <= 8");
+    cfg.waves = waves;
+    cfg.max_results_per_query = sp->max_results_per_query;
+    cfg.max_beam = sp->max_beam;
+    cfg.margin = sp->recheck_margin;
+    const size_t per_wave = (size_t)(ix->dtype == RR_F32 ? 24 : 16) * sp->beam + 64 * 12 + cs * 4 + 128;
+    if (per_wave * waves > 160 * 1024) return fail(RR_EINVAL, "beam/cache_slots/waves exceed LDS");
+
+    const bool greedy = sp->mode == RR_ADAPTIVE;
+    int64_t gcap = 0, hash_cap = 0, item_cap = 0;
+    if (greedy) {
+        gcap = sp->result_capacity > 0 ? sp->result_capacity
+                                       : std::min<int64_t>(std::max<int64_t>(nq, 1) * 4096, 1 << 21);
+        item_cap = nq * (int64_t)sp->beam + gcap;
+        hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024));
+    }
+    const int64_t arena_cap = nq * (int64_t)sp->beam + gcap;
+    rr_results *res = nullptr;
+    rr_status st = make_results(ix, nq, sp, greedy, arena_cap, item_cap, hash_cap, alloc, stream, &res);
+    if (st != RR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    SearchBufs &sb = res->sb;
+#define HIP_TRY_R(expr)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            rr_results_free(res);                                                             \
+            return fail(RR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+        }                                                                                     \
+    } while (0)
+    HIP_TRY_R(launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s));
+    if (greedy) {
+        HIP_TRY_R(launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s));
+        HIP_TRY_R(launch_fill_u64(sb.hash, sb.hash_cap, ~0ull, s));
+    }
+    HIP_TRY_R(launch_prep_queries(ix->dev, queries_dev, nq, radius, radius_dev, cfg, sb, s));
+    HIP_TRY_R(launch_set_esr(sb.qth, nq, sp->es_radius, s));
+    const int cus = device_cus();
+    HIP_TRY_R(launch_beam(ix->dev, nq, cfg, sb, cus, s));
+    if (greedy) HIP_TRY_R(launch_greedy(ix->dev, nq, cfg, sb, cus, s));
+    HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
+#undef HIP_TRY_R
+    *out = res;
+    return RR_OK;
+}
+
+extern "C" rr_status rr_brute_force(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                    double radius, const double *radius_dev,
+                                    const rr_allocator *alloc, void *stream, rr_results **out) {
+    if (!out) return fail(RR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
+    if (nq > 0 && !queries_dev) return fail(RR_EINVAL, "queries are NULL");
+    if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
+    return fail(RR_EINVAL, "brute force is not available in this build");
+}
+
+extern "C" rr_status rr_nn_dist(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                double *nn_dev, void *stream) {
+    (void)queries_dev;
+    (void)nn_dev;
+    (void)stream;
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (nq < 0) return fail(RR_EINVAL, "nq out of range");
+    return fail(RR_EINVAL, "nn_dist is not available in this build");
+}
+
+extern "C" rr_status rr_results_total(const rr_results *res, int64_t *total) {
+    if (!res || !total) return fail(RR_EINVAL, "results or total is NULL");
+    HIP_TRY(hipStreamSynchronize(res->stream));
+    unsigned long long ctr[CTR_COUNT];
+    HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    HIP_TRY(hipMemcpy(&tot, res->offsets + res->nq, sizeof tot, hipMemcpyDeviceToHost));
+    *total = tot;
+    if (ctr[CTR_OVERFLOW])
+        return fail(RR_ENOMEM,
+                    "a search capacity was exceeded (code %llu); raise result_capacity or "
+                    "max_results_per_query", (unsigned long long)ctr[CTR_OVERFLOW]);
+    return RR_OK;
+}
+
+extern "C" rr_status rr_results_copy(const rr_results *res, int32_t *ids_dev, void *dists_dev,
+                                     int64_t *offsets_dev, void *stream) {
+    if (!res) return fail(RR_EINVAL, "results are NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (s != res->stream) {
+        // order after the search: wait for its stream
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev, res->stream));
+        HIP_TRY(hipStreamWaitEvent(s, ev, 0));
+        HIP_TRY(hipEventDestroy(ev));
+    }
+    if (res->nq == 0) {
+        if (offsets_dev) HIP_TRY(hipMemsetAsync(offsets_dev, 0, sizeof(int64_t), s));
+        return RR_OK;
+    }
+    if (!ids_dev || !dists_dev || !offsets_dev) return fail(RR_EINVAL, "output buffers are NULL");
+    HIP_TRY(hipMemcpyAsync(offsets_dev, res->offsets, (res->nq + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_results_copy(res->dtype, res->precision, res->ix, res->sb.qpad, res->nq,
+                                res->sb.res_off, res->sb.res_cnt, res->sb.arena_ids,
+                                res->sb.arena_dists, ids_dev, dists_dev, offsets_dev,
+                                res->scan_tmp, s));
+    return RR_OK;
+}
+
+extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per_query_host,
+                                      rr_batch_stats *agg) {
+    if (!res) return fail(RR_EINVAL, "results are NULL");
+    HIP_TRY(hipStreamSynchronize(res->stream));
+    std::vector<rr_query_stats> st((size_t)std::max<int64_t>(res->nq, 1));
+    if (res->nq > 0)
+        HIP_TRY(hipMemcpy(st.data(), res->sb.stats, res->nq * sizeof(rr_query_stats),
+                          hipMemcpyDeviceToHost));
+    if (per_query_host && res->nq > 0)
+        std::memcpy(per_query_host, st.data(), res->nq * sizeof(rr_query_stats));
+    if (agg) {
+        std::memset(agg, 0, sizeof *agg);
+        agg->nq = res->nq;
+        const int64_t row = (int64_t)res->d * res->es;
+        for (int64_t i = 0; i < res->nq; ++i) {
+            const rr_query_stats &q = st[i];
+            agg->total_results += q.count;
+            agg->visits += q.visits;
+            agg->evals += q.evals;
+            agg->greedy_visits += q.greedy_visits;
+            agg->greedy_evals += q.greedy_evals;
+            agg->rechecked += q.rechecked;
+            agg->es_fired += q.es_fired;
+            agg->expanded += q.expanded;
+            agg->truncated += q.truncated;
+            agg->cache_overflow += q.cache_overflow;
+        }
+        // query + adjacency rows of visited points + rows of evaluated points + output
+        agg->bytes_algorithmic = res->nq * row + (agg->visits + agg->greedy_visits) * 4ll * res->R +
+                                 (agg->evals + agg->greedy_evals) * row + agg->total_results * 8ll;
+    }
+    return RR_OK;
+}

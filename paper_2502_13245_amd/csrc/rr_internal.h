@@ -1,0 +1,137 @@
+// rr_internal.h -- types shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rr.h"
+
+namespace rr {
+
+// Padded row stride for `bytes` of vector data: the next value of the form
+// 64 * 2^k or 192 * 2^k, so a row splits into G lanes x CPL 16-byte chunks
+// with G a power of two and CPL in {1, 2, 3, 4, 6}.
+int32_t padded_row_bytes(int64_t bytes);
+// (CPL, G) for a padded row stride.
+void row_split(int32_t row_bytes, int32_t *cpl, int32_t *g);
+
+struct DevMem {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Allocator {
+    rr_allocator user{};
+    bool has_user = false;
+    void *stream = nullptr;
+    void *alloc(size_t bytes);
+    void release(void *p);
+};
+
+// Device view of an index (plain pointers; passed to kernels by value).
+struct DevIndex {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t dtype = 0;
+    int32_t R = 0;
+    int32_t entry = 0;
+    int32_t row_bytes = 0;      // padded stride of `base`
+    int32_t row_bytes_bf16 = 0; // padded stride of `base_bf16` (float data)
+    const uint8_t *base = nullptr;
+    const uint8_t *base_bf16 = nullptr;
+    const int32_t *adj = nullptr;
+    float max_norm = 0.f; // largest |x| (float data)
+};
+
+// Per-query thresholds derived from the radius (written by a prep kernel).
+struct QThresh {
+    double r;        // squared radius
+    double esr;      // early-stop radius (squared units)
+    int64_t r_int;   // integer data: d <= r  <=>  d <= r_int
+    int64_t esr_int; // integer data: d > esr <=>  d > esr_int
+    float r_f;       // approximate pass: radius in squared units
+    float esr_f;
+    float lo, hi;    // approximate pass: accept if s <= lo, reject if s > hi
+};
+
+struct SearchCfg {
+    int32_t mode;
+    int32_t beam;
+    int32_t es_enable;
+    int32_t vl;
+    int32_t expand_thresh; // ceil(lambda * beam)
+    int32_t precision;
+    int32_t cache_slots;   // power of two
+    int32_t waves;         // waves per workgroup
+    int64_t max_results_per_query;
+    int64_t max_beam;
+    double margin;         // relative recheck band
+};
+
+// Device-side state of one batched search (all arrays on the device).
+struct SearchBufs {
+    // queries
+    uint8_t *qpad = nullptr;      // [nq][row_bytes] padded queries (float data: fp32)
+    QThresh *qth = nullptr;       // [nq]
+    // work queue / counters (int64 slots, zeroed before the search)
+    unsigned long long *counters = nullptr; // see CTR_* below
+    // per-query outputs
+    int64_t *res_off = nullptr;   // [nq] offset into the arena
+    int32_t *res_cnt = nullptr;   // [nq]
+    rr_query_stats *stats = nullptr; // [nq]
+    // result arena
+    int32_t *arena_ids = nullptr;
+    void *arena_dists = nullptr;  // uint32 (int data) / double (float data)
+    int64_t arena_cap = 0;
+    // greedy expansion
+    int32_t *task_q = nullptr;    // [nq] query of each task
+    unsigned long long *task_cnt = nullptr;   // [nq] results per task
+    unsigned long long *task_evals = nullptr; // [nq]
+    int32_t *item_task = nullptr; // [item_cap]
+    int32_t *item_id = nullptr;
+    void *item_dist = nullptr;
+    int64_t item_cap = 0;
+    unsigned long long *level_cnt = nullptr; // [max_levels]
+    int32_t max_levels = 0;
+    unsigned long long *hash = nullptr; // [hash_cap] (task << 32 | id), ~0 = empty
+    int64_t hash_cap = 0;
+    int64_t *seg_off = nullptr;   // [nq + 1] per-task segment offsets
+    unsigned long long *seg_cur = nullptr;   // [nq]
+    int32_t *seg_ids = nullptr;   // [item_cap]
+    void *seg_dists = nullptr;
+};
+
+enum {
+    CTR_QUEUE = 0,     // next query to take
+    CTR_ARENA = 1,     // arena cursor
+    CTR_TASKS = 2,     // number of expansion tasks
+    CTR_OVERFLOW = 3,  // non-zero: some capacity was exceeded
+    CTR_LEVELS = 4,    // levels run by the greedy phase
+    CTR_COUNT = 8
+};
+
+// kernel launchers (rr_kernels.hip)
+hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t nq, double radius,
+                               const double *radius_dev, const SearchCfg &cfg, SearchBufs &sb,
+                               hipStream_t s);
+hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                       int num_cus, hipStream_t s);
+hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                         int num_cus, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, const uint8_t *qpad,
+                               int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
+                               const int32_t *arena_ids, const void *arena_dists, int32_t *ids,
+                               void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s);
+size_t results_copy_tmp_bytes(int64_t nq);
+
+// brute force (rr_scan.hip)
+hipError_t launch_brute_force(const DevIndex &ix, const uint8_t *qpad, const QThresh *qth,
+                              int64_t nq, SearchBufs &sb, int num_cus, hipStream_t s);
+hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, double *nn,
+                          hipStream_t s);
+
+} // namespace rr

@@ -1,0 +1,1136 @@
+// rr_kernels.hip -- range search over a proximity graph on gfx950.
+//
+// One wavefront (64 lanes) runs one query's beam search (Algorithm 1) with
+// the d_visited early stop (Algorithm 5).  Queries come from a device-side
+// atomic queue, so a grid sized to the machine drains any batch.  Queries
+// whose in-range beam reaches the expansion threshold (Algorithm 6) become
+// tasks of the greedy phase (Algorithm 2), which a cooperative grid runs
+// level by level over all tasks at once: the closure inside the ball does
+// not depend on visiting order, so every frontier node of every query is an
+// independent work item and heavy queries spread over the whole GPU.
+//
+// Exactness of the beam on a GPU rests on two facts about Algorithm 1 under
+// the total order (d, id):
+//  * the b-th key of B never increases once |B| = b, so a point that was
+//    evaluated and trimmed is trimmed again if it is re-inserted;
+//  * therefore filtering neighbours by "ever evaluated" instead of by V gives
+//    the same B, and a cache of evaluated ids that may FORGET entries (never
+//    invent them) is exact as long as insertion into B removes duplicates.
+// The LDS seen-cache below is such a cache.
+//
+// Memory traffic: a neighbour row is read by a group of G lanes, each loading
+// CPL 16-byte chunks, so one load instruction covers 64/G whole rows with
+// fully used 64/128-byte segments.  Distances: uint8/int8 via the 4-way dot
+// instructions (|p|^2 - 2 p.q + |q|^2, exact in int32); float32 with FP64
+// accumulation of the differences.
+
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "rr_internal.h"
+
+namespace cg = cooperative_groups;
+
+namespace rr {
+
+// --------------------------------------------------------------------------
+// small device helpers
+// --------------------------------------------------------------------------
+
+#define RR_IDMASK 0x7fffffffu
+#define RR_VIS 0x80000000u
+#define RR_EMPTY32 0xffffffffu
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int mbcnt(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+template <typename D>
+__device__ __forceinline__ bool key_less(D da, uint32_t ia, D db, uint32_t ib) {
+    return da < db || (da == db && ia < ib);
+}
+
+template <typename D> __device__ __forceinline__ D dmax();
+template <> __device__ __forceinline__ uint32_t dmax<uint32_t>() { return 0xffffffffu; }
+template <> __device__ __forceinline__ double dmax<double>() { return __builtin_huge_val(); }
+template <> __device__ __forceinline__ float dmax<float>() { return __builtin_huge_valf(); }
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u; }
+
+// LDS seen-cache: open addressing, `probes` linear probes.  Returns true if
+// `id` was already present.  When every probe slot is taken by other ids the
+// id is not recorded (the cache forgets it) and `overflow` is set.
+__device__ __forceinline__ bool seen_insert(uint32_t *tab, uint32_t cs_mask, uint32_t id,
+                                            bool &overflow) {
+    uint32_t h = hash32(id);
+#pragma unroll 1
+    for (int p = 0; p < 8; ++p) {
+        uint32_t slot = (h + (uint32_t)p) & cs_mask;
+        uint32_t old = atomicCAS(&tab[slot], RR_EMPTY32, id);
+        if (old == RR_EMPTY32) return false;
+        if (old == id) return true;
+    }
+    overflow = true;
+    return false;
+}
+
+// Global exact set of (task, id) keys: returns true if the key was inserted
+// now, false if it was present.  `full` is set if the probe budget ran out.
+__device__ __forceinline__ bool gset_insert(unsigned long long *tab, int64_t cap_mask,
+                                            unsigned long long key, bool &full) {
+    uint64_t h = (uint64_t)hash32((uint32_t)key ^ hash32((uint32_t)(key >> 32))) * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+#pragma unroll 1
+    for (int p = 0; p < 128; ++p) {
+        int64_t slot = (int64_t)((h + (uint64_t)p) & (uint64_t)cap_mask);
+        unsigned long long old = atomicCAS(&tab[slot], ~0ull, key);
+        if (old == ~0ull) return true;
+        if (old == key) return false;
+    }
+    full = true;
+    return false;
+}
+
+template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// bitonic sort of one (d, id) pair per lane, ascending over lanes 0..63
+template <typename D> __device__ __forceinline__ void wave_sort(D &d, uint32_t &id) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            D od = __shfl_xor(d, j);
+            uint32_t oi = __shfl_xor(id, j);
+            bool up = (lane & k) == 0;
+            bool lower = (lane & j) == 0;
+            bool take = (lower == up) ? key_less(od, oi, d, id) : key_less(d, id, od, oi);
+            if (take) {
+                d = od;
+                id = oi;
+            }
+        }
+    }
+}
+
+// number of entries of the sorted arrays (ad, ai)[0, n) that are < (d, id);
+// ids compared without the visited bit
+template <typename D>
+__device__ __forceinline__ int lower_bound_key(const D *ad, const uint32_t *ai, int n, D d,
+                                               uint32_t id) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (key_less(ad[mid], ai[mid] & RR_IDMASK, d, id))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// --------------------------------------------------------------------------
+// distance of a row chunk against the query chunk held in registers
+// --------------------------------------------------------------------------
+
+template <int DTYPE> struct DistOf;
+template <> struct DistOf<RR_U8> { using T = uint32_t; using Acc = int; };
+template <> struct DistOf<RR_I8> { using T = uint32_t; using Acc = int; };
+template <> struct DistOf<RR_F32> { using T = double; using Acc = double; };
+
+template <int DTYPE>
+__device__ __forceinline__ typename DistOf<DTYPE>::Acc chunk_part(uint4 p, uint4 q);
+
+// uint8: |p|^2 - 2 p.q over 16 bytes (|q|^2 is added once per row)
+template <> __device__ __forceinline__ int chunk_part<RR_U8>(uint4 p, uint4 q) {
+    unsigned pp = __builtin_amdgcn_udot4(p.x, p.x, 0u, false);
+    pp = __builtin_amdgcn_udot4(p.y, p.y, pp, false);
+    pp = __builtin_amdgcn_udot4(p.z, p.z, pp, false);
+    pp = __builtin_amdgcn_udot4(p.w, p.w, pp, false);
+    unsigned pq = __builtin_amdgcn_udot4(p.x, q.x, 0u, false);
+    pq = __builtin_amdgcn_udot4(p.y, q.y, pq, false);
+    pq = __builtin_amdgcn_udot4(p.z, q.z, pq, false);
+    pq = __builtin_amdgcn_udot4(p.w, q.w, pq, false);
+    return (int)pp - 2 * (int)pq;
+}
+
+template <> __device__ __forceinline__ int chunk_part<RR_I8>(uint4 p, uint4 q) {
+    int pp = __builtin_amdgcn_sdot4((int)p.x, (int)p.x, 0, false);
+    pp = __builtin_amdgcn_sdot4((int)p.y, (int)p.y, pp, false);
+    pp = __builtin_amdgcn_sdot4((int)p.z, (int)p.z, pp, false);
+    pp = __builtin_amdgcn_sdot4((int)p.w, (int)p.w, pp, false);
+    int pq = __builtin_amdgcn_sdot4((int)p.x, (int)q.x, 0, false);
+    pq = __builtin_amdgcn_sdot4((int)p.y, (int)q.y, pq, false);
+    pq = __builtin_amdgcn_sdot4((int)p.z, (int)q.z, pq, false);
+    pq = __builtin_amdgcn_sdot4((int)p.w, (int)q.w, pq, false);
+    return pp - 2 * pq;
+}
+
+template <> __device__ __forceinline__ double chunk_part<RR_F32>(uint4 p, uint4 q) {
+    double t0 = (double)__uint_as_float(p.x) - (double)__uint_as_float(q.x);
+    double t1 = (double)__uint_as_float(p.y) - (double)__uint_as_float(q.y);
+    double t2 = (double)__uint_as_float(p.z) - (double)__uint_as_float(q.z);
+    double t3 = (double)__uint_as_float(p.w) - (double)__uint_as_float(q.w);
+    double a = t0 * t0;
+    a = fma(t1, t1, a);
+    a = fma(t2, t2, a);
+    a = fma(t3, t3, a);
+    return a;
+}
+
+// |q|^2 part for integer data (float data needs none)
+template <int DTYPE> __device__ __forceinline__ int chunk_qq(uint4 q);
+template <> __device__ __forceinline__ int chunk_qq<RR_U8>(uint4 q) {
+    unsigned s = __builtin_amdgcn_udot4(q.x, q.x, 0u, false);
+    s = __builtin_amdgcn_udot4(q.y, q.y, s, false);
+    s = __builtin_amdgcn_udot4(q.z, q.z, s, false);
+    s = __builtin_amdgcn_udot4(q.w, q.w, s, false);
+    return (int)s;
+}
+template <> __device__ __forceinline__ int chunk_qq<RR_I8>(uint4 q) {
+    int s = __builtin_amdgcn_sdot4((int)q.x, (int)q.x, 0, false);
+    s = __builtin_amdgcn_sdot4((int)q.y, (int)q.y, s, false);
+    s = __builtin_amdgcn_sdot4((int)q.z, (int)q.z, s, false);
+    s = __builtin_amdgcn_sdot4((int)q.w, (int)q.w, s, false);
+    return s;
+}
+
+// Query state held by each lane: its CPL chunks of the padded query row.
+template <int DTYPE, int CPL, int G> struct QueryRegs {
+    uint4 c[CPL];
+    int qq; // integer data: |q|^2
+
+    __device__ __forceinline__ void load(const uint8_t *qrow) {
+        const int gl = lane_id() & (G - 1);
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            c[k] = *reinterpret_cast<const uint4 *>(qrow + (size_t)(gl * CPL + k) * 16);
+            if constexpr (DTYPE != RR_F32) s += chunk_qq<DTYPE>(c[k]);
+        }
+        if constexpr (DTYPE != RR_F32) qq = group_sum<G>(s);
+        else qq = 0;
+    }
+};
+
+// Evaluate the distances of candidates ci[0, k) (ids in LDS) and write them
+// to cd[0, k).  Row c is handled by lane group c % (64/G) in round c / (64/G).
+// All lanes of the wave must call this.
+template <int DTYPE, int CPL, int G>
+__device__ __forceinline__ void eval_rows(const DevIndex &ix, const QueryRegs<DTYPE, CPL, G> &qr,
+                                          const uint32_t *ci, typename DistOf<DTYPE>::T *cd,
+                                          int k) {
+    using D = typename DistOf<DTYPE>::T;
+    using Acc = typename DistOf<DTYPE>::Acc;
+    constexpr int RPR = 64 / G;          // rows per round
+    constexpr int RB = CPL >= 8 ? 1 : 8 / CPL; // rounds issued together
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int grp = lane / G;
+    const int nrounds = (k + RPR - 1) / RPR;
+    for (int r0 = 0; r0 < nrounds; r0 += RB) {
+        uint4 buf[RB][CPL];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int c = (r0 + rb) * RPR + grp;
+            if (c < k) {
+                const uint8_t *row = ix.base + (size_t)ci[c] * (size_t)ix.row_bytes +
+                                     (size_t)gl * CPL * 16;
+#pragma unroll
+                for (int kk = 0; kk < CPL; ++kk)
+                    buf[rb][kk] = *reinterpret_cast<const uint4 *>(row + kk * 16);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < CPL; ++kk) buf[rb][kk] = qr.c[kk];
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            Acc a = 0;
+#pragma unroll
+            for (int kk = 0; kk < CPL; ++kk) a += chunk_part<DTYPE>(buf[rb][kk], qr.c[kk]);
+            a = group_sum<G>(a);
+            const int c = (r0 + rb) * RPR + grp;
+            if (gl == 0 && c < k) {
+                if constexpr (DTYPE == RR_F32) cd[c] = a;
+                else cd[c] = (uint32_t)(a + qr.qq);
+            }
+        }
+    }
+    wave_sync();
+}
+
+// in-range test and early-stop tests on the exact distance
+template <typename D> __device__ __forceinline__ bool in_range(D d, const QThresh &t);
+template <> __device__ __forceinline__ bool in_range<uint32_t>(uint32_t d, const QThresh &t) {
+    return (int64_t)d <= t.r_int;
+}
+template <> __device__ __forceinline__ bool in_range<double>(double d, const QThresh &t) {
+    return d <= t.r;
+}
+template <typename D> __device__ __forceinline__ bool beyond_esr(D d, const QThresh &t);
+template <> __device__ __forceinline__ bool beyond_esr<uint32_t>(uint32_t d, const QThresh &t) {
+    return (int64_t)d > t.esr_int;
+}
+template <> __device__ __forceinline__ bool beyond_esr<double>(double d, const QThresh &t) {
+    return d > t.esr;
+}
+
+// --------------------------------------------------------------------------
+// query preparation: pad rows, derive per-query thresholds
+// --------------------------------------------------------------------------
+
+__device__ int64_t floor_clamp(double r) {
+    if (!(r >= 0.0)) return -1; // negative or NaN: nothing is within
+    if (r >= 4.0e18) return (int64_t)4000000000000000000ll;
+    return (int64_t)floor(r);
+}
+
+__global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int32_t row_out,
+                               double radius, const double *radius_dev, double esr,
+                               QThresh *qth, uint8_t *qpad) {
+    const int64_t chunks = row_out / 16;
+    const int64_t tot = nq * chunks;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t qi = t / chunks;
+        const int64_t c = t % chunks;
+        uint8_t b[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t o = c * 16 + i;
+            b[i] = o < row_in ? q[qi * row_in + o] : 0;
+        }
+        uint4 v;
+        v.x = b[0] | (b[1] << 8) | (b[2] << 16) | ((uint32_t)b[3] << 24);
+        v.y = b[4] | (b[5] << 8) | (b[6] << 16) | ((uint32_t)b[7] << 24);
+        v.z = b[8] | (b[9] << 8) | (b[10] << 16) | ((uint32_t)b[11] << 24);
+        v.w = b[12] | (b[13] << 8) | (b[14] << 16) | ((uint32_t)b[15] << 24);
+        *reinterpret_cast<uint4 *>(qpad + qi * row_out + c * 16) = v;
+        if (c == 0) {
+            QThresh th;
+            const double r = radius_dev ? radius_dev[qi] : radius;
+            th.r = r;
+            th.esr = esr;
+            th.r_int = floor_clamp(r);
+            th.esr_int = floor_clamp(esr);
+            th.r_f = (float)r;
+            th.esr_f = (float)esr;
+            th.lo = -1.f;
+            th.hi = -1.f;
+            qth[qi] = th;
+        }
+    }
+}
+
+hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t nq, double radius,
+                               const double *radius_dev, const SearchCfg &cfg, SearchBufs &sb,
+                               hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
+    const int64_t tot = nq * (ix.row_bytes / 16);
+    int blocks = (int)((tot + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    (void)cfg;
+    hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s,
+                       (const uint8_t *)queries, nq, ix.d * esz, ix.row_bytes, radius, radius_dev,
+                       0.0, sb.qth, sb.qpad);
+    return hipGetLastError();
+}
+
+// esr is a search parameter: written separately so prep stays param-free
+__global__ void k_set_esr(QThresh *qth, int64_t nq, double esr) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        qth[i].esr = esr;
+        qth[i].esr_int = floor_clamp(esr);
+        qth[i].esr_f = (float)esr;
+    }
+}
+
+// --------------------------------------------------------------------------
+// beam kernel: Algorithm 1 (+ Algorithm 5), then Algorithm 6's decision
+// --------------------------------------------------------------------------
+
+struct BeamArgs {
+    DevIndex ix;
+    int64_t nq;
+    SearchCfg cfg;
+    SearchBufs sb;
+    int32_t lds_per_wave;
+    int32_t bcap;     // beam capacity in LDS
+};
+
+template <typename D>
+__host__ __device__ inline int32_t beam_lds_bytes(int32_t bcap, int32_t cs) {
+    auto al = [](int64_t x) { return (int32_t)((x + 15) & ~15ll); };
+    return al((int64_t)bcap * sizeof(D)) * 2 + al(64 * sizeof(D)) + al((int64_t)bcap * 4) * 2 +
+           al(64 * 4) + al((int64_t)cs * 4);
+}
+
+template <int DTYPE, int CPL, int G>
+__global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
+    using D = typename DistOf<DTYPE>::T;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    uint8_t *my = smem + (size_t)wid * a.lds_per_wave;
+    auto al = [](int64_t x) { return (int64_t)((x + 15) & ~15ll); };
+    const int bcap = a.bcap;
+    const int cs = a.cfg.cache_slots;
+    D *bdA = (D *)my;
+    D *bdB = (D *)(my + al((int64_t)bcap * sizeof(D)));
+    D *cd = (D *)(my + 2 * al((int64_t)bcap * sizeof(D)));
+    uint8_t *p2 = my + 2 * al((int64_t)bcap * sizeof(D)) + al(64 * sizeof(D));
+    uint32_t *biA = (uint32_t *)p2;
+    uint32_t *biB = (uint32_t *)(p2 + al((int64_t)bcap * 4));
+    uint32_t *ci = (uint32_t *)(p2 + 2 * al((int64_t)bcap * 4));
+    uint32_t *htab = (uint32_t *)(p2 + 2 * al((int64_t)bcap * 4) + al(64 * 4));
+    const uint32_t cs_mask = (uint32_t)cs - 1u;
+    const DevIndex &ix = a.ix;
+    const SearchCfg &cfg = a.cfg;
+    const int R = ix.R;
+    const int b = cfg.beam;
+
+    for (;;) {
+        int64_t q = 0;
+        if (lane == 0) q = (int64_t)atomicAdd(&a.sb.counters[CTR_QUEUE], 1ull);
+        q = __shfl(q, 0);
+        if (q >= a.nq) break;
+
+        const QThresh th = a.sb.qth[q];
+        QueryRegs<DTYPE, CPL, G> qr;
+        qr.load(a.sb.qpad + (size_t)q * ix.row_bytes);
+
+        for (int i = lane; i < cs; i += 64) htab[i] = RR_EMPTY32;
+        wave_sync();
+
+        bool ovf = false;
+        // B <- S = {entry}
+        if (lane == 0) {
+            ci[0] = (uint32_t)ix.entry;
+            seen_insert(htab, cs_mask, (uint32_t)ix.entry, ovf);
+        }
+        wave_sync();
+        eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, 1);
+        D *bd = bdA, *bdo = bdB;
+        uint32_t *bi = biA, *bio = biB;
+        if (lane == 0) {
+            bd[0] = cd[0];
+            bi[0] = (uint32_t)ix.entry;
+        }
+        wave_sync();
+        int nB = 1;
+        int visits = 0, evals = 1;
+        int cursor = 0;
+        bool es_fired = false;
+
+        for (;;) {
+            // p* = first unvisited entry of the sorted beam at or after cursor
+            int ip = -1;
+            for (int base = cursor & ~63; base < nB; base += 64) {
+                const int i = base + lane;
+                const bool unv = i >= cursor && i < nB && !(bi[i] & RR_VIS);
+                const unsigned long long m = __ballot(unv);
+                if (m) {
+                    ip = base + __ffsll((long long)m) - 1;
+                    break;
+                }
+            }
+            if (ip < 0) break;
+            const D dp = bd[ip];
+            // Algorithm 5: min_B d > r, v >= vl, d(p*) > esr
+            if (cfg.es_enable && visits >= cfg.vl && !in_range<D>(bd[0], th) &&
+                beyond_esr<D>(dp, th)) {
+                es_fired = true;
+                break;
+            }
+            const uint32_t p = bi[ip] & RR_IDMASK;
+            wave_sync();
+            if (lane == 0) bi[ip] = p | RR_VIS;
+            ++visits;
+            // N_out(p*), drop ids already evaluated
+            int32_t f = -1;
+            if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
+            bool cand = false;
+            if (f >= 0) cand = !seen_insert(htab, cs_mask, (uint32_t)f, ovf);
+            const unsigned long long cm = __ballot(cand);
+            const int k = __popcll(cm);
+            if (cand) ci[mbcnt(cm)] = (uint32_t)f;
+            wave_sync();
+            evals += k;
+            if (k == 0) {
+                cursor = ip + 1;
+                continue;
+            }
+            eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
+            D myd = dmax<D>();
+            uint32_t myi = RR_EMPTY32;
+            if (lane < k) {
+                myd = cd[lane];
+                myi = ci[lane];
+            }
+            wave_sort(myd, myi);
+            // de-duplicate against B (a forgotten id may be re-evaluated)
+            int lb = 0;
+            bool keep = false;
+            if (lane < k) {
+                lb = lower_bound_key(bd, bi, nB, myd, myi);
+                keep = !(lb < nB && bd[lb] == myd && (bi[lb] & RR_IDMASK) == myi);
+            }
+            const unsigned long long km = __ballot(keep);
+            const int k2 = __popcll(km);
+            const int r2 = mbcnt(km);
+            wave_sync();
+            if (keep) {
+                cd[r2] = myd;
+                ci[r2] = myi;
+            }
+            wave_sync();
+            // merge: B entry i moves to i + #(survivors < B[i]); survivor j to j + lb_j
+            const int nB2 = min(b, nB + k2);
+            int ipnew = ip;
+            for (int i = lane; i < nB; i += 64) {
+                const D di = bd[i];
+                const uint32_t ii = bi[i];
+                const int np = i + lower_bound_key(cd, ci, k2, di, ii & RR_IDMASK);
+                if (np < b) {
+                    bdo[np] = di;
+                    bio[np] = ii;
+                }
+                if (i == ip) ipnew = np;
+            }
+            ipnew = __shfl(ipnew, ip & 63);
+            int firstnew = 1 << 30;
+            if (keep) {
+                const int np = r2 + lb;
+                if (np < b) {
+                    bdo[np] = myd;
+                    bio[np] = myi;
+                }
+                if (r2 == 0) firstnew = np;
+            }
+            if (k2 > 0) firstnew = __shfl(firstnew, __ffsll((long long)km) - 1);
+            wave_sync();
+            D *td = bd;
+            bd = bdo;
+            bdo = td;
+            uint32_t *ti = bi;
+            bi = bio;
+            bio = ti;
+            nB = nB2;
+            cursor = min(ipnew + 1, firstnew);
+        }
+
+        // N = in-range prefix of the sorted beam
+        int cN = 0;
+        for (int base = 0; base < nB; base += 64) {
+            const int i = base + lane;
+            const bool inr = i < nB && in_range<D>(bd[i], th);
+            const int c = __popcll(__ballot(inr));
+            cN += c;
+            if (c < 64) break;
+        }
+        // Algorithm 6: expand iff |N| >= lambda b; an empty N expands to nothing
+        const bool expand_flag = cfg.mode == RR_ADAPTIVE && cN >= cfg.expand_thresh;
+        const bool expand = expand_flag && cN > 0;
+        rr_query_stats st;
+        st.visits = visits;
+        st.evals = evals;
+        st.greedy_visits = 0;
+        st.greedy_evals = 0;
+        st.count = expand ? 0 : cN;
+        st.final_beam = b;
+        st.es_fired = es_fired ? 1 : 0;
+        st.expanded = expand_flag ? 1 : 0;
+        st.truncated = 0;
+        st.cache_overflow = __ballot(ovf) ? 1 : 0;
+        st.rechecked = 0;
+        st.rounds = 1;
+        if (!expand) {
+            int64_t off = 0;
+            if (lane == 0 && cN > 0) off = (int64_t)atomicAdd(&a.sb.counters[CTR_ARENA], (unsigned long long)cN);
+            off = __shfl(off, 0);
+            if (cN > 0 && off + cN > a.sb.arena_cap) {
+                st.truncated = 1;
+                st.count = 0;
+                if (lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 1ull);
+            } else {
+                D *ad = (D *)a.sb.arena_dists;
+                for (int i = lane; i < cN; i += 64) {
+                    a.sb.arena_ids[off + i] = (int32_t)(bi[i] & RR_IDMASK);
+                    ad[off + i] = bd[i];
+                }
+            }
+            if (lane == 0) {
+                a.sb.res_off[q] = off;
+                a.sb.res_cnt[q] = st.count;
+            }
+        } else {
+            // become a task of the greedy phase: seeds N go to level 0
+            int64_t t = 0, off = 0;
+            if (lane == 0) {
+                t = (int64_t)atomicAdd(&a.sb.counters[CTR_TASKS], 1ull);
+                off = (int64_t)atomicAdd(&a.sb.level_cnt[0], (unsigned long long)cN);
+            }
+            t = __shfl(t, 0);
+            off = __shfl(off, 0);
+            bool full = false;
+            if (off + cN > a.sb.item_cap) {
+                full = true;
+            } else {
+                D *idist = (D *)a.sb.item_dist;
+                const int64_t hmask = a.sb.hash_cap - 1;
+                for (int i = lane; i < cN; i += 64) {
+                    const uint32_t id = bi[i] & RR_IDMASK;
+                    a.sb.item_task[off + i] = (int32_t)t;
+                    a.sb.item_id[off + i] = (int32_t)id;
+                    idist[off + i] = bd[i];
+                    gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
+                }
+            }
+            if (__ballot(full)) {
+                st.truncated = 1;
+                if (lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 2ull);
+            }
+            if (lane == 0) {
+                a.sb.task_q[t] = (int32_t)q;
+                a.sb.task_cnt[t] = (unsigned long long)cN;
+                a.sb.task_evals[t] = 0ull;
+                a.sb.res_off[q] = 0;
+                a.sb.res_cnt[q] = 0;
+            }
+        }
+        if (lane == 0) a.sb.stats[q] = st;
+        wave_sync();
+    }
+}
+
+// --------------------------------------------------------------------------
+// greedy phase: Algorithm 2 for all tasks at once, level-synchronous
+// --------------------------------------------------------------------------
+
+struct GreedyArgs {
+    DevIndex ix;
+    SearchCfg cfg;
+    SearchBufs sb;
+};
+
+template <int DTYPE, int CPL, int G>
+__global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
+    using D = typename DistOf<DTYPE>::T;
+    __shared__ uint32_t s_ci[4][64];
+    __shared__ D s_cd[4][64];
+    cg::grid_group grid = cg::this_grid();
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    const int64_t tw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const DevIndex &ix = a.ix;
+    const int R = ix.R;
+    uint32_t *ci = s_ci[wid];
+    D *cd = s_cd[wid];
+    D *idist = (D *)a.sb.item_dist;
+    const int64_t hmask = a.sb.hash_cap - 1;
+    const int64_t ntasks = (int64_t)a.sb.counters[CTR_TASKS];
+    int64_t base = 0;
+    int lvl = 0;
+    for (; lvl < a.sb.max_levels - 1; ++lvl) {
+        const int64_t cnt = (int64_t)__hip_atomic_load(&a.sb.level_cnt[lvl], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        if (cnt == 0) break;
+        const int64_t next_base = base + cnt;
+        for (int64_t it = gw; it < cnt; it += tw) {
+            const int64_t item = base + it;
+            if (item >= a.sb.item_cap) break;
+            const int32_t t = a.sb.item_task[item];
+            const int32_t p = a.sb.item_id[item];
+            if (t < 0 || t >= ntasks || p < 0 || (int64_t)p >= ix.n) continue; // never written
+            const int32_t q = a.sb.task_q[t];
+            const QThresh th = a.sb.qth[q];
+            QueryRegs<DTYPE, CPL, G> qr;
+            qr.load(a.sb.qpad + (size_t)q * ix.row_bytes);
+            int32_t f = -1;
+            if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
+            bool full = false;
+            bool cand = false;
+            if (f >= 0) cand = gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | (uint32_t)f, full);
+            const unsigned long long cm = __ballot(cand);
+            const int k = __popcll(cm);
+            if (cand) ci[mbcnt(cm)] = (uint32_t)f;
+            wave_sync();
+            if (k > 0) {
+                eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
+                bool inr = false;
+                D myd = dmax<D>();
+                uint32_t myi = 0;
+                if (lane < k) {
+                    myd = cd[lane];
+                    myi = ci[lane];
+                    inr = in_range<D>(myd, th);
+                }
+                const unsigned long long im = __ballot(inr);
+                const int m = __popcll(im);
+                int64_t off = 0;
+                if (lane == 0 && m > 0)
+                    off = (int64_t)atomicAdd(&a.sb.level_cnt[lvl + 1], (unsigned long long)m);
+                off = __shfl(off, 0) + next_base;
+                // every reserved slot below item_cap is written, so the next
+                // level never reads an unwritten item
+                const int64_t o = off + mbcnt(im);
+                const bool wrote = inr && o < a.sb.item_cap;
+                if (wrote) {
+                    a.sb.item_task[o] = t;
+                    a.sb.item_id[o] = (int32_t)myi;
+                    idist[o] = myd;
+                }
+                const int mw = __popcll(__ballot(wrote));
+                if (lane == 0) {
+                    atomicAdd(&a.sb.task_evals[t], (unsigned long long)k);
+                    if (mw > 0) atomicAdd(&a.sb.task_cnt[t], (unsigned long long)mw);
+                    if (mw < m) atomicOr(&a.sb.counters[CTR_OVERFLOW], 4ull);
+                }
+            }
+            if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
+            wave_sync();
+        }
+        __threadfence();
+        grid.sync();
+        base = next_base;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sb.counters[CTR_LEVELS] = (unsigned long long)lvl;
+        if (lvl == a.sb.max_levels - 1 &&
+            __hip_atomic_load(&a.sb.level_cnt[lvl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            atomicOr(&a.sb.counters[CTR_OVERFLOW], 16ull);
+    }
+}
+
+// ---- finalisation of the greedy phase: group items per task, sort, emit ----
+
+// exclusive scan of task_cnt[0, ntasks) into seg_off (one workgroup)
+__global__ void k_task_scan(SearchBufs sb) {
+    __shared__ unsigned long long part[1024];
+    const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
+    const int tid = threadIdx.x;
+    const int64_t per = (nt + blockDim.x - 1) / blockDim.x;
+    const int64_t lo = tid * per, hi = min(nt, lo + per);
+    unsigned long long s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += sb.task_cnt[i];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long run = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) {
+            unsigned long long v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        sb.seg_off[nt] = (int64_t)run;
+    }
+    __syncthreads();
+    unsigned long long run = part[tid];
+    for (int64_t i = lo; i < hi; ++i) {
+        sb.seg_off[i] = (int64_t)run;
+        run += sb.task_cnt[i];
+        sb.seg_cur[i] = 0ull;
+    }
+}
+
+template <typename D> __global__ void k_scatter(SearchBufs sb) {
+    const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
+    if (nt == 0) return;
+    const int64_t total = sb.seg_off[nt];
+    const D *idist = (const D *)sb.item_dist;
+    D *sd = (D *)sb.seg_dists;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total && i < sb.item_cap;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = sb.item_task[i];
+        const int64_t pos = sb.seg_off[t] + (int64_t)atomicAdd(&sb.seg_cur[t], 1ull);
+        sb.seg_ids[pos] = sb.item_id[i];
+        sd[pos] = idist[i];
+    }
+}
+
+// Sort one segment by (d, id) with the whole workgroup.  Segments that fit
+// in LDS use a bitonic network; longer ones are sorted in runs of that size
+// and merged pairwise through `tmp` (same length) by rank computation.
+constexpr int SORT_LDS = 2048;
+
+template <typename D>
+__device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int64_t n, D *sd,
+                                   uint32_t *si) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    // 1) sort runs of SORT_LDS in LDS
+    for (int64_t r0 = 0; r0 < n; r0 += SORT_LDS) {
+        const int m = (int)min((int64_t)SORT_LDS, n - r0);
+        int p2 = 1;
+        while (p2 < m) p2 <<= 1;
+        for (int i = t; i < p2; i += nt) {
+            if (i < m) {
+                sd[i] = d[r0 + i];
+                si[i] = (uint32_t)id[r0 + i];
+            } else {
+                sd[i] = dmax<D>();
+                si[i] = RR_EMPTY32;
+            }
+        }
+        __syncthreads();
+        for (int k = 2; k <= p2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = t; i < p2; i += nt) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const bool up = (i & k) == 0;
+                        const bool sw = up ? key_less(sd[ixj], si[ixj], sd[i], si[i])
+                                           : key_less(sd[i], si[i], sd[ixj], si[ixj]);
+                        if (sw) {
+                            D a = sd[i];
+                            sd[i] = sd[ixj];
+                            sd[ixj] = a;
+                            uint32_t b = si[i];
+                            si[i] = si[ixj];
+                            si[ixj] = b;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = t; i < m; i += nt) {
+            d[r0 + i] = sd[i];
+            id[r0 + i] = (int32_t)si[i];
+        }
+        __syncthreads();
+    }
+    // 2) merge runs pairwise until one run remains (ping-pong d <-> td)
+    D *src_d = d, *dst_d = td;
+    int32_t *src_i = id, *dst_i = tid_;
+    bool in_tmp = false;
+    for (int64_t w = SORT_LDS; w < n; w <<= 1) {
+        for (int64_t i = t; i < n; i += nt) {
+            const int64_t run = i / w;
+            const int64_t a0 = (run & ~1ll) * w;           // left run start
+            const int64_t b0 = a0 + w;                      // right run start
+            const int64_t a1 = min(n, b0), b1 = min(n, b0 + w);
+            const D x = src_d[i];
+            const uint32_t xi = (uint32_t)src_i[i];
+            int64_t pos;
+            if ((run & 1) == 0) {
+                // rank in the right run: elements strictly less
+                int64_t lo = b0, hi = b1;
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (key_less(src_d[mid], (uint32_t)src_i[mid], x, xi)) lo = mid + 1;
+                    else hi = mid;
+                }
+                pos = a0 + (i - a0) + (lo - b0);
+            } else {
+                int64_t lo = a0, hi = a1;
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (key_less(src_d[mid], (uint32_t)src_i[mid], x, xi)) lo = mid + 1;
+                    else hi = mid;
+                }
+                pos = a0 + (i - b0) + (lo - a0);
+            }
+            dst_d[pos] = x;
+            dst_i[pos] = (int32_t)xi;
+        }
+        __threadfence_block();
+        __syncthreads();
+        D *sw = src_d;
+        src_d = dst_d;
+        dst_d = sw;
+        int32_t *swi = src_i;
+        src_i = dst_i;
+        dst_i = swi;
+        in_tmp = !in_tmp;
+    }
+    if (in_tmp) {
+        for (int64_t i = t; i < n; i += nt) {
+            d[i] = td[i];
+            id[i] = tid_[i];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename D> __global__ __launch_bounds__(256) void k_seg_sort_emit(SearchBufs sb) {
+    __shared__ D sd[SORT_LDS];
+    __shared__ uint32_t si[SORT_LDS];
+    __shared__ int64_t s_off;
+    const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
+    D *segd = (D *)sb.seg_dists;
+    D *tmpd = (D *)sb.item_dist;
+    D *ad = (D *)sb.arena_dists;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
+        const int32_t q = sb.task_q[t];
+        block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0, sb.item_id + s0, n, sd, si);
+        if (threadIdx.x == 0) s_off = (int64_t)atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)n);
+        __syncthreads();
+        const int64_t off = s_off;
+        const bool ok = off + n <= sb.arena_cap;
+        if (ok) {
+            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                sb.arena_ids[off + i] = sb.seg_ids[s0 + i];
+                ad[off + i] = segd[s0 + i];
+            }
+        }
+        if (threadIdx.x == 0) {
+            sb.res_off[q] = off;
+            sb.res_cnt[q] = ok ? (int32_t)n : 0;
+            rr_query_stats *st = &sb.stats[q];
+            st->count = ok ? (int32_t)n : 0;
+            st->greedy_visits = (int32_t)n;
+            st->greedy_evals = (int32_t)sb.task_evals[t];
+            if (!ok) {
+                st->truncated = 1;
+                atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// dispatch over (dtype, row split)
+// --------------------------------------------------------------------------
+
+template <int DTYPE, int CPL, int G>
+static hipError_t run_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                           int num_cus, hipStream_t s) {
+    using D = typename DistOf<DTYPE>::T;
+    BeamArgs a;
+    a.ix = ix;
+    a.nq = nq;
+    a.cfg = cfg;
+    a.sb = sb;
+    a.bcap = cfg.beam;
+    a.lds_per_wave = beam_lds_bytes<D>(cfg.beam, cfg.cache_slots);
+    const int waves = cfg.waves;
+    const size_t shmem = (size_t)a.lds_per_wave * waves;
+    auto kern = k_beam<DTYPE, CPL, G>;
+    if (shmem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves * 64, shmem);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int64_t blocks = (int64_t)per_cu * num_cus;
+    const int64_t need = (nq + waves - 1) / waves;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(waves * 64), shmem, s, a);
+    return hipGetLastError();
+}
+
+template <int DTYPE, int CPL, int G>
+static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBufs &sb,
+                             int num_cus, hipStream_t s) {
+    using D = typename DistOf<DTYPE>::T;
+    GreedyArgs a;
+    a.ix = ix;
+    a.cfg = cfg;
+    a.sb = sb;
+    auto kern = k_greedy<DTYPE, CPL, G>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    if (per_cu > 8) per_cu = 8;
+    dim3 grid((unsigned)(per_cu * num_cus)), block(256);
+    void *args[] = {&a};
+    e = hipLaunchCooperativeKernel((const void *)kern, grid, block, args, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb);
+    hipLaunchKernelGGL(k_scatter<D>, dim3(1024), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL(k_seg_sort_emit<D>, dim3(2048), dim3(256), 0, s, sb);
+    return hipGetLastError();
+}
+
+#define RR_SPLITS(X, DT)                                                                      \
+    X(DT, 1, 4) X(DT, 1, 8) X(DT, 1, 16) X(DT, 1, 32) X(DT, 1, 64) X(DT, 2, 64) X(DT, 4, 64)  \
+        X(DT, 3, 4) X(DT, 3, 8) X(DT, 3, 16) X(DT, 3, 32) X(DT, 3, 64) X(DT, 6, 64)
+
+hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                       int num_cus, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    int32_t cpl = 0, g = 0;
+    row_split(ix.row_bytes, &cpl, &g);
+#define X(DT, C, GG)                                                                          \
+    if (ix.dtype == DT && cpl == C && g == GG) return run_beam<DT, C, GG>(ix, nq, cfg, sb, num_cus, s);
+    RR_SPLITS(X, RR_U8)
+    RR_SPLITS(X, RR_I8)
+    RR_SPLITS(X, RR_F32)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                         int num_cus, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    int32_t cpl = 0, g = 0;
+    row_split(ix.row_bytes, &cpl, &g);
+#define X(DT, C, GG)                                                                          \
+    if (ix.dtype == DT && cpl == C && g == GG) return run_greedy<DT, C, GG>(ix, cfg, sb, num_cus, s);
+    RR_SPLITS(X, RR_U8)
+    RR_SPLITS(X, RR_I8)
+    RR_SPLITS(X, RR_F32)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// --------------------------------------------------------------------------
+// CSR output: exclusive scan of per-query counts, then segment copies
+// --------------------------------------------------------------------------
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+size_t results_copy_tmp_bytes(int64_t nq) {
+    const int64_t tiles = (nq + SCAN_TILE - 1) / SCAN_TILE;
+    return (size_t)(tiles + 1) * sizeof(int64_t);
+}
+
+__global__ void k_scan_tiles(const int32_t *cnt, int64_t n, int64_t *out, int64_t *tile_sum) {
+    __shared__ int64_t sh[SCAN_BLOCK];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = t0 + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+        v[k] = i < n ? cnt[i] : 0;
+        s += v[k];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+        int64_t x = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += x;
+        __syncthreads();
+    }
+    int64_t run = sh[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = t0 + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == SCAN_BLOCK - 1) tile_sum[blockIdx.x] = sh[SCAN_BLOCK - 1];
+}
+
+__global__ void k_scan_tile_sums(int64_t *tile_sum, int64_t ntiles, int64_t *out, int64_t n) {
+    if (threadIdx.x != 0) return;
+    int64_t run = 0;
+    for (int64_t i = 0; i < ntiles; ++i) {
+        int64_t v = tile_sum[i];
+        tile_sum[i] = run;
+        run += v;
+    }
+    out[n] = run;
+}
+
+__global__ void k_scan_add(int64_t *out, int64_t n, const int64_t *tile_sum) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] += tile_sum[i / SCAN_TILE];
+}
+
+template <typename DIN, typename DOUT>
+__global__ void k_copy_segments(const int64_t *res_off, const int32_t *res_cnt,
+                                const int64_t *offsets, int64_t nq, const int32_t *aid,
+                                const DIN *ad, int32_t *ids, DOUT *dists) {
+    const int lane = lane_id();
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t tw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = w; q < nq; q += tw) {
+        const int64_t src = res_off[q], dst = offsets[q];
+        const int32_t c = res_cnt[q];
+        for (int i = lane; i < c; i += 64) {
+            ids[dst + i] = aid[src + i];
+            dists[dst + i] = (DOUT)ad[src + i];
+        }
+    }
+}
+
+hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
+                              hipStream_t s) {
+    const int64_t tiles = (nq + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *ts = (int64_t *)tmp;
+    if (nq == 0) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)offsets, 1, 0ull);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, nq,
+                       offsets, ts);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(64), 0, s, ts, tiles, offsets, nq);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)std::min<int64_t>(tiles * SCAN_ITEMS, 4096)),
+                       dim3(SCAN_BLOCK), 0, s, offsets, nq, ts);
+    return hipGetLastError();
+}
+
+hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, const uint8_t *qpad,
+                               int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
+                               const int32_t *arena_ids, const void *arena_dists, int32_t *ids,
+                               void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s) {
+    (void)precision;
+    (void)ix;
+    (void)qpad;
+    hipError_t e = launch_scan_counts(res_cnt, nq, offsets, scan_tmp, s);
+    if (e != hipSuccess || nq == 0) return e;
+    const int blocks = (int)std::min<int64_t>((nq + 3) / 4, 4096);
+    if (dtype == RR_F32)
+        hipLaunchKernelGGL((k_copy_segments<double, float>), dim3(blocks), dim3(256), 0, s,
+                           res_off, res_cnt, offsets, nq, arena_ids, (const double *)arena_dists,
+                           ids, (float *)dists);
+    else
+        hipLaunchKernelGGL((k_copy_segments<uint32_t, int32_t>), dim3(blocks), dim3(256), 0, s,
+                           res_off, res_cnt, offsets, nq, arena_ids,
+                           (const uint32_t *)arena_dists, ids, (int32_t *)dists);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_esr, dim3((unsigned)std::min<int64_t>((nq + 255) / 256, 4096)), dim3(256),
+                       0, s, qth, nq, esr);
+    return hipGetLastError();
+}
+
+} // namespace rr

@@ -1,0 +1,402 @@
+"""Python binding of the C ABI in include/rr.h (argument marshalling only).
+
+Every step of the search runs in the HIP library ``librr.so``; PyTorch only
+provides device memory (through the library's allocator callbacks) and the
+stream.  Importing this module on a machine without the built library raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librr.so")
+
+RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_EIO, RR_ESTATE = range(6)
+U8, I8, F32 = 0, 1, 2
+PLAIN, ES, ADAPTIVE, DOUBLING = 0, 1, 2, 3
+EXACT, BF16_RECHECK = 0, 1
+
+_MODES = {"plain": PLAIN, "es": ES, "adaptive": ADAPTIVE, "doubling": DOUBLING}
+
+
+class RRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"[rr status {status}] {msg}")
+        self.status = status
+
+
+class BuildParams(C.Structure):
+    _fields_ = [("R", C.c_int32), ("L", C.c_int32), ("alpha", C.c_double), ("passes", C.c_int32),
+                ("threads", C.c_int32), ("seed", C.c_uint64), ("order", C.POINTER(C.c_int64))]
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("beam", C.c_int32), ("es_enable", C.c_int32),
+                ("es_visit_limit", C.c_int32), ("es_radius", C.c_double), ("lam", C.c_double),
+                ("precision", C.c_int32), ("recheck_margin", C.c_double),
+                ("max_results_per_query", C.c_int64), ("max_beam", C.c_int64),
+                ("result_capacity", C.c_int64), ("cache_slots", C.c_int32),
+                ("waves_per_group", C.c_int32)]
+
+
+class QueryStats(C.Structure):
+    _fields_ = [("visits", C.c_int32), ("evals", C.c_int32), ("greedy_visits", C.c_int32),
+                ("greedy_evals", C.c_int32), ("count", C.c_int32), ("final_beam", C.c_int32),
+                ("es_fired", C.c_int16), ("expanded", C.c_int16), ("truncated", C.c_int16),
+                ("cache_overflow", C.c_int16), ("rechecked", C.c_int32), ("rounds", C.c_int32)]
+
+
+STATS_DTYPE = np.dtype([("visits", np.int32), ("evals", np.int32), ("greedy_visits", np.int32),
+                        ("greedy_evals", np.int32), ("count", np.int32),
+                        ("final_beam", np.int32), ("es_fired", np.int16),
+                        ("expanded", np.int16), ("truncated", np.int16),
+                        ("cache_overflow", np.int16), ("rechecked", np.int32),
+                        ("rounds", np.int32)])
+assert STATS_DTYPE.itemsize == C.sizeof(QueryStats)
+
+
+class BatchStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in
+                ("nq", "total_results", "visits", "evals", "greedy_visits", "greedy_evals",
+                 "rechecked", "es_fired", "expanded", "truncated", "cache_overflow",
+                 "bytes_algorithmic")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+# exported symbols and their signatures: (restype, argtypes)
+_VP, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
+SIGNATURES = {
+    "rr_last_error": (C.c_char_p, []),
+    "rr_version": (C.c_char_p, []),
+    "rr_default_build_params": (None, [C.POINTER(BuildParams)]),
+    "rr_default_search_params": (None, [C.POINTER(SearchParams)]),
+    "rr_index_build": (C.c_int, [_VP, C.c_int, _I64, _I32, C.POINTER(BuildParams),
+                                 C.POINTER(_VP)]),
+    "rr_index_from_graph": (C.c_int, [_VP, C.c_int, _I64, _I32, C.POINTER(C.c_int32), _I32,
+                                      _I32, C.POINTER(_VP)]),
+    "rr_index_graph": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
+    "rr_index_info": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32)]),
+    "rr_index_save": (C.c_int, [_VP, C.c_char_p]),
+    "rr_index_load": (C.c_int, [C.c_char_p, C.POINTER(_VP)]),
+    "rr_index_to_device": (C.c_int, [_VP, C.POINTER(Allocator), _VP]),
+    "rr_index_free": (None, [_VP]),
+    "rr_range_search": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, C.POINTER(SearchParams),
+                                  C.POINTER(Allocator), _VP, C.POINTER(_VP)]),
+    "rr_brute_force": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, C.POINTER(Allocator), _VP,
+                                 C.POINTER(_VP)]),
+    "rr_nn_dist": (C.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    "rr_results_total": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "rr_results_copy": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "rr_results_stats": (C.c_int, [_VP, C.POINTER(QueryStats), C.POINTER(BatchStats)]),
+    "rr_results_free": (None, [_VP]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librr.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2502_13245_amd.build_lib`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(st):
+    if st != RR_OK:
+        raise RRError(st, lib().rr_last_error().decode())
+
+
+def _dtype_code(dt) -> int:
+    dt = np.dtype(dt)
+    if dt == np.uint8:
+        return U8
+    if dt == np.int8:
+        return I8
+    if dt == np.float32:
+        return F32
+    raise TypeError(f"unsupported vector dtype {dt}")
+
+
+# ---------------------------------------------------------------------------
+# torch-backed device memory
+# ---------------------------------------------------------------------------
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator."""
+
+    def __init__(self, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.live = {}
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+                p = t.data_ptr()
+                self.live[p] = t
+                return p
+            except Exception:
+                return None
+
+        def _free(ptr, stream, ctx):
+            self.live.pop(ptr, None)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+    def ref(self):
+        return C.byref(self.struct)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# index
+# ---------------------------------------------------------------------------
+
+class Index:
+    """A proximity-graph index (host copy; on the device after to_device())."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+        self._alloc = None
+        self.device = None
+
+    def __del__(self):
+        try:
+            if self._h and self._h.value:
+                lib().rr_index_free(self._h)
+                self._h = C.c_void_p(0)
+        except Exception:
+            pass
+
+    @staticmethod
+    def build(base: np.ndarray, R=64, L=128, alpha=1.2, passes=2, threads=0, seed=0,
+              order=None) -> "Index":
+        """build_graph: DiskANN/Vamana construction on the host."""
+        base = np.ascontiguousarray(base)
+        bp = BuildParams()
+        lib().rr_default_build_params(C.byref(bp))
+        bp.R, bp.L, bp.alpha, bp.passes, bp.threads, bp.seed = R, L, alpha, passes, threads, seed
+        if order is not None:
+            order = np.ascontiguousarray(order, dtype=np.int64)
+            bp.order = order.ctypes.data_as(C.POINTER(C.c_int64))
+        out = C.c_void_p()
+        _check(lib().rr_index_build(base.ctypes.data, _dtype_code(base.dtype), base.shape[0],
+                                    base.shape[1], C.byref(bp), C.byref(out)))
+        return Index(out.value)
+
+    @staticmethod
+    def from_graph(base: np.ndarray, adj: np.ndarray, entry: int) -> "Index":
+        base = np.ascontiguousarray(base)
+        adj = np.ascontiguousarray(adj, dtype=np.int32)
+        out = C.c_void_p()
+        _check(lib().rr_index_from_graph(base.ctypes.data, _dtype_code(base.dtype),
+                                         base.shape[0], base.shape[1],
+                                         adj.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         adj.shape[1], int(entry), C.byref(out)))
+        return Index(out.value)
+
+    @staticmethod
+    def load(path: str) -> "Index":
+        out = C.c_void_p()
+        _check(lib().rr_index_load(path.encode(), C.byref(out)))
+        return Index(out.value)
+
+    def save(self, path: str):
+        _check(lib().rr_index_save(self._h, path.encode()))
+
+    def info(self):
+        n, d, dt, R, e = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().rr_index_info(self._h, C.byref(n), C.byref(d), C.byref(dt), C.byref(R),
+                                   C.byref(e)))
+        return dict(n=n.value, d=d.value, dtype=dt.value, R=R.value, entry=e.value)
+
+    def graph(self):
+        inf = self.info()
+        adj = np.empty((inf["n"], inf["R"]), dtype=np.int32)
+        R, e = C.c_int32(), C.c_int32()
+        _check(lib().rr_index_graph(self._h, adj.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    C.byref(R), C.byref(e)))
+        return adj, e.value
+
+    def to_device(self, device="cuda:0", stream=None):
+        import torch
+        torch.cuda.set_device(torch.device(device))
+        self._alloc = TorchAllocator(device)
+        _check(lib().rr_index_to_device(self._h, self._alloc.ref(), _stream_handle(stream)))
+        self.device = device
+        return self
+
+
+# ---------------------------------------------------------------------------
+# results
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Results:
+    offsets: "object"   # torch int64 [nq + 1] on the device
+    ids: "object"       # torch int32 [total]
+    dists: "object"     # torch int32 (integer data) / float32 (float data)
+    stats: np.ndarray | None
+    batch: dict | None
+
+    def numpy(self):
+        return (self.offsets.cpu().numpy(), self.ids.cpu().numpy(), self.dists.cpu().numpy())
+
+
+class PendingResults:
+    """Handle of a search whose kernels may still run (rr_results*)."""
+
+    def __init__(self, handle, nq, dtype, alloc, keep):
+        self._h = C.c_void_p(handle)
+        self.nq = nq
+        self.dtype = dtype
+        self._alloc = alloc
+        self._keep = keep
+
+    def __del__(self):
+        try:
+            if self._h and self._h.value:
+                lib().rr_results_free(self._h)
+                self._h = C.c_void_p(0)
+        except Exception:
+            pass
+
+    def total(self) -> int:
+        t = C.c_int64()
+        _check(lib().rr_results_total(self._h, C.byref(t)))
+        return t.value
+
+    def fetch(self, with_stats=True, stream=None) -> Results:
+        import torch
+        dev = self._alloc.device
+        total = self.total()
+        offsets = torch.empty(self.nq + 1, dtype=torch.int64, device=dev)
+        ids = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+        dists = torch.empty(max(total, 1),
+                            dtype=torch.float32 if self.dtype == F32 else torch.int32,
+                            device=dev)
+        _check(lib().rr_results_copy(self._h, C.c_void_p(ids.data_ptr()),
+                                     C.c_void_p(dists.data_ptr()),
+                                     C.c_void_p(offsets.data_ptr()), _stream_handle(stream)))
+        st = None
+        agg = None
+        if with_stats:
+            st = np.zeros(self.nq, dtype=STATS_DTYPE)
+            b = BatchStats()
+            _check(lib().rr_results_stats(
+                self._h, st.ctypes.data_as(C.POINTER(QueryStats)) if self.nq else None,
+                C.byref(b)))
+            agg = b.as_dict()
+        return Results(offsets, ids[:total], dists[:total], st, agg)
+
+
+def search_params(mode="adaptive", beam=32, es_enable=False, es_visit_limit=20, es_radius=0.0,
+                  lam=1.0, precision=EXACT, recheck_margin=0.02, max_results_per_query=None,
+                  max_beam=None, result_capacity=0, cache_slots=0, waves_per_group=0):
+    sp = SearchParams()
+    lib().rr_default_search_params(C.byref(sp))
+    sp.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
+    sp.beam = int(beam)
+    sp.es_enable = int(bool(es_enable))
+    sp.es_visit_limit = int(es_visit_limit)
+    sp.es_radius = float(es_radius)
+    sp.lam = float(lam)
+    sp.precision = int(precision)
+    sp.recheck_margin = float(recheck_margin)
+    if max_results_per_query is not None:
+        sp.max_results_per_query = int(max_results_per_query)
+    if max_beam is not None:
+        sp.max_beam = int(max_beam)
+    sp.result_capacity = int(result_capacity)
+    sp.cache_slots = int(cache_slots)
+    sp.waves_per_group = int(waves_per_group)
+    return sp
+
+
+def _radius_args(radius, nq, device):
+    import torch
+    if isinstance(radius, torch.Tensor):
+        r = radius.to(device=device, dtype=torch.float64).contiguous()
+        if r.numel() != nq:
+            raise ValueError("radius tensor must have one value per query")
+        return 0.0, C.c_void_p(r.data_ptr()), r
+    return float(radius), None, None
+
+
+def range_search_async(index: Index, queries, radius, params: SearchParams | None = None,
+                       stream=None, **kw) -> PendingResults:
+    """Enqueue one batched range_search (queries: torch tensor on the index's device)."""
+    import torch
+    if index.device is None:
+        raise RRError(RR_ESTATE, "index is not on the device")
+    sp = params if params is not None else search_params(**kw)
+    q = queries.contiguous()
+    nq = q.shape[0] if q.dim() == 2 else 0
+    r0, rdev, keep = _radius_args(radius, nq, q.device)
+    out = C.c_void_p()
+    _check(lib().rr_range_search(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev, C.byref(sp),
+                                 index._alloc.ref(), _stream_handle(stream), C.byref(out)))
+    return PendingResults(out.value, nq, index.info()["dtype"], index._alloc, (q, keep))
+
+
+def range_search(index: Index, queries, radius, params: SearchParams | None = None, stream=None,
+                 with_stats=True, **kw) -> Results:
+    """range_search(queries, radius, params) -> (ids, dists, offsets) + per-query counters."""
+    return range_search_async(index, queries, radius, params, stream, **kw).fetch(with_stats, stream)
+
+
+def brute_force(index: Index, queries, radius, stream=None) -> Results:
+    """Exact range search by a dense scan (ground truth)."""
+    q = queries.contiguous()
+    nq = q.shape[0]
+    r0, rdev, keep = _radius_args(radius, nq, q.device)
+    out = C.c_void_p()
+    _check(lib().rr_brute_force(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev,
+                                index._alloc.ref(), _stream_handle(stream), C.byref(out)))
+    return PendingResults(out.value, nq, index.info()["dtype"], index._alloc, (q, keep)).fetch(
+        False, stream)
+
+
+def nn_dist(index: Index, queries, stream=None):
+    """Squared distance from each query to its nearest base point (torch float64)."""
+    import torch
+    q = queries.contiguous()
+    out = torch.empty(q.shape[0], dtype=torch.float64, device=q.device)
+    _check(lib().rr_nn_dist(index._h, C.c_void_p(q.data_ptr()), q.shape[0],
+                            C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out

@@ -1,0 +1,166 @@
+"""GPU parity of the range-search path (beam, early stop, adaptive greedy)
+against the CPU oracle, called through the C ABI via the Python binding.
+
+The graph given to both sides is built by the oracle's builder (or drawn at
+random), the radius by the oracle's radius rules: nothing on the oracle side
+comes from the GPU library.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_13245_amd import synth
+from tests.gpu_common import compare_exact, compare_float, flush_print
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_13245_amd import rr as _rr
+    _rr.lib()
+    return _rr
+
+
+@pytest.fixture(scope="module")
+def small_u8(rr):
+    """10,000 x 128 uint8 base, 1,000 queries, Vamana R=32 L=64 alpha=1.2,
+    radius at the 0.1th percentile of all query-base distances."""
+    w = synth.config_small_u8(0)
+    order = synth.permutation(len(w.base), 0)
+    adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, order)
+    r = oracle.percentile_radius(w.base, w.queries, 0.001)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    return dict(w=w, adj=adj, entry=entry, r=r, ix=ix, q=q)
+
+
+def _orc(ctx, **kw):
+    return oracle.range_search(ctx["w"].base, ctx["adj"], ctx["entry"], ctx["w"].queries,
+                               ctx["r"], **kw)
+
+
+@pytest.mark.parametrize("beam", [1, 8, 32, 100])
+def test_plain_bit_exact(rr, small_u8, beam):
+    flush_print(f"plain beam={beam} r={small_u8['r']}")
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="plain", beam=beam)
+    o = _orc(small_u8, mode=oracle.PLAIN, beam=beam)
+    compare_exact(g, o, label=f"plain b={beam}")
+
+
+@pytest.mark.parametrize("vl,esr_scale", [(1, 1.0), (5, 1.0), (20, 1.5)])
+def test_early_stop_bit_exact(rr, small_u8, vl, esr_scale):
+    esr = small_u8["r"] * esr_scale
+    flush_print(f"es vl={vl} esr={esr}")
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="es", beam=32,
+                        es_visit_limit=vl, es_radius=esr)
+    o = _orc(small_u8, mode=oracle.ES, beam=32, es_visit_limit=vl, es_radius=esr)
+    compare_exact(g, o, label=f"es vl={vl}")
+    assert g.stats["es_fired"].sum() > 0
+
+
+@pytest.mark.parametrize("beam,es", [(4, False), (16, False), (32, True), (64, True)])
+def test_adaptive_bit_exact(rr, small_u8, beam, es):
+    flush_print(f"adaptive beam={beam} es={es}")
+    kw = dict(es_enable=es, es_visit_limit=10, es_radius=small_u8["r"])
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive",
+                        beam=beam, **kw)
+    o = _orc(small_u8, mode=oracle.ADAPTIVE, beam=beam, **kw)
+    compare_exact(g, o, label=f"adaptive b={beam}")
+    assert g.stats["expanded"].sum() > 0
+
+
+@pytest.mark.parametrize("waves,cache", [(1, 64), (2, 256), (8, 1024), (4, 4096)])
+def test_kernel_shapes_do_not_change_results(rr, small_u8, waves, cache):
+    """A small visited cache forgets ids (more evaluations) but never changes
+    the beam; workgroup shape changes nothing."""
+    flush_print(f"shape waves={waves} cache={cache}")
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=32,
+                        waves_per_group=waves, cache_slots=cache)
+    o = _orc(small_u8, mode=oracle.ADAPTIVE, beam=32)
+    compare_exact(g, o, label=f"w={waves} cs={cache}")
+    if cache == 64:
+        assert g.stats["cache_overflow"].any()
+
+
+def test_per_query_radius_and_edges(rr, small_u8):
+    n = len(small_u8["w"].queries)
+    rng = np.random.default_rng(5)
+    radii = small_u8["r"] * rng.choice([0.0, 0.5, 1.0, 2.0, -1.0], size=n)
+    flush_print("per-query radii")
+    g = rr.range_search(small_u8["ix"], small_u8["q"], torch.from_numpy(radii), mode="adaptive",
+                        beam=16)
+    o = _orc(dict(small_u8, r=radii), mode=oracle.ADAPTIVE, beam=16)
+    compare_exact(g, o, label="radii")
+    # empty batch
+    e = rr.range_search(small_u8["ix"], small_u8["q"][:0], small_u8["r"], mode="plain", beam=8)
+    assert e.offsets.cpu().tolist() == [0]
+    # negative radius: every query empty
+    z = rr.range_search(small_u8["ix"], small_u8["q"][:50], -1.0, mode="adaptive", beam=8)
+    assert z.offsets.cpu().sum().item() == 0
+
+
+def test_repeatable_and_batch_invariant(rr, small_u8):
+    """Same bytes across runs and when the batch is split."""
+    a = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=32)
+    b = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=32)
+    for x, y in zip(a.numpy(), b.numpy()):
+        np.testing.assert_array_equal(x, y)
+    part = rr.range_search(small_u8["ix"], small_u8["q"][337:338], small_u8["r"],
+                           mode="adaptive", beam=32)
+    off, ids, d = a.numpy()
+    po, pi, pd = part.numpy()
+    np.testing.assert_array_equal(pi, ids[off[337]:off[338]])
+    np.testing.assert_array_equal(pd, d[off[337]:off[338]])
+
+
+def test_int8_and_ragged_dims(rr):
+    """int8 vectors with d=100 (rows padded to 128 bytes) and a tiny d."""
+    for d, signed in ((100, True), (7, False), (200, False)):
+        w = synth.gaussian_mixture_int(3000, 200, d, 30, 12.0, 9, signed=signed, spread=0.3)
+        adj, entry = oracle.build_vamana(w.base, 24, 48, 1.2, synth.permutation(3000, 1))
+        r = oracle.percentile_radius(w.base, w.queries, 0.002)
+        ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+        q = torch.from_numpy(w.queries).cuda()
+        flush_print(f"int d={d} signed={signed}")
+        for mode, om in (("plain", oracle.PLAIN), ("adaptive", oracle.ADAPTIVE)):
+            g = rr.range_search(ix, q, r, mode=mode, beam=16)
+            o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=om, beam=16)
+            compare_exact(g, o, label=f"d={d} {mode}")
+
+
+def test_float32_within_tolerance(rr):
+    """float32 unit vectors (d=96): distances within 1e-5 relative of the
+    FP64 oracle, sets equal outside a 1e-5 band around the radius."""
+    w = synth.gaussian_mixture_unit(4000, 300, 96, 40, 0.3 / np.sqrt(96), 4, spread=0.3)
+    adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, synth.permutation(4000, 2))
+    r = oracle.percentile_radius(w.base, w.queries, 0.002)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    for mode, om in (("plain", oracle.PLAIN), ("es", oracle.ES), ("adaptive", oracle.ADAPTIVE)):
+        flush_print(f"f32 {mode}")
+        g = rr.range_search(ix, q, r, mode=mode, beam=24, es_visit_limit=10, es_radius=r)
+        o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=om, beam=24,
+                                es_visit_limit=10, es_radius=r)
+        compare_float(g, o, r, label=mode)
+        np.testing.assert_array_equal(g.stats["visits"], o.stats["visits"])
+
+
+def test_random_graph_heavy_expansion(rr):
+    """A random graph with a large radius: long greedy expansions (many
+    levels, thousands of results per query) stay exact."""
+    w = synth.gaussian_mixture_int(20000, 64, 32, 8, 30.0, 21)
+    adj = synth.random_graph(20000, 16, 3)
+    entry = 0
+    r = oracle.percentile_radius(w.base, w.queries, 0.05)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    flush_print("random graph heavy")
+    g = rr.range_search(ix, q, r, mode="adaptive", beam=8)
+    o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=oracle.ADAPTIVE, beam=8)
+    compare_exact(g, o, label="heavy")
+    assert np.diff(o.offsets).max() > 2048  # exercises the multi-run merge sort

@@ -419,3 +419,16 @@ def test_vamana_pruned_rows_respect_alpha():
         if len(out) < R:
             for c in set(cand.tolist()) - set(out.tolist()):
                 assert any(alpha * alpha * D[k, c] <= D[p, c] for k in out)
+
+
+def test_pair_dists_and_percentile_match_cdist():
+    rng = np.random.default_rng(12)
+    base = rng.integers(0, 256, (300, 9)).astype(np.uint8)
+    qs = rng.integers(0, 256, (30, 9)).astype(np.uint8)
+    D = sq(qs, base)
+    np.testing.assert_array_equal(oracle.pair_dists(base, qs), D)
+    for p in (0.001, 0.01, 0.5):
+        k = int(np.ceil(p * D.size))
+        assert oracle.percentile_radius(base, qs, p) == np.sort(D.ravel())[k - 1]
+    nn = np.sort(D.min(1))
+    assert oracle.empty_fraction_radius(base, qs, 0.25) == nn[int(np.ceil(0.25 * 30)) - 1]
