@@ -101,6 +101,7 @@ typedef struct {
                                whole batch (0 = auto); exceeding it is reported */
     int32_t cache_slots;    /* LDS visited-cache entries per query (pow2, 0 = auto) */
     int32_t waves_per_group;/* waves per workgroup of the beam kernel (0 = auto) */
+    int32_t timing;         /* record HIP events around each phase (see rr_batch_stats) */
 } rr_search_params;
 
 /* Per-query counters written by the search kernels. */
@@ -124,6 +125,10 @@ typedef struct {
     int64_t visits, evals, greedy_visits, greedy_evals, rechecked;
     int64_t es_fired, expanded, truncated, cache_overflow;
     int64_t bytes_algorithmic; /* query + adjacency + row + output bytes */
+    int64_t bytes_beam;        /* the same, beam phase only                 */
+    double beam_ms;            /* with timing: beam kernel (event pair)     */
+    double greedy_ms;          /* with timing: greedy phase incl. sort/emit */
+    double total_ms;           /* with timing: whole search call            */
 } rr_batch_stats;
 
 const char *rr_last_error(void);

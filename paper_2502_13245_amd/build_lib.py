@@ -20,7 +20,7 @@ SOURCES = ["rr_api.cpp", "rr_build.cpp", "rr_kernels.hip", "rr_scan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall",
-          "-Wno-unused-function", "-Wno-unused-variable"]
+          "-Wno-unused-function", "-Wno-unused-variable", "-Xarch_host", "-march=x86-64-v3"]
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 

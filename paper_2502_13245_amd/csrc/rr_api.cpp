@@ -211,7 +211,8 @@ static rr_status new_index(const void *base, int dtype, int64_t n, int32_t d, rr
     if (!base) return fail(RR_EINVAL, "base is NULL");
     if (n < 1 || n >= (1ll << 31) - 1) return fail(RR_EINVAL, "n must be in [1, 2^31-1)");
     if (d < 1 || d > 65536) return fail(RR_EINVAL, "d must be in [1, 65536]");
-    if (padded_row_bytes((int64_t)d * esize(dtype)) < 0) return fail(RR_EINVAL, "rows too long");
+    const int32_t rb = padded_row_bytes((int64_t)d * esize(dtype));
+    if (rb < 0 || rb > 6144) return fail(RR_EINVAL, "rows longer than 6144 bytes are not supported");
     rr_index *ix = new (std::nothrow) rr_index();
     if (!ix) return fail(RR_ENOMEM, "host allocation failed");
     try {
@@ -464,10 +465,14 @@ struct rr_results {
     void *scan_tmp = nullptr;
     DevIndex ix;
     bool stats_valid = true;
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr}; // start, after beam, after greedy, end
 };
 
 extern "C" void rr_results_free(rr_results *res) {
     if (!res) return;
+    for (auto &e : res->ev)
+        if (e) (void)hipEventDestroy(e);
     res->alloc.release(res->block);
     delete res;
 }
@@ -653,11 +658,61 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
         HIP_TRY_R(launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s));
         HIP_TRY_R(launch_fill_u64(sb.hash, sb.hash_cap, ~0ull, s));
     }
+    if (sp->timing) {
+        res->timing = true;
+        for (auto &e : res->ev) HIP_TRY_R(hipEventCreate(&e));
+        HIP_TRY_R(hipEventRecord(res->ev[0], s));
+    }
     HIP_TRY_R(launch_prep_queries(ix->dev, queries_dev, nq, radius, radius_dev, cfg, sb, s));
     HIP_TRY_R(launch_set_esr(sb.qth, nq, sp->es_radius, s));
     const int cus = device_cus();
+    if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[1], s));
     HIP_TRY_R(launch_beam(ix->dev, nq, cfg, sb, cus, s));
+    if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[2], s));
     if (greedy) HIP_TRY_R(launch_greedy(ix->dev, nq, cfg, sb, cus, s));
+    if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[3], s));
+    HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
+#undef HIP_TRY_R
+    *out = res;
+    return RR_OK;
+}
+
+static rr_status brute_force_once(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                  double radius, const double *radius_dev,
+                                  const rr_allocator *alloc, void *stream, int64_t cap,
+                                  rr_results **out, int64_t *hits) {
+    rr_search_params sp;
+    rr_default_search_params(&sp);
+    const int64_t item_cap = std::max<int64_t>(cap, 1);
+    rr_results *res = nullptr;
+    rr_status st = make_results(ix, nq, &sp, true, item_cap, item_cap, 1024, alloc, stream, &res);
+    if (st != RR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    SearchBufs &sb = res->sb;
+    SearchCfg cfg{};
+#define HIP_TRY_R(expr)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            rr_results_free(res);                                                             \
+            return fail(RR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+        }                                                                                     \
+    } while (0)
+    HIP_TRY_R(launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s));
+    HIP_TRY_R(launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s));
+    HIP_TRY_R(launch_prep_queries(ix->dev, queries_dev, nq, radius, radius_dev, cfg, sb, s));
+    HIP_TRY_R(launch_brute_force(ix->dev, sb.qpad, sb.qth, nq, sb, device_cus(), s));
+    // the hit count decides whether the capacity sufficed (ground truth is
+    // not on a timed path, so this call synchronizes)
+    unsigned long long h = 0;
+    HIP_TRY_R(hipMemcpyAsync(&h, sb.level_cnt, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY_R(hipStreamSynchronize(s));
+    *hits = (int64_t)h;
+    if ((int64_t)h > item_cap) {
+        rr_results_free(res);
+        return RR_OK; // caller retries with the exact capacity
+    }
+    HIP_TRY_R(launch_finalize(ix->dtype, sb, s));
     HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
 #undef HIP_TRY_R
     *out = res;
@@ -674,17 +729,51 @@ extern "C" rr_status rr_brute_force(const rr_index *ix, const void *queries_dev,
     if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
     if (nq > 0 && !queries_dev) return fail(RR_EINVAL, "queries are NULL");
     if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
-    return fail(RR_EINVAL, "brute force is not available in this build");
+    if (ix->dtype != RR_F32 && ix->dev.row_bytes > 512)
+        return fail(RR_EINVAL, "integer rows longer than 512 bytes are not scanned");
+    int64_t cap = std::max<int64_t>(1 << 20, 16 * nq), hits = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        rr_results *res = nullptr;
+        rr_status st = brute_force_once(ix, queries_dev, nq, radius, radius_dev, alloc, stream, cap,
+                                        &res, &hits);
+        if (st != RR_OK) return st;
+        if (res) {
+            *out = res;
+            return RR_OK;
+        }
+        cap = hits + 1;
+    }
+    return fail(RR_ENOMEM, "brute force: result capacity could not be sized");
 }
 
 extern "C" rr_status rr_nn_dist(const rr_index *ix, const void *queries_dev, int64_t nq,
                                 double *nn_dev, void *stream) {
-    (void)queries_dev;
-    (void)nn_dev;
-    (void)stream;
     if (!ix) return fail(RR_EINVAL, "index is NULL");
-    if (nq < 0) return fail(RR_EINVAL, "nq out of range");
-    return fail(RR_EINVAL, "nn_dist is not available in this build");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
+    if (nq == 0) return RR_OK;
+    if (!queries_dev || !nn_dev) return fail(RR_EINVAL, "queries or output are NULL");
+    if (ix->dtype != RR_F32 && ix->dev.row_bytes > 512)
+        return fail(RR_EINVAL, "integer rows longer than 512 bytes are not scanned");
+    hipStream_t s = (hipStream_t)stream;
+    rr::Allocator al = ix->alloc;
+    al.stream = stream;
+    const size_t qbytes = (size_t)nq * ix->dev.row_bytes;
+    const size_t tbytes = ((qbytes + 255) & ~(size_t)255) + (size_t)nq * (sizeof(QThresh) + 8) + 512;
+    uint8_t *tmp = (uint8_t *)al.alloc(tbytes);
+    if (!tmp) return fail(RR_ENOMEM, "device allocation failed");
+    SearchBufs sb;
+    sb.qpad = tmp;
+    sb.qth = (QThresh *)(tmp + ((qbytes + 255) & ~(size_t)255));
+    unsigned long long *bits =
+        (unsigned long long *)((uint8_t *)sb.qth + (((size_t)nq * sizeof(QThresh) + 255) & ~(size_t)255));
+    SearchCfg cfg{};
+    hipError_t e = launch_prep_queries(ix->dev, queries_dev, nq, 0.0, nullptr, cfg, sb, s);
+    if (e == hipSuccess) e = launch_nn_dist(ix->dev, sb.qpad, nq, nn_dev, bits, s);
+    if (e == hipSuccess && !al.has_user) e = hipStreamSynchronize(s);
+    al.release(tmp);
+    if (e != hipSuccess) return fail(RR_EHIP, "nn_dist: %s", hipGetErrorString(e));
+    return RR_OK;
 }
 
 extern "C" rr_status rr_results_total(const rr_results *res, int64_t *total) {
@@ -758,6 +847,19 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
         // query + adjacency rows of visited points + rows of evaluated points + output
         agg->bytes_algorithmic = res->nq * row + (agg->visits + agg->greedy_visits) * 4ll * res->R +
                                  (agg->evals + agg->greedy_evals) * row + agg->total_results * 8ll;
+        int64_t beam_out = 0;
+        for (int64_t i = 0; i < res->nq; ++i)
+            if (!st[i].expanded) beam_out += st[i].count;
+        agg->bytes_beam = res->nq * row + agg->visits * 4ll * res->R + agg->evals * row + beam_out * 8ll;
+        if (res->timing) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, res->ev[1], res->ev[2]));
+            agg->beam_ms = ms;
+            HIP_TRY(hipEventElapsedTime(&ms, res->ev[2], res->ev[3]));
+            agg->greedy_ms = ms;
+            HIP_TRY(hipEventElapsedTime(&ms, res->ev[0], res->ev[3]));
+            agg->total_ms = ms;
+        }
     }
     return RR_OK;
 }

@@ -132,6 +132,10 @@ size_t results_copy_tmp_bytes(int64_t nq);
 hipError_t launch_brute_force(const DevIndex &ix, const uint8_t *qpad, const QThresh *qth,
                               int64_t nq, SearchBufs &sb, int num_cus, hipStream_t s);
 hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, double *nn,
-                          hipStream_t s);
+                          unsigned long long *bits, hipStream_t s);
+hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s);
+hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
+                              hipStream_t s);
+hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s);
 
 } // namespace rr

@@ -926,6 +926,20 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 // dispatch over (dtype, row split)
 // --------------------------------------------------------------------------
 
+// group the items of every task by task, sort each group by (d, id) and
+// append it to the result arena (greedy phase and brute force)
+hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s) {
+    hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb);
+    if (dtype == RR_F32) {
+        hipLaunchKernelGGL(k_scatter<double>, dim3(1024), dim3(256), 0, s, sb);
+        hipLaunchKernelGGL(k_seg_sort_emit<double>, dim3(2048), dim3(256), 0, s, sb);
+    } else {
+        hipLaunchKernelGGL(k_scatter<uint32_t>, dim3(1024), dim3(256), 0, s, sb);
+        hipLaunchKernelGGL(k_seg_sort_emit<uint32_t>, dim3(2048), dim3(256), 0, s, sb);
+    }
+    return hipGetLastError();
+}
+
 template <int DTYPE, int CPL, int G>
 static hipError_t run_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                            int num_cus, hipStream_t s) {
@@ -975,10 +989,7 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
     void *args[] = {&a};
     e = hipLaunchCooperativeKernel((const void *)kern, grid, block, args, 0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb);
-    hipLaunchKernelGGL(k_scatter<D>, dim3(1024), dim3(256), 0, s, sb);
-    hipLaunchKernelGGL(k_seg_sort_emit<D>, dim3(2048), dim3(256), 0, s, sb);
-    return hipGetLastError();
+    return launch_finalize(ix.dtype, sb, s);
 }
 
 #define RR_SPLITS(X, DT)                                                                      \

@@ -1,3 +1,368 @@
-// rr_scan.hip -- dense brute-force range scan (placeholder until the MFMA scan lands)
+// rr_scan.hip -- dense query x base scan on the matrix cores (ground truth).
+//
+// Definition 2.1 evaluated for every pair: K_q = { p : d(p, q) <= r_q }, plus
+// the per-query nearest-neighbour distance used to choose radii.  The scan is
+// a dense contraction Q X^T, so it runs on MFMA:
+//  * uint8 / int8: v_mfma_i32_16x16x64_i8.  uint8 values are shifted by -128
+//    (x ^ 0x80) into int8; squared distances are shift invariant, so
+//    d = |q'|^2 + |x'|^2 - 2 q'.x' is exact in int32.
+//  * float32: v_mfma_f64_16x16x4f64 on the float32 values widened to FP64,
+//    d = |q|^2 + |x|^2 - 2 q.x in FP64.
+// Each wave keeps QT tiles of 16 queries in registers (A operand) and
+// streams 16-point base tiles (B operand); the four waves of a workgroup
+// share the base tiles through the L1 cache.  Output tile layout of the int8
+// 16x16x64 MFMA: lane l, register v holds row 4*(l/16)+v, column l%16.
+
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
 #include "rr_internal.h"
+
+namespace rr {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+enum { SCAN_NN = 0, SCAN_RANGE = 1 };
+
+struct ScanArgs {
+    DevIndex ix;
+    const uint8_t *qpad;  // [nq][row_bytes]
+    const QThresh *qth;   // [nq] (range mode)
+    int64_t nq;
+    int64_t chunk;        // base points per workgroup
+    // nn mode
+    unsigned long long *nn_bits; // [nq] min distance bits (uint32 value or double bits)
+    // range mode: hits appended as items (task = query)
+    int32_t *item_task;
+    int32_t *item_id;
+    void *item_dist;
+    int64_t item_cap;
+    unsigned long long *item_cursor;
+    unsigned long long *task_cnt;
+    unsigned long long *overflow;
+};
+
+constexpr int QT = 4; // 16-query tiles per wave
+
+__device__ __forceinline__ uint32_t shift_u8(uint32_t w) { return w ^ 0x80808080u; }
+
+template <int DTYPE, int KS>
+__global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    constexpr int ks_n = KS; // 64-byte K steps per row
+    const int64_t q0 = ((int64_t)blockIdx.x * 4 + wid) * (QT * 16);
+    const int64_t p_begin = (int64_t)blockIdx.y * a.chunk;
+    const int64_t p_end = min(a.ix.n, p_begin + a.chunk);
+    if (q0 >= a.nq || p_begin >= p_end) return;
+
+    constexpr int KSMAX = KS;
+    v4i A[QT][KSMAX];
+    int qn_own[QT];
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+        const int64_t q = min(q0 + t * 16 + row, a.nq - 1);
+        int s = 0;
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) {
+            if (ks < ks_n) {
+                uint4 v = *reinterpret_cast<const uint4 *>(a.qpad + q * a.ix.row_bytes + ks * 64 + grp * 16);
+                if (DTYPE == RR_U8) {
+                    v.x = shift_u8(v.x);
+                    v.y = shift_u8(v.y);
+                    v.z = shift_u8(v.z);
+                    v.w = shift_u8(v.w);
+                }
+                A[t][ks] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+                s = __builtin_amdgcn_sdot4((int)v.x, (int)v.x, s, false);
+                s = __builtin_amdgcn_sdot4((int)v.y, (int)v.y, s, false);
+                s = __builtin_amdgcn_sdot4((int)v.z, (int)v.z, s, false);
+                s = __builtin_amdgcn_sdot4((int)v.w, (int)v.w, s, false);
+            }
+        }
+        // zero padding becomes -128 after the uint8 shift in queries and base
+        // rows alike, so padded coordinates add (q'-x')^2 = 0 to the distance
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        qn_own[t] = s; // lanes with row == i hold |q_i'|^2
+    }
+    int qn[QT][4];
+    int64_t rthr[QT][4];
+#pragma unroll
+    for (int t = 0; t < QT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            qn[t][v] = __shfl(qn_own[t], 4 * grp + v);
+            const int64_t q = q0 + t * 16 + 4 * grp + v;
+            rthr[t][v] = (mode == SCAN_RANGE && q < a.nq) ? a.qth[q].r_int : -1;
+        }
+    uint32_t best[QT][4];
+#pragma unroll
+    for (int t = 0; t < QT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) best[t][v] = 0xffffffffu;
+
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += 16) {
+        const int64_t p = min(p0 + row, p_end - 1);
+        const uint8_t *xr = a.ix.base + p * a.ix.row_bytes + grp * 16;
+        v4i B[KSMAX];
+        int xs = 0;
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) {
+            if (ks < ks_n) {
+                uint4 v = *reinterpret_cast<const uint4 *>(xr + ks * 64);
+                if (DTYPE == RR_U8) {
+                    v.x = shift_u8(v.x);
+                    v.y = shift_u8(v.y);
+                    v.z = shift_u8(v.z);
+                    v.w = shift_u8(v.w);
+                }
+                B[ks] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+                xs = __builtin_amdgcn_sdot4((int)v.x, (int)v.x, xs, false);
+                xs = __builtin_amdgcn_sdot4((int)v.y, (int)v.y, xs, false);
+                xs = __builtin_amdgcn_sdot4((int)v.z, (int)v.z, xs, false);
+                xs = __builtin_amdgcn_sdot4((int)v.w, (int)v.w, xs, false);
+            }
+        }
+        xs += __shfl_xor(xs, 16);
+        xs += __shfl_xor(xs, 32);
+        const bool pvalid = p0 + row < p_end;
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+            v4i acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KSMAX; ++ks)
+                if (ks < ks_n) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t][ks], B[ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int dd = qn[t][v] + xs - 2 * acc[v];
+                const uint32_t du = (uint32_t)dd;
+                if (mode == SCAN_NN) {
+                    if (pvalid && du < best[t][v]) best[t][v] = du;
+                } else {
+                    const bool hit = pvalid && (int64_t)dd <= rthr[t][v];
+                    const unsigned long long hm = __ballot(hit);
+                    if (hm) {
+                        unsigned long long base = 0;
+                        if (lane == (__ffsll((long long)hm) - 1))
+                            base = atomicAdd(a.item_cursor, (unsigned long long)__popcll(hm));
+                        base = __shfl(base, __ffsll((long long)hm) - 1);
+                        if (hit) {
+                            const int64_t pos = (int64_t)base + __builtin_amdgcn_mbcnt_hi(
+                                (unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
+                            const int64_t q = q0 + t * 16 + 4 * grp + v;
+                            if (pos < a.item_cap) {
+                                a.item_task[pos] = (int32_t)q;
+                                a.item_id[pos] = (int32_t)(p0 + row);
+                                ((uint32_t *)a.item_dist)[pos] = du;
+                                atomicAdd(&a.task_cnt[q], 1ull);
+                            } else {
+                                atomicOr(a.overflow, 64ull);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (mode == SCAN_NN) {
+#pragma unroll
+        for (int t = 0; t < QT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                uint32_t b = best[t][v];
+#pragma unroll
+                for (int m = 1; m < 16; m <<= 1) b = min(b, (uint32_t)__shfl_xor((int)b, m));
+                const int64_t q = q0 + t * 16 + 4 * grp + v;
+                if (row == 0 && q < a.nq) atomicMin(&a.nn_bits[q], (unsigned long long)b);
+            }
+    }
+}
+
+// float32 data: FP64 MFMA (16x16x4).  A: lane l holds q[i=l%16][k=4s+l/16];
+// B: lane l holds x[j=l%16][k=4s+l/16].  The FP64 output tile differs from
+// the integer one: lane l, register v holds row (l/16) + 4v, column l%16.
+#define F64_ROW(grp, v) ((grp) + 4 * (v))
+__global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    const int d = a.ix.d;
+    const int ksteps = (d + 3) / 4;
+    constexpr int QTF = 2;
+    const int64_t q0 = ((int64_t)blockIdx.x * 4 + wid) * (QTF * 16);
+    const int64_t p_begin = (int64_t)blockIdx.y * a.chunk;
+    const int64_t p_end = min(a.ix.n, p_begin + a.chunk);
+    if (q0 >= a.nq || p_begin >= p_end) return;
+    double qn_own[QTF];
+    for (int t = 0; t < QTF; ++t) {
+        const int64_t q = min(q0 + t * 16 + row, a.nq - 1);
+        const float *qr = (const float *)(a.qpad + q * a.ix.row_bytes);
+        double s = 0;
+        for (int k = grp; k < d; k += 4) s = fma((double)qr[k], (double)qr[k], s);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        qn_own[t] = s;
+    }
+    double qn[QTF][4], rr_[QTF][4];
+    double best[QTF][4];
+    for (int t = 0; t < QTF; ++t)
+        for (int v = 0; v < 4; ++v) {
+            qn[t][v] = __shfl(qn_own[t], F64_ROW(grp, v));
+            const int64_t q = q0 + t * 16 + F64_ROW(grp, v);
+            rr_[t][v] = (mode == SCAN_RANGE && q < a.nq) ? a.qth[q].r : -1.0;
+            best[t][v] = __builtin_huge_val();
+        }
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += 16) {
+        const int64_t p = min(p0 + row, p_end - 1);
+        const float *xr = (const float *)(a.ix.base + p * a.ix.row_bytes);
+        v4d acc[QTF];
+        for (int t = 0; t < QTF; ++t) acc[t] = v4d{0, 0, 0, 0};
+        double xs = 0;
+        for (int s = 0; s < ksteps; ++s) {
+            const int k = 4 * s + grp;
+            const double xv = k < d ? (double)xr[k] : 0.0;
+            xs = fma(xv, xv, xs);
+            for (int t = 0; t < QTF; ++t) {
+                const int64_t q = min(q0 + t * 16 + row, a.nq - 1);
+                const float *qr = (const float *)(a.qpad + q * a.ix.row_bytes);
+                const double qv = k < d ? (double)qr[k] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, xv, acc[t], 0, 0, 0);
+            }
+        }
+        xs += __shfl_xor(xs, 16);
+        xs += __shfl_xor(xs, 32);
+        const bool pvalid = p0 + row < p_end;
+        for (int t = 0; t < QTF; ++t)
+            for (int v = 0; v < 4; ++v) {
+                double dd = qn[t][v] + xs - 2.0 * acc[t][v];
+                if (dd < 0) dd = 0;
+                if (mode == SCAN_NN) {
+                    if (pvalid && dd < best[t][v]) best[t][v] = dd;
+                } else {
+                    const bool hit = pvalid && dd <= rr_[t][v];
+                    const unsigned long long hm = __ballot(hit);
+                    if (hm) {
+                        unsigned long long base = 0;
+                        const int leader = __ffsll((long long)hm) - 1;
+                        if (lane == leader) base = atomicAdd(a.item_cursor, (unsigned long long)__popcll(hm));
+                        base = __shfl(base, leader);
+                        if (hit) {
+                            const int64_t pos = (int64_t)base + __builtin_amdgcn_mbcnt_hi(
+                                (unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
+                            const int64_t q = q0 + t * 16 + F64_ROW(grp, v);
+                            if (pos < a.item_cap) {
+                                a.item_task[pos] = (int32_t)q;
+                                a.item_id[pos] = (int32_t)(p0 + row);
+                                ((double *)a.item_dist)[pos] = dd;
+                                atomicAdd(&a.task_cnt[q], 1ull);
+                            } else {
+                                atomicOr(a.overflow, 64ull);
+                            }
+                        }
+                    }
+                }
+            }
+    }
+    if (mode == SCAN_NN) {
+        for (int t = 0; t < QTF; ++t)
+            for (int v = 0; v < 4; ++v) {
+                double b = best[t][v];
+                for (int m = 1; m < 16; m <<= 1) b = fmin(b, __shfl_xor(b, m));
+                const int64_t q = q0 + t * 16 + F64_ROW(grp, v);
+                if (row == 0 && q < a.nq) atomicMin(&a.nn_bits[q], (unsigned long long)__double_as_longlong(b));
+            }
+    }
+}
+
+__global__ void k_nn_finish(const unsigned long long *bits, int64_t nq, int dtype, double *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = dtype == RR_F32 ? __longlong_as_double((long long)bits[i]) : (double)(uint32_t)bits[i];
+}
+
+__global__ void k_identity_tasks(int32_t *task_q, int64_t nq, unsigned long long *counters) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x)
+        task_q[i] = (int32_t)i;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counters[CTR_TASKS] = (unsigned long long)nq;
+}
+
+static hipError_t launch_scan(const ScanArgs &a0, int mode, hipStream_t s) {
+    ScanArgs a = a0;
+    const int qper = a.ix.dtype == RR_F32 ? 4 * 2 * 16 : 4 * QT * 16;
+    const int64_t qblocks = (a.nq + qper - 1) / qper;
+    // enough workgroups to fill the machine several times over
+    int64_t target = 4096;
+    int64_t pblocks = std::max<int64_t>(1, target / std::max<int64_t>(qblocks, 1));
+    a.chunk = ((a.ix.n + pblocks - 1) / pblocks + 15) / 16 * 16;
+    pblocks = (a.ix.n + a.chunk - 1) / a.chunk;
+    if (pblocks > 65535) {
+        pblocks = 65535;
+        a.chunk = ((a.ix.n + pblocks - 1) / pblocks + 15) / 16 * 16;
+        pblocks = (a.ix.n + a.chunk - 1) / a.chunk;
+    }
+    dim3 grid((unsigned)qblocks, (unsigned)pblocks), block(256);
+    if (a.ix.dtype == RR_F32) {
+        hipLaunchKernelGGL(k_scan_f32, grid, block, 0, s, a, mode);
+        return hipGetLastError();
+    }
+    const int ks = a.ix.row_bytes / 64;
+#define RR_SCAN_KS(K)                                                                         \
+    if (ks == K) {                                                                            \
+        if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K>), grid, block, 0, s, a, mode); \
+        else hipLaunchKernelGGL((k_scan_int<RR_I8, K>), grid, block, 0, s, a, mode);         \
+        return hipGetLastError();                                                             \
+    }
+    RR_SCAN_KS(1) RR_SCAN_KS(2) RR_SCAN_KS(3) RR_SCAN_KS(4) RR_SCAN_KS(6) RR_SCAN_KS(8)
+#undef RR_SCAN_KS
+    return hipErrorInvalidValue; // integer rows above 512 bytes are not scanned
+}
+
+hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, double *nn,
+                          unsigned long long *bits, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    hipError_t e = launch_fill_u64(bits, nq, ~0ull, s);
+    if (e != hipSuccess) return e;
+    ScanArgs a{};
+    a.ix = ix;
+    a.qpad = qpad;
+    a.nq = nq;
+    a.nn_bits = bits;
+    e = launch_scan(a, SCAN_NN, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nn_finish, dim3((unsigned)std::min<int64_t>((nq + 255) / 256, 4096)),
+                       dim3(256), 0, s, bits, nq, ix.dtype, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_brute_force(const DevIndex &ix, const uint8_t *qpad, const QThresh *qth,
+                              int64_t nq, SearchBufs &sb, int num_cus, hipStream_t s) {
+    (void)num_cus;
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_identity_tasks, dim3((unsigned)std::min<int64_t>((nq + 255) / 256, 4096)),
+                       dim3(256), 0, s, sb.task_q, nq, sb.counters);
+    hipError_t e = launch_fill_u64(sb.task_cnt, nq, 0ull, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u64(sb.task_evals, nq, 0ull, s);
+    if (e != hipSuccess) return e;
+    ScanArgs a{};
+    a.ix = ix;
+    a.qpad = qpad;
+    a.qth = qth;
+    a.nq = nq;
+    a.item_task = sb.item_task;
+    a.item_id = sb.item_id;
+    a.item_dist = sb.item_dist;
+    a.item_cap = sb.item_cap;
+    a.item_cursor = &sb.level_cnt[0];
+    a.task_cnt = sb.task_cnt;
+    a.overflow = &sb.counters[CTR_OVERFLOW];
+    return launch_scan(a, SCAN_RANGE, s);
+}
+
+} // namespace rr

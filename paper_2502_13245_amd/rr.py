@@ -41,7 +41,7 @@ class SearchParams(C.Structure):
                 ("precision", C.c_int32), ("recheck_margin", C.c_double),
                 ("max_results_per_query", C.c_int64), ("max_beam", C.c_int64),
                 ("result_capacity", C.c_int64), ("cache_slots", C.c_int32),
-                ("waves_per_group", C.c_int32)]
+                ("waves_per_group", C.c_int32), ("timing", C.c_int32)]
 
 
 class QueryStats(C.Structure):
@@ -64,10 +64,11 @@ class BatchStats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in
                 ("nq", "total_results", "visits", "evals", "greedy_visits", "greedy_evals",
                  "rechecked", "es_fired", "expanded", "truncated", "cache_overflow",
-                 "bytes_algorithmic")]
+                 "bytes_algorithmic", "bytes_beam")] + [
+                (k, C.c_double) for k in ("beam_ms", "greedy_ms", "total_ms")]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -327,7 +328,8 @@ class PendingResults:
 
 def search_params(mode="adaptive", beam=32, es_enable=False, es_visit_limit=20, es_radius=0.0,
                   lam=1.0, precision=EXACT, recheck_margin=0.02, max_results_per_query=None,
-                  max_beam=None, result_capacity=0, cache_slots=0, waves_per_group=0):
+                  max_beam=None, result_capacity=0, cache_slots=0, waves_per_group=0,
+                  timing=False):
     sp = SearchParams()
     lib().rr_default_search_params(C.byref(sp))
     sp.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
@@ -345,6 +347,7 @@ def search_params(mode="adaptive", beam=32, es_enable=False, es_visit_limit=20, 
     sp.result_capacity = int(result_capacity)
     sp.cache_slots = int(cache_slots)
     sp.waves_per_group = int(waves_per_group)
+    sp.timing = int(bool(timing))
     return sp
 
 

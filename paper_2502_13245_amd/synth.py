@@ -101,6 +101,50 @@ def gaussian_mixture_unit(n: int, nq: int, d: int, k: int, sigma: float, seed: i
     return Workload(name, base, queries, meta)
 
 
+def latent_mixture_u8(n: int, nq: int, d: int, k: int, sigma: float, seed: int, *,
+                      latent: int = 16, center_std: float = 40.0, within: int = 10,
+                      noise: float = 4.0, spread: float = 0.35, zipf: float = 1.0,
+                      dense_frac: float = 0.1, dense_sigma: float = 6.0, chunk: int = 1 << 16,
+                      name: str = "latent-u8") -> Workload:
+    """uint8 mixture with low intrinsic dimension, like image descriptors.
+
+    Centres lie on a `latent`-dimensional Gaussian sheet around 127.5
+    (c = 127.5 + A u, per-coordinate std `center_std`); each cluster varies
+    along its own `within`-dimensional random basis with per-coordinate std
+    sigma_k, plus isotropic noise of std `noise`; values are rounded and
+    clipped to [0, 255].  sigma_k = sigma * exp(U[-spread, spread]), except a
+    `dense_frac` share of clusters that are near-duplicate groups with
+    sigma_k = dense_sigma * exp(U[-0.5, 0.5]).  Zipf(`zipf`) cluster weights
+    set the cluster sizes, so a few dense groups hold thousands of points."""
+    ss = np.random.SeedSequence(seed).spawn(7)
+    r_c, r_s, r_l, r_x, r_ql, r_qx, r_b = [np.random.default_rng(x) for x in ss]
+    A = r_c.standard_normal((d, latent)) * (center_std / np.sqrt(latent))
+    centers = np.clip(127.5 + r_c.standard_normal((k, latent)) @ A.T, 0.0, 255.0)
+    scale = sigma * np.exp(r_s.uniform(-spread, spread, size=k))
+    dense = r_s.random(k) < dense_frac
+    scale[dense] = dense_sigma * np.exp(r_s.uniform(-0.5, 0.5, size=int(dense.sum())))
+    basis = r_b.standard_normal((k, d, within)) / np.sqrt(within)
+
+    def draw(m, rl, rx):
+        lab = _labels(rl, k, m, zipf)
+        out = np.empty((m, d), dtype=np.uint8)
+        for a in range(0, m, chunk):
+            b = min(m, a + chunk)
+            L = lab[a:b]
+            z = rx.standard_normal(size=(b - a, within)) * scale[L, None]
+            v = centers[L] + np.einsum("ndm,nm->nd", basis[L], z)
+            v += noise * rx.standard_normal(size=(b - a, d))
+            out[a:b] = np.clip(np.rint(v), 0, 255).astype(np.uint8)
+        return out
+
+    base = draw(n, r_l, r_x)
+    queries = draw(nq, r_ql, r_qx)
+    meta = dict(generator="latent_mixture_u8", n=n, nq=nq, d=d, k=k, sigma=sigma, seed=seed,
+                latent=latent, center_std=center_std, within=within, noise=noise, spread=spread,
+                zipf=zipf, dense_frac=dense_frac, dense_sigma=dense_sigma, dtype="uint8")
+    return Workload(name, base, queries, meta)
+
+
 def permutation(n: int, seed: int) -> np.ndarray:
     """Seeded insertion order for graph construction (an input, like the data)."""
     return np.random.default_rng(np.random.SeedSequence([seed, 0x5EED])).permutation(n).astype(np.int64)
@@ -131,7 +175,9 @@ def random_graph_fast(n: int, R: int, seed: int) -> np.ndarray:
     s = np.sort(adj, axis=1)
     dup_sorted = np.zeros_like(s, dtype=bool)
     dup_sorted[:, 1:] = s[:, 1:] == s[:, :-1]
-    s[dup_sorted] = -1
+    s[dup_sorted] = n  # repeats sort to the end, then become -1 padding
+    s.sort(axis=1)
+    s[s == n] = -1
     return s.astype(np.int32)
 
 
@@ -149,9 +195,9 @@ def config_small_u8(seed: int = 0) -> Workload:
 
 def config_1m_u8(seed: int = 1, n: int = 1_000_000, nq: int = 10_000) -> Workload:
     """1M base + 10,000 queries, d=128 uint8, 1,000-centre mixture (sigma 25)
-    with per-cluster spread and Zipf weights for the heavy result tail."""
-    return gaussian_mixture_int(n, nq, 128, 1_000, 25.0, seed, spread=0.35, zipf=1.0,
-                                name=f"u8-{n // 1000}k-d128")
+    with low intrinsic dimension, Zipf cluster sizes and 10% near-duplicate
+    groups: most queries empty at the benchmark radius, a heavy result tail."""
+    return latent_mixture_u8(n, nq, 128, 1_000, 25.0, seed, name=f"u8-{n // 1000}k-d128")
 
 
 def config_1m_f32(seed: int = 2, n: int = 1_000_000, nq: int = 10_000) -> Workload:
