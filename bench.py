@@ -59,6 +59,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", default="", help="load the index from this file if present")
+    ap.add_argument("--choice", default="", help="write (full run) / read (--only) the chosen "
+                                                 "setting as JSON")
+    ap.add_argument("--only", action="store_true",
+                    help="profiling mode: skip sweeps, run the setting from --choice --steps times")
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="also run a device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; this build has no multi-GPU path (asked for {args.gpus})",
@@ -79,7 +85,8 @@ def main():
         build_s = None
         log(f"index loaded from {args.graph}")
     else:
-        ix = rr.Index.build(w.base, R=64, L=128, alpha=1.2, passes=2, threads=threads, seed=1)
+        ix = rr.Index.build(w.base, R=64, L=128, alpha=1.2, passes=2, threads=threads, seed=1,
+                            verbose=True)
         build_s = time.time() - t0
         log(f"graph built on the host in {build_s:.1f}s ({threads} threads)")
         if args.graph:
@@ -88,6 +95,22 @@ def main():
     q = torch.from_numpy(w.queries).cuda()
     n, nq, d = args.n, args.nq, 128
     torch.cuda.synchronize()
+
+    if args.only:
+        ch = json.load(open(args.choice))
+        if args.copy_ref_mb:
+            src = torch.empty(args.copy_ref_mb << 20, dtype=torch.uint8, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"copy reference: {args.copy_ref_mb} MiB device-to-device x3")
+        for _ in range(args.steps):
+            rr.range_search(ix, q, ch["radius"], mode=ch["mode"], beam=ch["beam"],
+                            with_stats=False, **ch["kw"])
+        torch.cuda.synchronize()
+        log(f"profiling run done: {args.steps} x {ch['mode']} b={ch['beam']}")
+        return
 
     # radius: 75% of queries empty (nearest-neighbour distance quantile), on the GPU
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -157,6 +180,9 @@ def main():
     if "adaptive" not in best:
         raise SystemExit("adaptive search did not reach the recall target")
     A = best["adaptive"]
+    if args.choice:
+        json.dump(dict(radius=radius, mode=A["mode"], beam=A["beam"], kw=A["kw"]),
+                  open(args.choice, "w"))
 
     # timed steps: the chosen adaptive setting
     for _ in range(args.warmup):
@@ -186,7 +212,10 @@ def main():
                     kernel="k_beam", bytes_per_launch=int(st["bytes_beam"]),
                     avg_ms=round(beam_avg, 4))
     log(f"adaptive b={A['beam']}: {qps:,.0f} QPS, beam kernel {beam_avg:.3f} ms "
-        f"({achieved:.0f} GB/s), greedy {np.mean(greedy_ms):.3f} ms, call {np.mean(total_ms):.3f} ms")
+        f"({achieved:.0f} GB/s), greedy {np.mean(greedy_ms):.3f} ms, call {np.mean(total_ms):.3f} ms; "
+        f"greedy levels {st['greedy_levels']}, items {st['greedy_items']}, tasks {st['expanded']}, "
+        f"evals {st['greedy_evals']}, beam visits {st['visits']}, beam evals {st['evals']}, "
+        f"cache overflow {st['cache_overflow']}")
 
     # CPU oracle on the host cores, bounded sample
     cpu = None
@@ -239,6 +268,8 @@ def main():
                     "tops": round(scan_tops, 1), "peak_tops": INT8_PEAK_TOPS,
                     "frac": round(scan_tops / INT8_PEAK_TOPS, 4)},
         "graph_build_s": round(build_s, 1) if build_s else None,
+        "greedy": {"ms": round(float(np.mean(greedy_ms)), 4), "levels": st["greedy_levels"],
+                   "items": st["greedy_items"], "tasks": st["expanded"]},
         "curves": curves,
     }
     print(json.dumps(out), flush=True)

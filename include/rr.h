@@ -84,6 +84,7 @@ typedef struct {
     int32_t threads;      /* host threads (0 = all cores)              */
     uint64_t seed;        /* insertion order seed when order == NULL   */
     const int64_t *order; /* optional insertion order (permutation of n) */
+    int32_t verbose;      /* print progress lines to stderr              */
 } rr_build_params;
 
 typedef struct {
@@ -129,6 +130,8 @@ typedef struct {
     double beam_ms;            /* with timing: beam kernel (event pair)     */
     double greedy_ms;          /* with timing: greedy phase incl. sort/emit */
     double total_ms;           /* with timing: whole search call            */
+    int64_t greedy_levels;     /* frontier levels run by the greedy phase   */
+    int64_t greedy_items;      /* frontier items (in-ball points) processed */
 } rr_batch_stats;
 
 const char *rr_last_error(void);

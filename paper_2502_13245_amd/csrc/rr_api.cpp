@@ -184,6 +184,7 @@ extern "C" void rr_default_build_params(rr_build_params *p) {
     p->threads = 0;
     p->seed = 0;
     p->order = nullptr;
+    p->verbose = 0;
 }
 
 extern "C" void rr_default_search_params(rr_search_params *p) {
@@ -622,14 +623,17 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     if (cs & (cs - 1)) return fail(RR_EINVAL, "cache_slots must be a power of two");
     if (cs < 64 || cs > 16384) return fail(RR_EINVAL, "cache_slots must be in [64, 16384]");
     cfg.cache_slots = cs;
-    int waves = sp->waves_per_group > 0 ? sp->waves_per_group : 4;
+    const size_t per_wave = (size_t)(ix->dtype == RR_F32 ? 24 : 16) * sp->beam + 64 * 12 + cs * 4 + 128;
+    const size_t lds_cap = 160 * 1024;
+    if (per_wave > lds_cap) return fail(RR_EINVAL, "beam/cache_slots exceed the LDS of one CU");
+    int waves = sp->waves_per_group;
+    if (waves <= 0) waves = (int)std::max<size_t>(1, std::min<size_t>(4, lds_cap / per_wave));
     if (waves > 8) return fail(RR_EINVAL, "waves_per_group must be <= 8");
+    if (per_wave * waves > lds_cap) return fail(RR_EINVAL, "beam/cache_slots/waves exceed LDS");
     cfg.waves = waves;
     cfg.max_results_per_query = sp->max_results_per_query;
     cfg.max_beam = sp->max_beam;
     cfg.margin = sp->recheck_margin;
-    const size_t per_wave = (size_t)(ix->dtype == RR_F32 ? 24 : 16) * sp->beam + 64 * 12 + cs * 4 + 128;
-    if (per_wave * waves > 160 * 1024) return fail(RR_EINVAL, "beam/cache_slots/waves exceed LDS");
 
     const bool greedy = sp->mode == RR_ADAPTIVE;
     int64_t gcap = 0, hash_cap = 0, item_cap = 0;
@@ -637,7 +641,7 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
         gcap = sp->result_capacity > 0 ? sp->result_capacity
                                        : std::min<int64_t>(std::max<int64_t>(nq, 1) * 4096, 1 << 21);
         item_cap = nq * (int64_t)sp->beam + gcap;
-        hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024));
+        hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024)); // >= 8 and a power of two
     }
     const int64_t arena_cap = nq * (int64_t)sp->beam + gcap;
     rr_results *res = nullptr;
@@ -851,6 +855,17 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
         for (int64_t i = 0; i < res->nq; ++i)
             if (!st[i].expanded) beam_out += st[i].count;
         agg->bytes_beam = res->nq * row + agg->visits * 4ll * res->R + agg->evals * row + beam_out * 8ll;
+        if (res->sb.level_cnt) {
+            unsigned long long ctr[CTR_COUNT];
+            HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
+            const int64_t lv = (int64_t)ctr[CTR_LEVELS];
+            agg->greedy_levels = lv;
+            std::vector<unsigned long long> lc((size_t)std::max<int64_t>(lv, 1));
+            if (lv > 0)
+                HIP_TRY(hipMemcpy(lc.data(), res->sb.level_cnt, lv * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < lv; ++i) agg->greedy_items += (int64_t)lc[i];
+        }
         if (res->timing) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, res->ev[1], res->ev[2]));

@@ -25,6 +25,8 @@
 #include <random>
 #include <thread>
 #include <vector>
+#include <chrono>
+#include <cstdio>
 
 #include "rr_internal.h"
 
@@ -297,6 +299,7 @@ rr_status vamana_build(const void *base, int dtype, int64_t n, int32_t d, const 
     std::vector<int32_t> snap;
     std::vector<int32_t> newadj((size_t)cap * R), newdeg((size_t)cap);
     std::vector<std::pair<int32_t, int32_t>> edges;
+    const auto t_start = std::chrono::steady_clock::now();
     for (int pass = 0; pass < bp->passes; ++pass) {
         const double alpha = (bp->passes == 2 && pass == 0) ? 1.0 : bp->alpha;
         int64_t pos = 0, bsz = 1;
@@ -350,8 +353,15 @@ rr_status vamana_build(const void *base, int dtype, int64_t n, int32_t d, const 
                     g.deg[j] = k;
                 }
             });
+            const int64_t before = pos;
             pos += cnt;
             bsz = std::min(bsz * 2, cap);
+            if (bp->verbose && (pos * 10 / n) != (before * 10 / n)) {
+                const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+                std::fprintf(stderr, "[build] pass %d/%d: %lld/%lld points inserted (%.1fs)\n", pass + 1,
+                             bp->passes, (long long)pos, (long long)n, secs);
+                std::fflush(stderr);
+            }
         }
     }
     adj_out.swap(g.adj);

@@ -87,16 +87,35 @@ __device__ __forceinline__ bool seen_insert(uint32_t *tab, uint32_t cs_mask, uin
 
 // Global exact set of (task, id) keys: returns true if the key was inserted
 // now, false if it was present.  `full` is set if the probe budget ran out.
+// Probing reads whole 8-slot buckets (64 bytes) with plain loads and uses CAS
+// only on the first slot that looked empty.  Within one search a slot only
+// ever changes from empty to a key, so a stale read can only show "empty";
+// the CAS then fails and reveals the key, so the set stays exact.
 __device__ __forceinline__ bool gset_insert(unsigned long long *tab, int64_t cap_mask,
                                             unsigned long long key, bool &full) {
     uint64_t h = (uint64_t)hash32((uint32_t)key ^ hash32((uint32_t)(key >> 32))) * 0x9E3779B97F4A7C15ull;
     h ^= h >> 29;
+    const uint64_t b0 = h & (uint64_t)cap_mask & ~7ull;
 #pragma unroll 1
-    for (int p = 0; p < 128; ++p) {
-        int64_t slot = (int64_t)((h + (uint64_t)p) & (uint64_t)cap_mask);
-        unsigned long long old = atomicCAS(&tab[slot], ~0ull, key);
-        if (old == ~0ull) return true;
-        if (old == key) return false;
+    for (int pb = 0; pb < 16; ++pb) {
+        const uint64_t b = (b0 + 8ull * (uint64_t)pb) & (uint64_t)cap_mask;
+        const uint4 *bp = reinterpret_cast<const uint4 *>(tab + b);
+        unsigned long long v[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4 w = bp[j];
+            v[2 * j] = ((unsigned long long)w.y << 32) | w.x;
+            v[2 * j + 1] = ((unsigned long long)w.w << 32) | w.z;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (v[j] == key) return false;
+            if (v[j] == ~0ull) {
+                const unsigned long long old = atomicCAS(&tab[b + j], ~0ull, key);
+                if (old == ~0ull) return true;
+                if (old == key) return false;
+            }
+        }
     }
     full = true;
     return false;
@@ -631,21 +650,69 @@ struct GreedyArgs {
     SearchBufs sb;
 };
 
+constexpr int GREEDY_WAVES = 4;     // waves per workgroup
+constexpr int GREEDY_CACHE = 1024;  // per-wave LDS cache of ids known to the global set
+constexpr int GREEDY_STAGE = 256;   // per-wave staged outputs before a global reservation
+
+template <typename D> struct GreedyLds {
+    uint32_t ci[GREEDY_WAVES][64];
+    D cd[GREEDY_WAVES][64];
+    uint32_t cache[GREEDY_WAVES][GREEDY_CACHE];
+    uint32_t st_id[GREEDY_WAVES][GREEDY_STAGE];
+    int32_t st_task[GREEDY_WAVES][GREEDY_STAGE];
+    D st_d[GREEDY_WAVES][GREEDY_STAGE];
+    int32_t st_n[GREEDY_WAVES];
+    unsigned long long wg_base;
+};
+
+// write a wave's staged outputs to items [dst, dst + n); every slot below
+// item_cap is written, so the next level never reads an unwritten item
+template <typename D>
+__device__ __forceinline__ void greedy_emit(GreedyLds<D> &L, int wid, int n, int64_t dst,
+                                            const SearchBufs &sb) {
+    const int lane = lane_id();
+    D *idist = (D *)sb.item_dist;
+    for (int i = lane; i < n; i += 64) {
+        const int64_t o = dst + i;
+        if (o < sb.item_cap) {
+            sb.item_task[o] = L.st_task[wid][i];
+            sb.item_id[o] = (int32_t)L.st_id[wid][i];
+            idist[o] = L.st_d[wid][i];
+        }
+    }
+    // results per task, one atomic per run of equal tasks (runs are contiguous)
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        const bool valid = i < n && dst + i < sb.item_cap;
+        const int32_t t = valid ? L.st_task[wid][i] : -1;
+        const int32_t tprev = __shfl_up(t, 1);
+        const bool head = valid && (lane == 0 || tprev != t);
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long vm = __ballot(valid);
+        if (head) {
+            // run length: up to the next head or the end of the valid lanes
+            const unsigned long long later = hm & ~((2ull << lane) - 1ull);
+            const int end = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)vm);
+            atomicAdd(&sb.task_cnt[t], (unsigned long long)(end - lane));
+        }
+    }
+    if (dst + n > sb.item_cap && lane == 0) atomicOr(&sb.counters[CTR_OVERFLOW], 4ull);
+}
+
 template <int DTYPE, int CPL, int G>
 __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
     using D = typename DistOf<DTYPE>::T;
-    __shared__ uint32_t s_ci[4][64];
-    __shared__ D s_cd[4][64];
+    __shared__ GreedyLds<D> L;
     cg::grid_group grid = cg::this_grid();
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wid;
-    const int64_t tw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t gw = (int64_t)blockIdx.x * GREEDY_WAVES + wid;
+    const int64_t tw = (int64_t)gridDim.x * GREEDY_WAVES;
     const DevIndex &ix = a.ix;
     const int R = ix.R;
-    uint32_t *ci = s_ci[wid];
-    D *cd = s_cd[wid];
-    D *idist = (D *)a.sb.item_dist;
+    uint32_t *ci = L.ci[wid];
+    D *cd = L.cd[wid];
+    uint32_t *cache = L.cache[wid];
     const int64_t hmask = a.sb.hash_cap - 1;
     const int64_t ntasks = (int64_t)a.sb.counters[CTR_TASKS];
     int64_t base = 0;
@@ -655,61 +722,106 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
                                                        __HIP_MEMORY_SCOPE_AGENT);
         if (cnt == 0) break;
         const int64_t next_base = base + cnt;
-        for (int64_t it = gw; it < cnt; it += tw) {
-            const int64_t item = base + it;
-            if (item >= a.sb.item_cap) break;
-            const int32_t t = a.sb.item_task[item];
-            const int32_t p = a.sb.item_id[item];
-            if (t < 0 || t >= ntasks || p < 0 || (int64_t)p >= ix.n) continue; // never written
-            const int32_t q = a.sb.task_q[t];
-            const QThresh th = a.sb.qth[q];
-            QueryRegs<DTYPE, CPL, G> qr;
-            qr.load(a.sb.qpad + (size_t)q * ix.row_bytes);
-            int32_t f = -1;
-            if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
-            bool full = false;
+        if (lane == 0) L.st_n[wid] = 0;
+        // a contiguous block of items per wave keeps one task's items together
+        const int64_t per = (cnt + tw - 1) / tw;
+        const int64_t i0 = gw * per, i1 = min(cnt, i0 + per);
+        int32_t cur = -1;
+        unsigned long long run_evals = 0;
+        QThresh th{};
+        QueryRegs<DTYPE, CPL, G> qr;
+        const int64_t i_end = min(i1, a.sb.item_cap - base);
+        auto item_ok = [&](int32_t t, int32_t p) {
+            return t >= 0 && t < ntasks && p >= 0 && (int64_t)p < ix.n;
+        };
+        // one-item pipeline: the next item's adjacency row is in flight while
+        // the current item probes the hash set and gathers its rows
+        int32_t t_nx = -1, p_nx = -1, f_nx = -1;
+        if (i0 < i_end) {
+            t_nx = a.sb.item_task[base + i0];
+            p_nx = a.sb.item_id[base + i0];
+            if (item_ok(t_nx, p_nx) && lane < R) f_nx = ix.adj[(size_t)p_nx * (size_t)R + lane];
+        }
+        for (int64_t it = i0; it < i_end; ++it) {
+            const int32_t t = t_nx, p = p_nx;
+            const int32_t f = f_nx;
+            t_nx = -1;
+            p_nx = -1;
+            f_nx = -1;
+            if (it + 1 < i_end) {
+                t_nx = a.sb.item_task[base + it + 1];
+                p_nx = a.sb.item_id[base + it + 1];
+                if (item_ok(t_nx, p_nx) && lane < R) f_nx = ix.adj[(size_t)p_nx * (size_t)R + lane];
+            }
+            if (!item_ok(t, p)) continue; // never written
+            if (t != cur) {
+                if (cur >= 0 && lane == 0 && run_evals) atomicAdd(&a.sb.task_evals[cur], run_evals);
+                run_evals = 0;
+                cur = t;
+                const int32_t q = a.sb.task_q[t];
+                th = a.sb.qth[q];
+                qr.load(a.sb.qpad + (size_t)q * ix.row_bytes);
+                for (int i = lane; i < GREEDY_CACHE; i += 64) cache[i] = RR_EMPTY32;
+                wave_sync();
+            }
+            bool full = false, ovf = false;
             bool cand = false;
-            if (f >= 0) cand = gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | (uint32_t)f, full);
+            if (f >= 0 && !seen_insert(cache, GREEDY_CACHE - 1, (uint32_t)f, ovf))
+                cand = gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | (uint32_t)f, full);
             const unsigned long long cm = __ballot(cand);
             const int k = __popcll(cm);
             if (cand) ci[mbcnt(cm)] = (uint32_t)f;
             wave_sync();
-            if (k > 0) {
-                eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
-                bool inr = false;
-                D myd = dmax<D>();
-                uint32_t myi = 0;
-                if (lane < k) {
-                    myd = cd[lane];
-                    myi = ci[lane];
-                    inr = in_range<D>(myd, th);
-                }
-                const unsigned long long im = __ballot(inr);
-                const int m = __popcll(im);
-                int64_t off = 0;
-                if (lane == 0 && m > 0)
-                    off = (int64_t)atomicAdd(&a.sb.level_cnt[lvl + 1], (unsigned long long)m);
-                off = __shfl(off, 0) + next_base;
-                // every reserved slot below item_cap is written, so the next
-                // level never reads an unwritten item
-                const int64_t o = off + mbcnt(im);
-                const bool wrote = inr && o < a.sb.item_cap;
-                if (wrote) {
-                    a.sb.item_task[o] = t;
-                    a.sb.item_id[o] = (int32_t)myi;
-                    idist[o] = myd;
-                }
-                const int mw = __popcll(__ballot(wrote));
-                if (lane == 0) {
-                    atomicAdd(&a.sb.task_evals[t], (unsigned long long)k);
-                    if (mw > 0) atomicAdd(&a.sb.task_cnt[t], (unsigned long long)mw);
-                    if (mw < m) atomicOr(&a.sb.counters[CTR_OVERFLOW], 4ull);
-                }
-            }
             if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
+            if (k == 0) continue;
+            run_evals += (unsigned long long)k;
+            eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
+            bool inr = false;
+            D myd = dmax<D>();
+            uint32_t myi = 0;
+            if (lane < k) {
+                myd = cd[lane];
+                myi = ci[lane];
+                inr = in_range<D>(myd, th);
+            }
+            const unsigned long long im = __ballot(inr);
+            const int m = __popcll(im);
+            if (m == 0) continue;
+            int sn = L.st_n[wid];
+            if (sn + m > GREEDY_STAGE) {
+                // stage full: reserve for it now
+                unsigned long long o = 0;
+                if (lane == 0) o = atomicAdd(&a.sb.level_cnt[lvl + 1], (unsigned long long)sn);
+                o = __shfl(o, 0);
+                greedy_emit<D>(L, wid, sn, next_base + (int64_t)o, a.sb);
+                wave_sync();
+                sn = 0;
+            }
+            if (inr) {
+                const int o = sn + mbcnt(im);
+                L.st_id[wid][o] = myi;
+                L.st_task[wid][o] = t;
+                L.st_d[wid][o] = myd;
+            }
+            wave_sync();
+            if (lane == 0) L.st_n[wid] = sn + m;
             wave_sync();
         }
-        __threadfence();
+        if (cur >= 0 && lane == 0 && run_evals) atomicAdd(&a.sb.task_evals[cur], run_evals);
+        // one reservation per workgroup for what the waves still hold
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < GREEDY_WAVES; ++w) tot += (unsigned long long)L.st_n[w];
+            L.wg_base = tot ? atomicAdd(&a.sb.level_cnt[lvl + 1], tot) : 0ull;
+        }
+        __syncthreads();
+        {
+            int64_t off = (int64_t)L.wg_base;
+            for (int w = 0; w < wid; ++w) off += L.st_n[w];
+            const int sn = L.st_n[wid];
+            if (sn > 0) greedy_emit<D>(L, wid, sn, next_base + off, a.sb);
+        }
         grid.sync();
         base = next_base;
     }
@@ -755,22 +867,44 @@ __global__ void k_task_scan(SearchBufs sb) {
 template <typename D> __global__ void k_scatter(SearchBufs sb) {
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
     if (nt == 0) return;
-    const int64_t total = sb.seg_off[nt];
+    const int64_t total = min(sb.seg_off[nt], sb.item_cap);
     const D *idist = (const D *)sb.item_dist;
     D *sd = (D *)sb.seg_dists;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total && i < sb.item_cap;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t t = sb.item_task[i];
-        const int64_t pos = sb.seg_off[t] + (int64_t)atomicAdd(&sb.seg_cur[t], 1ull);
-        sb.seg_ids[pos] = sb.item_id[i];
-        sd[pos] = idist[i];
+    const int lane = lane_id();
+    // whole waves walk the items so equal-task runs share one atomic
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t tw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = w0 * 64; c < total; c += tw * 64) {
+        const int64_t i = c + lane;
+        const bool valid = i < total;
+        const int32_t t = valid ? sb.item_task[i] : -1;
+        const int32_t tprev = __shfl_up(t, 1);
+        const bool head = valid && (lane == 0 || tprev != t);
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long vm = __ballot(valid);
+        unsigned long long b = 0;
+        if (head) {
+            const unsigned long long later = hm & ~((2ull << lane) - 1ull);
+            const int end = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)vm);
+            b = atomicAdd(&sb.seg_cur[t], (unsigned long long)(end - lane));
+        }
+        // each lane's run head: the highest head lane at or below it
+        const unsigned long long mine = hm & ((2ull << lane) - 1ull);
+        const int hl = mine ? 63 - __clzll((long long)mine) : 0;
+        b = __shfl(b, hl);
+        if (valid) {
+            const int64_t pos = sb.seg_off[t] + (int64_t)b + (lane - hl);
+            sb.seg_ids[pos] = sb.item_id[i];
+            sd[pos] = idist[i];
+        }
     }
 }
 
 // Sort one segment by (d, id) with the whole workgroup.  Segments that fit
 // in LDS use a bitonic network; longer ones are sorted in runs of that size
 // and merged pairwise through `tmp` (same length) by rank computation.
-constexpr int SORT_LDS = 2048;
+constexpr int SORT_LDS = 8192;
+constexpr int SORT_THREADS = 1024;
 
 template <typename D>
 __device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int64_t n, D *sd,
@@ -871,9 +1005,10 @@ __device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int6
     }
 }
 
-template <typename D> __global__ __launch_bounds__(256) void k_seg_sort_emit(SearchBufs sb) {
-    __shared__ D sd[SORT_LDS];
-    __shared__ uint32_t si[SORT_LDS];
+template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort_emit(SearchBufs sb) {
+    extern __shared__ __align__(16) uint8_t sort_smem[];
+    D *sd = (D *)sort_smem;
+    uint32_t *si = (uint32_t *)(sort_smem + SORT_LDS * sizeof(D));
     __shared__ int64_t s_off;
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
     D *segd = (D *)sb.seg_dists;
@@ -928,16 +1063,19 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 
 // group the items of every task by task, sort each group by (d, id) and
 // append it to the result arena (greedy phase and brute force)
-hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s) {
+template <typename D> static hipError_t run_finalize(SearchBufs &sb, hipStream_t s) {
+    const size_t shmem = (size_t)SORT_LDS * (sizeof(D) + 4);
+    hipError_t e = hipFuncSetAttribute((const void *)k_seg_sort_emit<D>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb);
-    if (dtype == RR_F32) {
-        hipLaunchKernelGGL(k_scatter<double>, dim3(1024), dim3(256), 0, s, sb);
-        hipLaunchKernelGGL(k_seg_sort_emit<double>, dim3(2048), dim3(256), 0, s, sb);
-    } else {
-        hipLaunchKernelGGL(k_scatter<uint32_t>, dim3(1024), dim3(256), 0, s, sb);
-        hipLaunchKernelGGL(k_seg_sort_emit<uint32_t>, dim3(2048), dim3(256), 0, s, sb);
-    }
+    hipLaunchKernelGGL(k_scatter<D>, dim3(1024), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL(k_seg_sort_emit<D>, dim3(2048), dim3(SORT_THREADS), shmem, s, sb);
     return hipGetLastError();
+}
+
+hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s) {
+    return dtype == RR_F32 ? run_finalize<double>(sb, s) : run_finalize<uint32_t>(sb, s);
 }
 
 template <int DTYPE, int CPL, int G>

@@ -32,7 +32,8 @@ class RRError(RuntimeError):
 
 class BuildParams(C.Structure):
     _fields_ = [("R", C.c_int32), ("L", C.c_int32), ("alpha", C.c_double), ("passes", C.c_int32),
-                ("threads", C.c_int32), ("seed", C.c_uint64), ("order", C.POINTER(C.c_int64))]
+                ("threads", C.c_int32), ("seed", C.c_uint64), ("order", C.POINTER(C.c_int64)),
+                ("verbose", C.c_int32)]
 
 
 class SearchParams(C.Structure):
@@ -65,7 +66,8 @@ class BatchStats(C.Structure):
                 ("nq", "total_results", "visits", "evals", "greedy_visits", "greedy_evals",
                  "rechecked", "es_fired", "expanded", "truncated", "cache_overflow",
                  "bytes_algorithmic", "bytes_beam")] + [
-                (k, C.c_double) for k in ("beam_ms", "greedy_ms", "total_ms")]
+                (k, C.c_double) for k in ("beam_ms", "greedy_ms", "total_ms")] + [
+                (k, C.c_int64) for k in ("greedy_levels", "greedy_items")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -206,12 +208,13 @@ class Index:
 
     @staticmethod
     def build(base: np.ndarray, R=64, L=128, alpha=1.2, passes=2, threads=0, seed=0,
-              order=None) -> "Index":
+              order=None, verbose=False) -> "Index":
         """build_graph: DiskANN/Vamana construction on the host."""
         base = np.ascontiguousarray(base)
         bp = BuildParams()
         lib().rr_default_build_params(C.byref(bp))
         bp.R, bp.L, bp.alpha, bp.passes, bp.threads, bp.seed = R, L, alpha, passes, threads, seed
+        bp.verbose = int(bool(verbose))
         if order is not None:
             order = np.ascontiguousarray(order, dtype=np.int64)
             bp.order = order.ctypes.data_as(C.POINTER(C.c_int64))
