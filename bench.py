@@ -38,6 +38,23 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def load_traffic(tag):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), or
+    None when the kernel source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.md")
+    if not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_2502_13245_amd", "csrc", "rr_kernels.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+            if rec.get("kernel_source_sha1") == sha:
+                return rec["bytes_per_launch"]
+    return None
+
+
 def recall_of(found_off, found_ids, truth_keys, n, truth_total):
     """Range recall (average precision of the paper): sum |K & K'| / sum |K|."""
     nq = len(found_off) - 1
@@ -196,26 +213,38 @@ def main():
     ms_step = wall / args.steps * 1e3
     qps = nq / (wall / args.steps)
 
-    # roofline of the dominant kernel (the beam kernel), HIP events on its stream
-    beam_ms, greedy_ms, total_ms = [], [], []
+    # roofline of the dominant kernel, HIP events recorded by the library on
+    # the stream the kernels run on
+    beam_ms, gk_ms, greedy_ms, total_ms = [], [], [], []
     st = None
     for _ in range(5):
         res = run(A["mode"], A["beam"], timing=True, **A["kw"])
         st = res.batch
         beam_ms.append(st["beam_ms"])
+        gk_ms.append(st["greedy_kernel_ms"])
         greedy_ms.append(st["greedy_ms"])
         total_ms.append(st["total_ms"])
-    beam_avg = float(np.mean(beam_ms))
-    achieved = st["bytes_beam"] / (beam_avg * 1e-3) / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel="k_beam", bytes_per_launch=int(st["bytes_beam"]),
-                    avg_ms=round(beam_avg, 4))
-    log(f"adaptive b={A['beam']}: {qps:,.0f} QPS, beam kernel {beam_avg:.3f} ms "
-        f"({achieved:.0f} GB/s), greedy {np.mean(greedy_ms):.3f} ms, call {np.mean(total_ms):.3f} ms; "
-        f"greedy levels {st['greedy_levels']}, items {st['greedy_items']}, tasks {st['expanded']}, "
-        f"evals {st['greedy_evals']}, beam visits {st['visits']}, beam evals {st['evals']}, "
-        f"cache overflow {st['cache_overflow']}")
+    traffic = load_traffic(f"u8-1M-d128_adaptive-b{A['beam']}") if n == 1_000_000 else None
+
+    def roof(kernel, nbytes, ms, tkey):
+        ach = nbytes / (ms * 1e-3) / 1e9
+        t = None
+        if traffic and tkey in traffic:
+            t = traffic[tkey]
+        return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=t, kernel=kernel,
+                    bytes_per_launch=int(nbytes), avg_ms=round(ms, 4))
+
+    r_beam = roof("k_beam", st["bytes_beam"], float(np.mean(beam_ms)), "k_beam<0, 1, 8>")
+    r_greedy = (roof("k_greedy", st["bytes_greedy"], float(np.mean(gk_ms)), "k_greedy<0, 1, 8>")
+                if st["greedy_kernel_ms"] > 0 else None)
+    dominant = r_greedy if r_greedy and r_greedy["avg_ms"] > r_beam["avg_ms"] else r_beam
+    log(f"adaptive b={A['beam']}: {qps:,.0f} QPS; beam kernel {r_beam['avg_ms']:.3f} ms "
+        f"({r_beam['achieved']:.0f} GB/s), greedy kernel {np.mean(gk_ms):.3f} ms "
+        f"({r_greedy['achieved'] if r_greedy else 0:.0f} GB/s), greedy phase {np.mean(greedy_ms):.3f} ms, "
+        f"call {np.mean(total_ms):.3f} ms; greedy levels {st['greedy_levels']}, items {st['greedy_items']}, "
+        f"tasks {st['expanded']}, evals {st['greedy_evals']}, beam visits {st['visits']}, "
+        f"beam evals {st['evals']}, cache overflow {st['cache_overflow']}")
 
     # CPU oracle on the host cores, bounded sample
     cpu = None
@@ -256,7 +285,9 @@ def main():
                    "radius": radius, "beam": A["beam"], "es_visit_limit": 10,
                    "es_radius": radius, "recall": round(A["recall"], 4),
                    "result_hist_0_10_1e2_1e3_1e4_1e5": hist, "max_results": int(counts.max())},
-        "roofline": roofline,
+        "roofline": dominant,
+        "roofline_beam": r_beam,
+        "roofline_greedy": r_greedy,
         "cpu_baseline": cpu,
         "plain_qps_at_0.9": round(plain["qps"], 1) if plain else None,
         "plain_beam_at_0.9": plain["beam"] if plain else None,
@@ -268,7 +299,8 @@ def main():
                     "tops": round(scan_tops, 1), "peak_tops": INT8_PEAK_TOPS,
                     "frac": round(scan_tops / INT8_PEAK_TOPS, 4)},
         "graph_build_s": round(build_s, 1) if build_s else None,
-        "greedy": {"ms": round(float(np.mean(greedy_ms)), 4), "levels": st["greedy_levels"],
+        "greedy": {"phase_ms": round(float(np.mean(greedy_ms)), 4),
+                   "kernel_ms": round(float(np.mean(gk_ms)), 4), "levels": st["greedy_levels"],
                    "items": st["greedy_items"], "tasks": st["expanded"]},
         "curves": curves,
     }

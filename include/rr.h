@@ -132,6 +132,8 @@ typedef struct {
     double total_ms;           /* with timing: whole search call            */
     int64_t greedy_levels;     /* frontier levels run by the greedy phase   */
     int64_t greedy_items;      /* frontier items (in-ball points) processed */
+    int64_t bytes_greedy;      /* algorithmic bytes of the greedy phase     */
+    double greedy_kernel_ms;   /* with timing: greedy kernel alone          */
 } rr_batch_stats;
 
 const char *rr_last_error(void);

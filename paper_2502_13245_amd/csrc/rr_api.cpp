@@ -467,7 +467,9 @@ struct rr_results {
     DevIndex ix;
     bool stats_valid = true;
     bool timing = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr}; // start, after beam, after greedy, end
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr}; // start, before beam,
+                                                                   // after beam, after greedy phase,
+                                                                   // after greedy kernel
 };
 
 extern "C" void rr_results_free(rr_results *res) {
@@ -673,7 +675,7 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[1], s));
     HIP_TRY_R(launch_beam(ix->dev, nq, cfg, sb, cus, s));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[2], s));
-    if (greedy) HIP_TRY_R(launch_greedy(ix->dev, nq, cfg, sb, cus, s));
+    if (greedy) HIP_TRY_R(launch_greedy(ix->dev, nq, cfg, sb, cus, s, res->timing ? res->ev[4] : nullptr));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[3], s));
     HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
 #undef HIP_TRY_R
@@ -855,6 +857,10 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
         for (int64_t i = 0; i < res->nq; ++i)
             if (!st[i].expanded) beam_out += st[i].count;
         agg->bytes_beam = res->nq * row + agg->visits * 4ll * res->R + agg->evals * row + beam_out * 8ll;
+        // greedy phase: adjacency of every in-ball point it visits, rows of the
+        // points it evaluates, and its output pairs
+        agg->bytes_greedy = agg->greedy_visits * 4ll * res->R + agg->greedy_evals * row +
+                            (agg->total_results - beam_out) * 8ll;
         if (res->sb.level_cnt) {
             unsigned long long ctr[CTR_COUNT];
             HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
@@ -874,6 +880,10 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
             agg->greedy_ms = ms;
             HIP_TRY(hipEventElapsedTime(&ms, res->ev[0], res->ev[3]));
             agg->total_ms = ms;
+            if (res->sb.level_cnt && res->nq > 0) {
+                HIP_TRY(hipEventElapsedTime(&ms, res->ev[2], res->ev[4]));
+                agg->greedy_kernel_ms = ms;
+            }
         }
     }
     return RR_OK;

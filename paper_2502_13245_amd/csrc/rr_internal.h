@@ -120,7 +120,7 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
 hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                        int num_cus, hipStream_t s);
 hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
-                         int num_cus, hipStream_t s);
+                         int num_cus, hipStream_t s, hipEvent_t after_kernel = nullptr);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, const uint8_t *qpad,
                                int64_t nq, const int64_t *res_off, const int32_t *res_cnt,

@@ -250,14 +250,14 @@ template <int DTYPE, int CPL, int G> struct QueryRegs {
 // Evaluate the distances of candidates ci[0, k) (ids in LDS) and write them
 // to cd[0, k).  Row c is handled by lane group c % (64/G) in round c / (64/G).
 // All lanes of the wave must call this.
-template <int DTYPE, int CPL, int G>
+template <int DTYPE, int CPL, int G, int ROUNDS_IN_FLIGHT = 8>
 __device__ __forceinline__ void eval_rows(const DevIndex &ix, const QueryRegs<DTYPE, CPL, G> &qr,
                                           const uint32_t *ci, typename DistOf<DTYPE>::T *cd,
                                           int k) {
     using D = typename DistOf<DTYPE>::T;
     using Acc = typename DistOf<DTYPE>::Acc;
     constexpr int RPR = 64 / G;          // rows per round
-    constexpr int RB = CPL >= 8 ? 1 : 8 / CPL; // rounds issued together
+    constexpr int RB = CPL >= ROUNDS_IN_FLIGHT ? 1 : ROUNDS_IN_FLIGHT / CPL; // rounds issued together
     const int lane = lane_id();
     const int gl = lane & (G - 1);
     const int grp = lane / G;
@@ -1111,7 +1111,7 @@ static hipError_t run_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
 
 template <int DTYPE, int CPL, int G>
 static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBufs &sb,
-                             int num_cus, hipStream_t s) {
+                             int num_cus, hipStream_t s, hipEvent_t after_kernel) {
     using D = typename DistOf<DTYPE>::T;
     GreedyArgs a;
     a.ix = ix;
@@ -1127,6 +1127,10 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
     void *args[] = {&a};
     e = hipLaunchCooperativeKernel((const void *)kern, grid, block, args, 0, s);
     if (e != hipSuccess) return e;
+    if (after_kernel) {
+        e = hipEventRecord(after_kernel, s);
+        if (e != hipSuccess) return e;
+    }
     return launch_finalize(ix.dtype, sb, s);
 }
 
@@ -1149,12 +1153,12 @@ hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, Sea
 }
 
 hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
-                         int num_cus, hipStream_t s) {
+                         int num_cus, hipStream_t s, hipEvent_t after_kernel) {
     if (nq == 0) return hipSuccess;
     int32_t cpl = 0, g = 0;
     row_split(ix.row_bytes, &cpl, &g);
 #define X(DT, C, GG)                                                                          \
-    if (ix.dtype == DT && cpl == C && g == GG) return run_greedy<DT, C, GG>(ix, cfg, sb, num_cus, s);
+    if (ix.dtype == DT && cpl == C && g == GG) return run_greedy<DT, C, GG>(ix, cfg, sb, num_cus, s, after_kernel);
     RR_SPLITS(X, RR_U8)
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)

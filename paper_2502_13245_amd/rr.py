@@ -67,7 +67,8 @@ class BatchStats(C.Structure):
                  "rechecked", "es_fired", "expanded", "truncated", "cache_overflow",
                  "bytes_algorithmic", "bytes_beam")] + [
                 (k, C.c_double) for k in ("beam_ms", "greedy_ms", "total_ms")] + [
-                (k, C.c_int64) for k in ("greedy_levels", "greedy_items")]
+                (k, C.c_int64) for k in ("greedy_levels", "greedy_items", "bytes_greedy")] + [
+                ("greedy_kernel_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
