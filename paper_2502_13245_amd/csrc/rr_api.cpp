@@ -434,6 +434,8 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
     dv.row_bytes = rb;
     dv.row_bytes_bf16 = rb16;
     dv.base = (const uint8_t *)ix->d_base;
+    dv.base_exact = dv.base;
+    dv.row_bytes_exact = rb;
     dv.base_bf16 = (const uint8_t *)ix->d_bf16;
     dv.adj = (const int32_t *)ix->d_adj;
     dv.max_norm = maxn;
@@ -496,21 +498,21 @@ static int64_t next_pow2(int64_t x) {
     return p;
 }
 
-static rr_status make_results(const rr_index *ix, int64_t nq, const rr_search_params *sp,
-                              bool with_greedy, int64_t arena_cap, int64_t item_cap,
-                              int64_t hash_cap, const rr_allocator *alloc, void *stream,
-                              rr_results **out) {
+static rr_status make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
+                              const rr_search_params *sp, bool with_greedy, int64_t arena_cap,
+                              int64_t item_cap, int64_t hash_cap, int32_t qrow,
+                              const rr_allocator *alloc, void *stream, rr_results **out) {
     rr_results *res = new (std::nothrow) rr_results();
     if (!res) return fail(RR_ENOMEM, "host allocation failed");
     res->nq = nq;
     res->dtype = ix->dtype;
     res->precision = sp ? sp->precision : 0;
     res->R = ix->R;
-    res->row_bytes = ix->dev.row_bytes;
+    res->row_bytes = view.row_bytes;
     res->d = ix->d;
     res->es = esize(ix->dtype);
     res->stream = (hipStream_t)stream;
-    res->ix = ix->dev;
+    res->ix = view;
     if (alloc && alloc->alloc && alloc->free) {
         res->alloc.user = *alloc;
         res->alloc.has_user = true;
@@ -518,7 +520,7 @@ static rr_status make_results(const rr_index *ix, int64_t nq, const rr_search_pa
     res->alloc.stream = stream;
     const size_t dsz = ix->dtype == RR_F32 ? 8 : 4;
     Carver c;
-    size_t o_qpad = c.take<uint8_t>(nq * (int64_t)ix->dev.row_bytes);
+    size_t o_qpad = c.take<uint8_t>(nq * (int64_t)qrow);
     size_t o_qth = c.take<QThresh>(nq);
     size_t o_ctr = c.take<unsigned long long>(CTR_COUNT);
     size_t o_roff = c.take<int64_t>(nq);
@@ -529,12 +531,14 @@ static rr_status make_results(const rr_index *ix, int64_t nq, const rr_search_pa
     size_t o_off = c.take<int64_t>(nq + 1);
     size_t o_scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
     size_t o_tq = 0, o_tc = 0, o_te = 0, o_it = 0, o_ii = 0, o_idist = 0, o_lvl = 0, o_hash = 0,
-           o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0;
+           o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0, o_tr = 0, o_tx = 0;
     const int32_t max_levels = 4096;
     if (with_greedy) {
         o_tq = c.take<int32_t>(nq);
         o_tc = c.take<unsigned long long>(nq);
         o_te = c.take<unsigned long long>(nq);
+        o_tr = c.take<unsigned long long>(nq);
+        o_tx = c.take<int8_t>(nq);
         o_it = c.take<int32_t>(item_cap);
         o_ii = c.take<int32_t>(item_cap);
         o_idist = c.take<uint8_t>(item_cap * (int64_t)dsz);
@@ -568,6 +572,8 @@ static rr_status make_results(const rr_index *ix, int64_t nq, const rr_search_pa
         sb.task_q = (int32_t *)(b + o_tq);
         sb.task_cnt = (unsigned long long *)(b + o_tc);
         sb.task_evals = (unsigned long long *)(b + o_te);
+        sb.task_rechk = (unsigned long long *)(b + o_tr);
+        sb.task_expand = (int8_t *)(b + o_tx);
         sb.item_task = (int32_t *)(b + o_it);
         sb.item_id = (int32_t *)(b + o_ii);
         sb.item_dist = b + o_idist;
@@ -610,8 +616,10 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     if (!(sp->lambda >= 0.0)) return fail(RR_EINVAL, "lambda must be >= 0");
     if (sp->precision != RR_EXACT && sp->precision != RR_BF16_RECHECK)
         return fail(RR_EINVAL, "unknown precision %d", sp->precision);
-    if (sp->precision == RR_BF16_RECHECK)
-        return fail(RR_EINVAL, "bf16 precision is not available in this build");
+    if (sp->precision == RR_BF16_RECHECK && ix->dtype != RR_F32)
+        return fail(RR_EINVAL, "bf16 precision needs float32 data");
+    if (sp->precision == RR_BF16_RECHECK && !(sp->recheck_margin >= 0.0))
+        return fail(RR_EINVAL, "recheck_margin must be >= 0");
     if (ix->dev.dtype != ix->dtype) return fail(RR_ESTATE, "index state is inconsistent");
 
     SearchCfg cfg{};
@@ -637,7 +645,15 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     cfg.max_beam = sp->max_beam;
     cfg.margin = sp->recheck_margin;
 
-    const bool greedy = sp->mode == RR_ADAPTIVE;
+    // the bf16 pass sends every result list through the sort/emit stage
+    const bool approx = sp->precision == RR_BF16_RECHECK;
+    const bool greedy = sp->mode == RR_ADAPTIVE || approx;
+    DevIndex view = ix->dev;
+    if (approx) {
+        view.base = ix->dev.base_bf16;
+        view.row_bytes = ix->dev.row_bytes_bf16;
+    }
+    const int32_t qrow = approx ? 2 * view.row_bytes : view.row_bytes;
     int64_t gcap = 0, hash_cap = 0, item_cap = 0;
     if (greedy) {
         gcap = sp->result_capacity > 0 ? sp->result_capacity
@@ -647,7 +663,8 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     }
     const int64_t arena_cap = nq * (int64_t)sp->beam + gcap;
     rr_results *res = nullptr;
-    rr_status st = make_results(ix, nq, sp, greedy, arena_cap, item_cap, hash_cap, alloc, stream, &res);
+    rr_status st = make_results(ix, view, nq, sp, greedy, arena_cap, item_cap, hash_cap, qrow, alloc,
+                                stream, &res);
     if (st != RR_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     SearchBufs &sb = res->sb;
@@ -669,13 +686,13 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
         for (auto &e : res->ev) HIP_TRY_R(hipEventCreate(&e));
         HIP_TRY_R(hipEventRecord(res->ev[0], s));
     }
-    HIP_TRY_R(launch_prep_queries(ix->dev, queries_dev, nq, radius, radius_dev, cfg, sb, s));
+    HIP_TRY_R(launch_prep_queries(view, queries_dev, nq, radius, radius_dev, cfg, sb, s));
     HIP_TRY_R(launch_set_esr(sb.qth, nq, sp->es_radius, s));
     const int cus = device_cus();
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[1], s));
-    HIP_TRY_R(launch_beam(ix->dev, nq, cfg, sb, cus, s));
+    HIP_TRY_R(launch_beam(view, nq, cfg, sb, cus, s));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[2], s));
-    if (greedy) HIP_TRY_R(launch_greedy(ix->dev, nq, cfg, sb, cus, s, res->timing ? res->ev[4] : nullptr));
+    if (greedy) HIP_TRY_R(launch_greedy(view, nq, cfg, sb, cus, s, res->timing ? res->ev[4] : nullptr));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[3], s));
     HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
 #undef HIP_TRY_R
@@ -691,10 +708,13 @@ static rr_status brute_force_once(const rr_index *ix, const void *queries_dev, i
     rr_default_search_params(&sp);
     const int64_t item_cap = std::max<int64_t>(cap, 1);
     rr_results *res = nullptr;
-    rr_status st = make_results(ix, nq, &sp, true, item_cap, item_cap, 1024, alloc, stream, &res);
+    rr_status st = make_results(ix, ix->dev, nq, &sp, true, item_cap, item_cap, 1024,
+                                ix->dev.row_bytes, alloc, stream, &res);
     if (st != RR_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     SearchBufs &sb = res->sb;
+    sb.task_rechk = nullptr; // no greedy phase: every query is a plain result list
+    sb.task_expand = nullptr;
     SearchCfg cfg{};
 #define HIP_TRY_R(expr)                                                                       \
     do {                                                                                      \
@@ -836,7 +856,11 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
     if (agg) {
         std::memset(agg, 0, sizeof *agg);
         agg->nq = res->nq;
-        const int64_t row = (int64_t)res->d * res->es;
+        // the bf16 pass reads 2 bytes per coordinate while searching and the
+        // float32 row of every rechecked or returned point
+        const bool approx = res->precision == RR_BF16_RECHECK;
+        const int64_t row = (int64_t)res->d * (approx ? 2 : res->es);
+        const int64_t exact_row = approx ? (int64_t)res->d * 4 : 0;
         for (int64_t i = 0; i < res->nq; ++i) {
             const rr_query_stats &q = st[i];
             agg->total_results += q.count;
@@ -852,7 +876,8 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
         }
         // query + adjacency rows of visited points + rows of evaluated points + output
         agg->bytes_algorithmic = res->nq * row + (agg->visits + agg->greedy_visits) * 4ll * res->R +
-                                 (agg->evals + agg->greedy_evals) * row + agg->total_results * 8ll;
+                                 (agg->evals + agg->greedy_evals) * row + agg->total_results * 8ll +
+                                 (agg->rechecked + agg->total_results) * exact_row;
         int64_t beam_out = 0;
         for (int64_t i = 0; i < res->nq; ++i)
             if (!st[i].expanded) beam_out += st[i].count;

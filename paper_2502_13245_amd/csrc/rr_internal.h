@@ -40,7 +40,9 @@ struct DevIndex {
     int32_t entry = 0;
     int32_t row_bytes = 0;      // padded stride of `base`
     int32_t row_bytes_bf16 = 0; // padded stride of `base_bf16` (float data)
-    const uint8_t *base = nullptr;
+    const uint8_t *base = nullptr;      // rows the search reads (bf16 copy in the approximate pass)
+    const uint8_t *base_exact = nullptr; // float32/int rows for exact distances
+    int32_t row_bytes_exact = 0;
     const uint8_t *base_bf16 = nullptr;
     const int32_t *adj = nullptr;
     float max_norm = 0.f; // largest |x| (float data)
@@ -90,6 +92,8 @@ struct SearchBufs {
     int32_t *task_q = nullptr;    // [nq] query of each task
     unsigned long long *task_cnt = nullptr;   // [nq] results per task
     unsigned long long *task_evals = nullptr; // [nq]
+    unsigned long long *task_rechk = nullptr; // [nq] exact rechecks in the band
+    int8_t *task_expand = nullptr;            // [nq] 1: run Algorithm 2 from the seeds
     int32_t *item_task = nullptr; // [item_cap]
     int32_t *item_id = nullptr;
     void *item_dist = nullptr;

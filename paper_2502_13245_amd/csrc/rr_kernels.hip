@@ -167,10 +167,17 @@ __device__ __forceinline__ int lower_bound_key(const D *ad, const uint32_t *ai, 
 // distance of a row chunk against the query chunk held in registers
 // --------------------------------------------------------------------------
 
+// Internal data type of the approximate pass on float data: rows are the
+// bfloat16 copy, the query stays float32, squares accumulate in float32.
+constexpr int RR_BF16X = 3;
+
+// T: the search key; Acc: the accumulator; O: the distance that decides
+// membership and is reported (exact for every type).
 template <int DTYPE> struct DistOf;
-template <> struct DistOf<RR_U8> { using T = uint32_t; using Acc = int; };
-template <> struct DistOf<RR_I8> { using T = uint32_t; using Acc = int; };
-template <> struct DistOf<RR_F32> { using T = double; using Acc = double; };
+template <> struct DistOf<RR_U8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
+template <> struct DistOf<RR_I8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
+template <> struct DistOf<RR_F32> { using T = double; using Acc = double; using O = double; };
+template <> struct DistOf<RR_BF16X> { using T = float; using Acc = float; using O = double; };
 
 template <int DTYPE>
 __device__ __forceinline__ typename DistOf<DTYPE>::Acc chunk_part(uint4 p, uint4 q);
@@ -212,6 +219,46 @@ template <> __device__ __forceinline__ double chunk_part<RR_F32>(uint4 p, uint4 
     return a;
 }
 
+// bfloat16 row chunk (8 values) against 8 float32 query values: sum of
+// squared differences, float32 accumulation
+__device__ __forceinline__ float chunk_part_bf16(uint4 p, uint4 q0, uint4 q1) {
+    const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+    const uint32_t qa[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float lo = __uint_as_float(w[j] << 16);
+        const float hi = __uint_as_float(w[j] & 0xffff0000u);
+        const float t0 = lo - __uint_as_float(qa[2 * j]);
+        const float t1 = hi - __uint_as_float(qa[2 * j + 1]);
+        a = fmaf(t0, t0, a);
+        a = fmaf(t1, t1, a);
+    }
+    return a;
+}
+
+// exact distance of a float32 row for the recheck: FP64 sum of squared
+// differences over the zero-padded rows
+__device__ __forceinline__ double exact_dist_f32(const DevIndex &ix, uint32_t id,
+                                                 const uint8_t *qrow) {
+    const float4 *x = reinterpret_cast<const float4 *>(ix.base_exact + (size_t)id * ix.row_bytes_exact);
+    const float4 *q = reinterpret_cast<const float4 *>(qrow);
+    const int n4 = (ix.d + 3) / 4;
+    double a = 0.0;
+    for (int i = 0; i < n4; ++i) {
+        const float4 u = x[i], v = q[i];
+        double t = (double)u.x - (double)v.x;
+        a = fma(t, t, a);
+        t = (double)u.y - (double)v.y;
+        a = fma(t, t, a);
+        t = (double)u.z - (double)v.z;
+        a = fma(t, t, a);
+        t = (double)u.w - (double)v.w;
+        a = fma(t, t, a);
+    }
+    return a;
+}
+
 // |q|^2 part for integer data (float data needs none)
 template <int DTYPE> __device__ __forceinline__ int chunk_qq(uint4 q);
 template <> __device__ __forceinline__ int chunk_qq<RR_U8>(uint4 q) {
@@ -230,19 +277,24 @@ template <> __device__ __forceinline__ int chunk_qq<RR_I8>(uint4 q) {
 }
 
 // Query state held by each lane: its CPL chunks of the padded query row.
+// For the bfloat16 pass each 16-byte row chunk (8 values) pairs with 32
+// bytes of the float32 query, so a lane holds 2*CPL query chunks.
 template <int DTYPE, int CPL, int G> struct QueryRegs {
-    uint4 c[CPL];
+    static constexpr int QC = DTYPE == RR_BF16X ? 2 * CPL : CPL;
+    uint4 c[QC];
     int qq; // integer data: |q|^2
+    const uint8_t *row; // the padded query row (the recheck reads it)
 
     __device__ __forceinline__ void load(const uint8_t *qrow) {
         const int gl = lane_id() & (G - 1);
+        row = qrow;
         int s = 0;
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            c[k] = *reinterpret_cast<const uint4 *>(qrow + (size_t)(gl * CPL + k) * 16);
-            if constexpr (DTYPE != RR_F32) s += chunk_qq<DTYPE>(c[k]);
+        for (int k = 0; k < QC; ++k) {
+            c[k] = *reinterpret_cast<const uint4 *>(qrow + (size_t)(gl * QC + k) * 16);
+            if constexpr (DTYPE == RR_U8 || DTYPE == RR_I8) s += chunk_qq<DTYPE>(c[k]);
         }
-        if constexpr (DTYPE != RR_F32) qq = group_sum<G>(s);
+        if constexpr (DTYPE == RR_U8 || DTYPE == RR_I8) qq = group_sum<G>(s);
         else qq = 0;
     }
 };
@@ -275,18 +327,23 @@ __device__ __forceinline__ void eval_rows(const DevIndex &ix, const QueryRegs<DT
                     buf[rb][kk] = *reinterpret_cast<const uint4 *>(row + kk * 16);
             } else {
 #pragma unroll
-                for (int kk = 0; kk < CPL; ++kk) buf[rb][kk] = qr.c[kk];
+                for (int kk = 0; kk < CPL; ++kk) buf[rb][kk] = make_uint4(0u, 0u, 0u, 0u);
             }
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             Acc a = 0;
 #pragma unroll
-            for (int kk = 0; kk < CPL; ++kk) a += chunk_part<DTYPE>(buf[rb][kk], qr.c[kk]);
+            for (int kk = 0; kk < CPL; ++kk) {
+                if constexpr (DTYPE == RR_BF16X)
+                    a += chunk_part_bf16(buf[rb][kk], qr.c[2 * kk], qr.c[2 * kk + 1]);
+                else
+                    a += chunk_part<DTYPE>(buf[rb][kk], qr.c[kk]);
+            }
             a = group_sum<G>(a);
             const int c = (r0 + rb) * RPR + grp;
             if (gl == 0 && c < k) {
-                if constexpr (DTYPE == RR_F32) cd[c] = a;
+                if constexpr (DTYPE == RR_F32 || DTYPE == RR_BF16X) cd[c] = a;
                 else cd[c] = (uint32_t)(a + qr.qq);
             }
         }
@@ -302,12 +359,31 @@ template <> __device__ __forceinline__ bool in_range<uint32_t>(uint32_t d, const
 template <> __device__ __forceinline__ bool in_range<double>(double d, const QThresh &t) {
     return d <= t.r;
 }
+// approximate pass: used only by the early-stop test (membership is decided
+// on the exact distance)
+template <> __device__ __forceinline__ bool in_range<float>(float d, const QThresh &t) {
+    return d <= t.r_f;
+}
 template <typename D> __device__ __forceinline__ bool beyond_esr(D d, const QThresh &t);
 template <> __device__ __forceinline__ bool beyond_esr<uint32_t>(uint32_t d, const QThresh &t) {
     return (int64_t)d > t.esr_int;
 }
 template <> __device__ __forceinline__ bool beyond_esr<double>(double d, const QThresh &t) {
     return d > t.esr;
+}
+template <> __device__ __forceinline__ bool beyond_esr<float>(float d, const QThresh &t) {
+    return d > t.esr_f;
+}
+
+// the kernels' data type: the index dtype, or the bfloat16 pass
+static int kernel_dtype(const DevIndex &ix, const SearchCfg &cfg) {
+    return (ix.dtype == RR_F32 && cfg.precision == RR_BF16_RECHECK) ? RR_BF16X : ix.dtype;
+}
+
+// stride of the padded query rows: the bfloat16 pass keeps float32 queries
+// next to bf16 rows, so its query rows are twice the row stride
+template <int DTYPE> __device__ __forceinline__ size_t qrow_stride(const DevIndex &ix) {
+    return DTYPE == RR_BF16X ? 2 * (size_t)ix.row_bytes : (size_t)ix.row_bytes;
 }
 
 // --------------------------------------------------------------------------
@@ -320,9 +396,31 @@ __device__ int64_t floor_clamp(double r) {
     return (int64_t)floor(r);
 }
 
+// Band of the approximate pass (squared units).  With x^ the bfloat16 row
+// (per-coordinate relative rounding <= 2^-8, so |x^ - x| <= 2^-8 |x|) and
+// float32 accumulation of d squared differences (relative error <= gamma =
+// (d + 2) 2^-24), s > (1 + gamma)(r + delta)^2 with delta >= 2^-8 max|x|
+// proves |x - q| > r.  lo is the matching lower edge: below it the point is
+// certainly inside (reported as "rechecked" only in between).
+__device__ void band(double r2, double maxnorm, int d, double margin, float *lo, float *hi) {
+    if (!(r2 >= 0.0)) {
+        *lo = -1.f;
+        *hi = -1.f;
+        return;
+    }
+    const double r = sqrt(r2);
+    const double gamma = (double)(d + 2) * 0x1p-24;
+    const double delta = fmax(margin * r, 0x1p-8 * maxnorm * (1.0 + 1e-6));
+    const double h = (1.0 + gamma) * (r + delta) * (r + delta);
+    *hi = __double2float_ru(h);
+    const double l = r > delta ? (1.0 - gamma) * (r - delta) * (r - delta) : -1.0;
+    *lo = __double2float_rd(l);
+}
+
 __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int32_t row_out,
                                double radius, const double *radius_dev, double esr,
-                               QThresh *qth, uint8_t *qpad) {
+                               QThresh *qth, uint8_t *qpad, double maxnorm, int d,
+                               double margin, int approx) {
     const int64_t chunks = row_out / 16;
     const int64_t tot = nq * chunks;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
@@ -352,6 +450,7 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
             th.esr_f = (float)esr;
             th.lo = -1.f;
             th.hi = -1.f;
+            if (approx) band(r, maxnorm, d, margin, &th.lo, &th.hi);
             qth[qi] = th;
         }
     }
@@ -362,13 +461,16 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
                                hipStream_t s) {
     if (nq == 0) return hipSuccess;
     const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
-    const int64_t tot = nq * (ix.row_bytes / 16);
+    const int approx = kernel_dtype(ix, cfg) == RR_BF16X;
+    // the approximate pass pairs each bf16 row chunk with twice its bytes of
+    // float32 query
+    const int32_t row_out = approx ? 2 * ix.row_bytes : ix.row_bytes;
+    const int64_t tot = nq * (row_out / 16);
     int blocks = (int)((tot + 255) / 256);
     if (blocks > 65536) blocks = 65536;
-    (void)cfg;
     hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s,
-                       (const uint8_t *)queries, nq, ix.d * esz, ix.row_bytes, radius, radius_dev,
-                       0.0, sb.qth, sb.qpad);
+                       (const uint8_t *)queries, nq, ix.d * esz, row_out, radius, radius_dev,
+                       0.0, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, approx);
     return hipGetLastError();
 }
 
@@ -405,6 +507,7 @@ __host__ __device__ inline int32_t beam_lds_bytes(int32_t bcap, int32_t cs) {
 template <int DTYPE, int CPL, int G>
 __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
     using D = typename DistOf<DTYPE>::T;
+    using O = typename DistOf<DTYPE>::O;
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
@@ -434,7 +537,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
 
         const QThresh th = a.sb.qth[q];
         QueryRegs<DTYPE, CPL, G> qr;
-        qr.load(a.sb.qpad + (size_t)q * ix.row_bytes);
+        qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
 
         for (int i = lane; i < cs; i += 64) htab[i] = RR_EMPTY32;
         wave_sync();
@@ -556,32 +659,53 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             cursor = min(ipnew + 1, firstnew);
         }
 
-        // N = in-range prefix of the sorted beam
-        int cN = 0;
-        for (int base = 0; base < nB; base += 64) {
-            const int i = base + lane;
-            const bool inr = i < nB && in_range<D>(bd[i], th);
-            const int c = __popcll(__ballot(inr));
-            cN += c;
-            if (c < 64) break;
+        // N = the in-range points of B.  Exact types: an in-range prefix of
+        // the sorted beam.  Approximate pass: the prefix with s <= hi holds
+        // every possible member; each is re-decided on its exact distance.
+        int cN = 0, cH = 0, nband = 0;
+        if constexpr (DTYPE == RR_BF16X) {
+            for (int base = 0; base < nB; base += 64) {
+                const int i = base + lane;
+                const int c = __popcll(__ballot(i < nB && bd[i] <= th.hi));
+                cH += c;
+                if (c < 64) break;
+            }
+            for (int base = 0; base < cH; base += 64) {
+                const int i = base + lane;
+                bool inr = false;
+                if (i < cH) inr = exact_dist_f32(ix, bi[i] & RR_IDMASK, qr.row) <= th.r;
+                cN += __popcll(__ballot(inr));
+                nband += __popcll(__ballot(i < cH && bd[i] > th.lo));
+            }
+        } else {
+            for (int base = 0; base < nB; base += 64) {
+                const int i = base + lane;
+                const bool inr = i < nB && in_range<D>(bd[i], th);
+                const int c = __popcll(__ballot(inr));
+                cN += c;
+                if (c < 64) break;
+            }
         }
         // Algorithm 6: expand iff |N| >= lambda b; an empty N expands to nothing
         const bool expand_flag = cfg.mode == RR_ADAPTIVE && cN >= cfg.expand_thresh;
         const bool expand = expand_flag && cN > 0;
+        // results of the approximate pass are sorted by exact distance in the
+        // finalisation, so every non-empty query becomes a task there
+        const bool as_task = expand || (DTYPE == RR_BF16X && cN > 0);
         rr_query_stats st;
         st.visits = visits;
         st.evals = evals;
         st.greedy_visits = 0;
         st.greedy_evals = 0;
-        st.count = expand ? 0 : cN;
+        st.count = as_task ? 0 : cN;
         st.final_beam = b;
         st.es_fired = es_fired ? 1 : 0;
         st.expanded = expand_flag ? 1 : 0;
         st.truncated = 0;
         st.cache_overflow = __ballot(ovf) ? 1 : 0;
-        st.rechecked = 0;
+        st.rechecked = nband;
         st.rounds = 1;
-        if (!expand) {
+        if (!as_task) {
             int64_t off = 0;
             if (lane == 0 && cN > 0) off = (int64_t)atomicAdd(&a.sb.counters[CTR_ARENA], (unsigned long long)cN);
             off = __shfl(off, 0);
@@ -590,10 +714,10 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 st.count = 0;
                 if (lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 1ull);
             } else {
-                D *ad = (D *)a.sb.arena_dists;
+                O *ad = (O *)a.sb.arena_dists;
                 for (int i = lane; i < cN; i += 64) {
                     a.sb.arena_ids[off + i] = (int32_t)(bi[i] & RR_IDMASK);
-                    ad[off + i] = bd[i];
+                    ad[off + i] = (O)bd[i];
                 }
             }
             if (lane == 0) {
@@ -601,27 +725,60 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 a.sb.res_cnt[q] = st.count;
             }
         } else {
-            // become a task of the greedy phase: seeds N go to level 0
-            int64_t t = 0, off = 0;
-            if (lane == 0) {
-                t = (int64_t)atomicAdd(&a.sb.counters[CTR_TASKS], 1ull);
-                off = (int64_t)atomicAdd(&a.sb.level_cnt[0], (unsigned long long)cN);
-            }
+            // a task of the greedy phase: N goes to level 0 (expanded only if
+            // `expand`; otherwise it is just sorted and emitted)
+            int64_t t = 0;
+            if (lane == 0) t = (int64_t)atomicAdd(&a.sb.counters[CTR_TASKS], 1ull);
             t = __shfl(t, 0);
-            off = __shfl(off, 0);
             bool full = false;
-            if (off + cN > a.sb.item_cap) {
-                full = true;
+            int written = 0;
+            O *idist = (O *)a.sb.item_dist;
+            const int64_t hmask = a.sb.hash_cap - 1;
+            if constexpr (DTYPE == RR_BF16X) {
+                for (int base = 0; base < cH; base += 64) {
+                    const int i = base + lane;
+                    double dx = 0.0;
+                    bool inr = false;
+                    if (i < cH) {
+                        dx = exact_dist_f32(ix, bi[i] & RR_IDMASK, qr.row);
+                        inr = dx <= th.r;
+                    }
+                    const unsigned long long im = __ballot(inr);
+                    const int m = __popcll(im);
+                    if (m == 0) continue;
+                    int64_t off = 0;
+                    if (lane == 0) off = (int64_t)atomicAdd(&a.sb.level_cnt[0], (unsigned long long)m);
+                    off = __shfl(off, 0);
+                    const int64_t o = off + mbcnt(im);
+                    const bool wr = inr && o < a.sb.item_cap;
+                    if (wr) {
+                        const uint32_t id = bi[i] & RR_IDMASK;
+                        a.sb.item_task[o] = (int32_t)t;
+                        a.sb.item_id[o] = (int32_t)id;
+                        idist[o] = dx;
+                        if (expand) gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
+                    }
+                    const int mw = __popcll(__ballot(wr));
+                    written += mw;
+                    if (mw < m) full = true;
+                }
             } else {
-                D *idist = (D *)a.sb.item_dist;
-                const int64_t hmask = a.sb.hash_cap - 1;
+                int64_t off = 0;
+                if (lane == 0) off = (int64_t)atomicAdd(&a.sb.level_cnt[0], (unsigned long long)cN);
+                off = __shfl(off, 0);
                 for (int i = lane; i < cN; i += 64) {
+                    const int64_t o = off + i;
+                    if (o >= a.sb.item_cap) {
+                        full = true;
+                        continue;
+                    }
                     const uint32_t id = bi[i] & RR_IDMASK;
-                    a.sb.item_task[off + i] = (int32_t)t;
-                    a.sb.item_id[off + i] = (int32_t)id;
-                    idist[off + i] = bd[i];
+                    a.sb.item_task[o] = (int32_t)t;
+                    a.sb.item_id[o] = (int32_t)id;
+                    idist[o] = (O)bd[i];
                     gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
                 }
+                written = (int)max((int64_t)0, min((int64_t)cN, a.sb.item_cap - off));
             }
             if (__ballot(full)) {
                 st.truncated = 1;
@@ -629,8 +786,10 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             }
             if (lane == 0) {
                 a.sb.task_q[t] = (int32_t)q;
-                a.sb.task_cnt[t] = (unsigned long long)cN;
+                a.sb.task_cnt[t] = (unsigned long long)written;
                 a.sb.task_evals[t] = 0ull;
+                a.sb.task_rechk[t] = 0ull;
+                a.sb.task_expand[t] = expand ? 1 : 0;
                 a.sb.res_off[q] = 0;
                 a.sb.res_cnt[q] = 0;
             }
@@ -654,24 +813,24 @@ constexpr int GREEDY_WAVES = 4;     // waves per workgroup
 constexpr int GREEDY_CACHE = 1024;  // per-wave LDS cache of ids known to the global set
 constexpr int GREEDY_STAGE = 256;   // per-wave staged outputs before a global reservation
 
-template <typename D> struct GreedyLds {
+template <typename D, typename O> struct GreedyLds {
     uint32_t ci[GREEDY_WAVES][64];
     D cd[GREEDY_WAVES][64];
     uint32_t cache[GREEDY_WAVES][GREEDY_CACHE];
     uint32_t st_id[GREEDY_WAVES][GREEDY_STAGE];
     int32_t st_task[GREEDY_WAVES][GREEDY_STAGE];
-    D st_d[GREEDY_WAVES][GREEDY_STAGE];
+    O st_d[GREEDY_WAVES][GREEDY_STAGE];
     int32_t st_n[GREEDY_WAVES];
     unsigned long long wg_base;
 };
 
 // write a wave's staged outputs to items [dst, dst + n); every slot below
 // item_cap is written, so the next level never reads an unwritten item
-template <typename D>
-__device__ __forceinline__ void greedy_emit(GreedyLds<D> &L, int wid, int n, int64_t dst,
+template <typename D, typename O>
+__device__ __forceinline__ void greedy_emit(GreedyLds<D, O> &L, int wid, int n, int64_t dst,
                                             const SearchBufs &sb) {
     const int lane = lane_id();
-    D *idist = (D *)sb.item_dist;
+    O *idist = (O *)sb.item_dist;
     for (int i = lane; i < n; i += 64) {
         const int64_t o = dst + i;
         if (o < sb.item_cap) {
@@ -702,7 +861,8 @@ __device__ __forceinline__ void greedy_emit(GreedyLds<D> &L, int wid, int n, int
 template <int DTYPE, int CPL, int G>
 __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
     using D = typename DistOf<DTYPE>::T;
-    __shared__ GreedyLds<D> L;
+    using O = typename DistOf<DTYPE>::O;
+    __shared__ GreedyLds<D, O> L;
     cg::grid_group grid = cg::this_grid();
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
@@ -727,7 +887,8 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
         const int64_t per = (cnt + tw - 1) / tw;
         const int64_t i0 = gw * per, i1 = min(cnt, i0 + per);
         int32_t cur = -1;
-        unsigned long long run_evals = 0;
+        bool cur_expand = false;
+        unsigned long long run_evals = 0, run_rechk = 0;
         QThresh th{};
         QueryRegs<DTYPE, CPL, G> qr;
         const int64_t i_end = min(i1, a.sb.item_cap - base);
@@ -756,14 +917,18 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
             if (!item_ok(t, p)) continue; // never written
             if (t != cur) {
                 if (cur >= 0 && lane == 0 && run_evals) atomicAdd(&a.sb.task_evals[cur], run_evals);
+                if (cur >= 0 && lane == 0 && run_rechk) atomicAdd(&a.sb.task_rechk[cur], run_rechk);
                 run_evals = 0;
+                run_rechk = 0;
                 cur = t;
+                cur_expand = a.sb.task_expand[t] != 0;
                 const int32_t q = a.sb.task_q[t];
                 th = a.sb.qth[q];
-                qr.load(a.sb.qpad + (size_t)q * ix.row_bytes);
+                qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
                 for (int i = lane; i < GREEDY_CACHE; i += 64) cache[i] = RR_EMPTY32;
                 wave_sync();
             }
+            if (!cur_expand) continue; // results only: sorted and emitted later
             bool full = false, ovf = false;
             bool cand = false;
             if (f >= 0 && !seen_insert(cache, GREEDY_CACHE - 1, (uint32_t)f, ovf))
@@ -777,12 +942,26 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
             run_evals += (unsigned long long)k;
             eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
             bool inr = false;
-            D myd = dmax<D>();
+            O myd = dmax<O>();
             uint32_t myi = 0;
             if (lane < k) {
-                myd = cd[lane];
                 myi = ci[lane];
-                inr = in_range<D>(myd, th);
+                if constexpr (DTYPE == RR_BF16X) {
+                    // approximate distance above hi: provably outside the ball;
+                    // otherwise the exact distance decides
+                    const float sx = cd[lane];
+                    if (sx <= th.hi) {
+                        myd = exact_dist_f32(ix, myi, qr.row);
+                        inr = myd <= th.r;
+                    }
+                } else {
+                    myd = cd[lane];
+                    inr = in_range<D>(cd[lane], th);
+                }
+            }
+            if constexpr (DTYPE == RR_BF16X) {
+                const int nb = __popcll(__ballot(lane < k && cd[lane] > th.lo && cd[lane] <= th.hi));
+                run_rechk += (unsigned long long)nb;
             }
             const unsigned long long im = __ballot(inr);
             const int m = __popcll(im);
@@ -793,7 +972,7 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
                 unsigned long long o = 0;
                 if (lane == 0) o = atomicAdd(&a.sb.level_cnt[lvl + 1], (unsigned long long)sn);
                 o = __shfl(o, 0);
-                greedy_emit<D>(L, wid, sn, next_base + (int64_t)o, a.sb);
+                greedy_emit<D, O>(L, wid, sn, next_base + (int64_t)o, a.sb);
                 wave_sync();
                 sn = 0;
             }
@@ -808,6 +987,7 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
             wave_sync();
         }
         if (cur >= 0 && lane == 0 && run_evals) atomicAdd(&a.sb.task_evals[cur], run_evals);
+        if (cur >= 0 && lane == 0 && run_rechk) atomicAdd(&a.sb.task_rechk[cur], run_rechk);
         // one reservation per workgroup for what the waves still hold
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -820,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
             int64_t off = (int64_t)L.wg_base;
             for (int w = 0; w < wid; ++w) off += L.st_n[w];
             const int sn = L.st_n[wid];
-            if (sn > 0) greedy_emit<D>(L, wid, sn, next_base + off, a.sb);
+            if (sn > 0) greedy_emit<D, O>(L, wid, sn, next_base + off, a.sb);
         }
         grid.sync();
         base = next_base;
@@ -1033,8 +1213,10 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
             sb.res_cnt[q] = ok ? (int32_t)n : 0;
             rr_query_stats *st = &sb.stats[q];
             st->count = ok ? (int32_t)n : 0;
-            st->greedy_visits = (int32_t)n;
+            const bool exp = sb.task_expand == nullptr || sb.task_expand[t] != 0;
+            st->greedy_visits = exp ? (int32_t)n : 0;
             st->greedy_evals = (int32_t)sb.task_evals[t];
+            if (sb.task_rechk) st->rechecked += (int32_t)sb.task_rechk[t];
             if (!ok) {
                 st->truncated = 1;
                 atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);
@@ -1143,11 +1325,13 @@ hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, Sea
     if (nq == 0) return hipSuccess;
     int32_t cpl = 0, g = 0;
     row_split(ix.row_bytes, &cpl, &g);
+    const int kd = kernel_dtype(ix, cfg);
 #define X(DT, C, GG)                                                                          \
-    if (ix.dtype == DT && cpl == C && g == GG) return run_beam<DT, C, GG>(ix, nq, cfg, sb, num_cus, s);
+    if (kd == DT && cpl == C && g == GG) return run_beam<DT, C, GG>(ix, nq, cfg, sb, num_cus, s);
     RR_SPLITS(X, RR_U8)
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
+    RR_SPLITS(X, RR_BF16X)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -1157,11 +1341,13 @@ hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, S
     if (nq == 0) return hipSuccess;
     int32_t cpl = 0, g = 0;
     row_split(ix.row_bytes, &cpl, &g);
+    const int kd = kernel_dtype(ix, cfg);
 #define X(DT, C, GG)                                                                          \
-    if (ix.dtype == DT && cpl == C && g == GG) return run_greedy<DT, C, GG>(ix, cfg, sb, num_cus, s, after_kernel);
+    if (kd == DT && cpl == C && g == GG) return run_greedy<DT, C, GG>(ix, cfg, sb, num_cus, s, after_kernel);
     RR_SPLITS(X, RR_U8)
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
+    RR_SPLITS(X, RR_BF16X)
 #undef X
     return hipErrorInvalidValue;
 }

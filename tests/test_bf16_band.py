@@ -1,0 +1,56 @@
+"""The approximate pass's band (bf16 rows, float32 accumulation) against an
+emulation of that arithmetic on the CPU: a point inside the radius must
+never compute above the band's upper edge, whatever the summation order."""
+import numpy as np
+
+
+def bf16_round(x):
+    """float32 -> bfloat16 -> float32 with round-to-nearest-even."""
+    u = x.astype(np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def approx_sq(xb, q, rng):
+    """float32 sum of squared differences in a random order (FMA emulated by
+    rounding each product-sum once)."""
+    order = rng.permutation(len(q))
+    acc = np.float32(0)
+    for i in order:
+        t = np.float32(xb[i] - q[i])
+        acc = np.float32(np.float64(t) * np.float64(t) + np.float64(acc))
+    return acc
+
+
+def band_hi(r2, maxnorm, d, margin):
+    r = np.sqrt(r2)
+    gamma = (d + 2) * 2.0 ** -24
+    delta = max(margin * r, 2.0 ** -8 * maxnorm * (1 + 1e-6))
+    return (1 + gamma) * (r + delta) ** 2
+
+
+def test_band_never_rejects_an_inside_point():
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for d in (8, 96, 768):
+        for _ in range(300):
+            q = rng.standard_normal(d).astype(np.float32)
+            q /= np.linalg.norm(q)
+            x = (q + rng.standard_normal(d).astype(np.float32) * rng.uniform(0.001, 0.2)).astype(np.float32)
+            x /= np.linalg.norm(x)
+            d64 = float(((x.astype(np.float64) - q) ** 2).sum())
+            s = float(approx_sq(bf16_round(x), q, rng))
+            # radius exactly at the point: the hardest case for the upper edge
+            hi = band_hi(d64, 1.0, d, margin=0.0)
+            assert s <= hi, (d, s, hi, d64)
+            worst = max(worst, (s - d64) / max(hi - d64, 1e-30))
+    assert worst < 1.0
+
+
+def test_bf16_rounding_matches_definition():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: round to even gives 1
+    assert bf16_round(np.array([1 + 2 ** -8], np.float32))[0] == 1.0
+    assert bf16_round(np.array([1 + 3 * 2 ** -8], np.float32))[0] == 1 + 2 ** -6
+    x = np.random.default_rng(1).standard_normal(1000).astype(np.float32)
+    assert np.all(np.abs(bf16_round(x) - x) <= 2 ** -8 * np.abs(x))

@@ -179,3 +179,34 @@ def test_random_graph_large(rr):
         g = rr.range_search(ix, q, r, mode=mode, beam=b)
         o = oracle.range_search(w.base, adj, 0, w.queries, r, mode=om, beam=b)
         compare_exact(g, o, label=f"random {mode}")
+
+
+@pytest.mark.parametrize("mode,om", [("plain", oracle.PLAIN), ("adaptive", oracle.ADAPTIVE)])
+def test_bf16_recheck_sound_exact_and_close(rr, mode, om):
+    """bf16 first pass + exact recheck: every returned point is inside the
+    ball by the FP64 oracle's distance, reported distances are that exact
+    distance, lists are ordered by (distance, id), and recall stays close to
+    the exact float path."""
+    w = synth.gaussian_mixture_unit(8000, 400, 96, 40, 0.3 / np.sqrt(96), 14, spread=0.3)
+    adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, synth.permutation(8000, 4))
+    r = oracle.percentile_radius(w.base, w.queries, 0.002)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    flush_print(f"bf16 {mode}")
+    g = rr.range_search(ix, q, r, mode=mode, beam=24, precision=rr.BF16_RECHECK)
+    e = rr.range_search(ix, q, r, mode=mode, beam=24)
+    bf = oracle.brute_force(w.base, w.queries, r)
+    off, ids, d = g.numpy()
+    D = oracle.pair_dists(w.base, w.queries)
+    for qi in range(len(w.queries)):
+        gi, gd = ids[off[qi]:off[qi + 1]], d[off[qi]:off[qi + 1]].astype(np.float64)
+        assert np.all(D[qi, gi] <= r), f"q{qi}: point outside the ball"
+        np.testing.assert_allclose(gd, D[qi, gi], rtol=1e-6, atol=1e-12)
+        keys = list(zip(gd.tolist(), gi.tolist()))
+        assert keys == sorted(keys)
+    assert g.stats["truncated"].sum() == 0
+    rec_b = oracle.range_recall(bf, oracle.Result(off, ids, d, None))
+    eo, ei, ed = e.numpy()
+    rec_e = oracle.range_recall(bf, oracle.Result(eo, ei, ed, None))
+    flush_print(f"  recall bf16 {rec_b:.4f} exact {rec_e:.4f}, rechecked {g.stats['rechecked'].sum()}")
+    assert rec_b >= rec_e - 0.02
