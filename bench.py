@@ -142,7 +142,8 @@ def main():
     scan_tops = 2.0 * nq * n * d / (nn_ms * 1e-3) / 1e12
     log(f"radius {radius:.0f} (nn scan {nn_ms:.2f} ms, {scan_tops:.0f} TOP/s int8 MFMA)")
     t0 = time.time()
-    truth = rr.brute_force(ix, q, radius)
+    truth_h = rr.brute_force_async(ix, q, radius)
+    truth = truth_h.fetch(False)
     toff, tids, _ = truth.numpy()
     counts = np.diff(toff)
     truth_total = int(toff[-1])
@@ -196,7 +197,13 @@ def main():
                     break
     if "adaptive" not in best:
         raise SystemExit("adaptive search did not reach the recall target")
-    A = best["adaptive"]
+    # the library's autotuner picks the adaptive setting: beam for the target,
+    # then the beam kernel's shape
+    sp, tune = rr.autotune(ix, q, radius, truth_h, target=args.target, reps=5, mode="adaptive",
+                           **es_kw)
+    log(f"autotune: {tune}")
+    A = dict(mode="adaptive", beam=sp.beam, recall=tune["recall"],
+             kw=dict(es_kw, waves_per_group=sp.waves_per_group, cache_slots=sp.cache_slots))
     if args.choice:
         json.dump(dict(radius=radius, mode=A["mode"], beam=A["beam"], kw=A["kw"]),
                   open(args.choice, "w"))
@@ -289,6 +296,7 @@ def main():
         "roofline_beam": r_beam,
         "roofline_greedy": r_greedy,
         "cpu_baseline": cpu,
+        "autotune": tune,
         "plain_qps_at_0.9": round(plain["qps"], 1) if plain else None,
         "plain_beam_at_0.9": plain["beam"] if plain else None,
         "es_qps_at_0.9": round(best["es"]["qps"], 1) if "es" in best else None,

@@ -204,6 +204,32 @@ rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t n
 rr_status rr_nn_dist(const rr_index *idx, const void *queries_dev, int64_t nq,
                      double *nn_dev, void *stream);
 
+/* ---------------- autotuning (batched search) ---------------- */
+
+typedef struct {
+    int32_t tried;        /* settings timed                                  */
+    int32_t beam;         /* chosen beam width                               */
+    int32_t waves_per_group;
+    int32_t cache_slots;
+    double ms;            /* median time of one search call with the choice  */
+    double recall;        /* range recall of the choice against `truth`      */
+    int32_t met_target;   /* 1 if recall >= target was reached                */
+} rr_tune_report;
+
+/* Pick the search parameters of a workload.  `truth` is an exact result of
+ * the same queries and radii (rr_brute_force).  Keeps mode, early-stop and
+ * precision fields of *inout and writes beam, waves_per_group and
+ * cache_slots: first the fastest beam (from a fixed ladder) whose range
+ * recall (sum |K & K'| / sum |K|, Definition 2.2) is >= target, then the
+ * fastest kernel shape for that beam (shapes never change results).  Each
+ * setting is timed as the median of `reps` calls with HIP events on
+ * `stream`.  If no beam reaches the target the highest-recall one is kept
+ * and met_target = 0.  Synchronizes.  Errors: those of rr_range_search. */
+rr_status rr_autotune(const rr_index *idx, const void *queries_dev, int64_t nq, double radius,
+                      const double *radius_dev, const rr_results *truth, double target_recall,
+                      int32_t reps, rr_search_params *inout, rr_tune_report *report,
+                      const rr_allocator *alloc, void *stream);
+
 /* ---------------- results ---------------- */
 
 /* Total number of results (synchronizes with the stream of the search). */

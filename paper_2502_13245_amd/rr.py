@@ -74,6 +74,15 @@ class BatchStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("tried", C.c_int32), ("beam", C.c_int32), ("waves_per_group", C.c_int32),
+                ("cache_slots", C.c_int32), ("ms", C.c_double), ("recall", C.c_double),
+                ("met_target", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
@@ -111,6 +120,9 @@ SIGNATURES = {
     "rr_results_copy": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "rr_results_stats": (C.c_int, [_VP, C.POINTER(QueryStats), C.POINTER(BatchStats)]),
     "rr_results_free": (None, [_VP]),
+    "rr_autotune": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, _VP, C.c_double, _I32,
+                              C.POINTER(SearchParams), C.POINTER(TuneReport),
+                              C.POINTER(Allocator), _VP]),
 }
 
 _lib = None
@@ -387,16 +399,35 @@ def range_search(index: Index, queries, radius, params: SearchParams | None = No
     return range_search_async(index, queries, radius, params, stream, **kw).fetch(with_stats, stream)
 
 
-def brute_force(index: Index, queries, radius, stream=None) -> Results:
-    """Exact range search by a dense scan (ground truth)."""
+def brute_force_async(index: Index, queries, radius, stream=None) -> PendingResults:
+    """Exact range search by a dense scan (ground truth), as a result handle."""
     q = queries.contiguous()
     nq = q.shape[0]
     r0, rdev, keep = _radius_args(radius, nq, q.device)
     out = C.c_void_p()
     _check(lib().rr_brute_force(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev,
                                 index._alloc.ref(), _stream_handle(stream), C.byref(out)))
-    return PendingResults(out.value, nq, index.info()["dtype"], index._alloc, (q, keep)).fetch(
-        False, stream)
+    return PendingResults(out.value, nq, index.info()["dtype"], index._alloc, (q, keep))
+
+
+def brute_force(index: Index, queries, radius, stream=None) -> Results:
+    """Exact range search by a dense scan (ground truth)."""
+    return brute_force_async(index, queries, radius, stream).fetch(False, stream)
+
+
+def autotune(index: Index, queries, radius, truth: PendingResults, target=0.9, reps=3,
+             params: SearchParams | None = None, stream=None, **kw):
+    """rr_autotune: beam width for the recall target, then kernel shape.
+    Returns (SearchParams, report dict)."""
+    sp = params if params is not None else search_params(**kw)
+    q = queries.contiguous()
+    nq = q.shape[0]
+    r0, rdev, keep = _radius_args(radius, nq, q.device)
+    rep = TuneReport()
+    _check(lib().rr_autotune(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev, truth._h,
+                             float(target), int(reps), C.byref(sp), C.byref(rep),
+                             index._alloc.ref(), _stream_handle(stream)))
+    return sp, rep.as_dict()
 
 
 def nn_dist(index: Index, queries, stream=None):

@@ -210,3 +210,39 @@ def test_bf16_recheck_sound_exact_and_close(rr, mode, om):
     rec_e = oracle.range_recall(bf, oracle.Result(eo, ei, ed, None))
     flush_print(f"  recall bf16 {rec_b:.4f} exact {rec_e:.4f}, rechecked {g.stats['rechecked'].sum()}")
     assert rec_b >= rec_e - 0.02
+
+
+@pytest.fixture(scope="module")
+def nav_u8(rr):
+    """20,000 x 128 uint8 base with low intrinsic dimension (navigable),
+    500 queries, radius with 75% of queries empty."""
+    w = synth.latent_mixture_u8(20000, 500, 128, 100, 25.0, 5)
+    adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, synth.permutation(20000, 5))
+    r = oracle.empty_fraction_radius(w.base, w.queries, 0.25)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    return dict(w=w, adj=adj, entry=entry, r=r, ix=ix, q=q)
+
+
+def test_autotune_meets_target_and_keeps_results(rr, nav_u8):
+    """rr_autotune picks a beam meeting the recall target and a kernel shape;
+    the tuned setting gives the same results as the untuned one at that beam,
+    and the recall it reports is the oracle's recall of those results."""
+    flush_print("autotune")
+    ctx = nav_u8
+    es = dict(es_enable=True, es_visit_limit=10, es_radius=ctx["r"])
+    truth = rr.brute_force_async(ctx["ix"], ctx["q"], ctx["r"])
+    sp, rep = rr.autotune(ctx["ix"], ctx["q"], ctx["r"], truth, target=0.85, reps=2,
+                          mode="adaptive", **es)
+    flush_print(f"  {rep}")
+    assert rep["met_target"] == 1 and rep["recall"] >= 0.85
+    assert sp.beam == rep["beam"] and rep["waves_per_group"] >= 1 and rep["cache_slots"] >= 512
+    tuned = rr.range_search(ctx["ix"], ctx["q"], ctx["r"], params=sp)
+    ref = rr.range_search(ctx["ix"], ctx["q"], ctx["r"], mode="adaptive", beam=sp.beam, **es)
+    for x, y in zip(tuned.numpy(), ref.numpy()):
+        np.testing.assert_array_equal(x, y)
+    o = oracle.range_search(ctx["w"].base, ctx["adj"], ctx["entry"], ctx["w"].queries, ctx["r"],
+                            mode=oracle.ADAPTIVE, beam=sp.beam, **es)
+    compare_exact(tuned, o, label="tuned")
+    bf = oracle.brute_force(ctx["w"].base, ctx["w"].queries, ctx["r"])
+    assert abs(oracle.range_recall(bf, o) - rep["recall"]) < 1e-9
