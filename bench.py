@@ -64,6 +64,62 @@ def recall_of(found_off, found_ids, truth_keys, n, truth_total):
     return float(hit) / truth_total if truth_total else float("nan")
 
 
+def serve_leg(rr, ix, w, nn_sorted, sp, args):
+    """Open-loop serving run per offered rate: arrival times from a Poisson
+    process, queries cycled from the query set, each request's radius drawn
+    from three levels (the radii at which 80%, 75% and 70% of the queries
+    have no result).  Latency = completion time (results on the host) minus
+    scheduled arrival time, so submitter lag counts against the server."""
+    if args.serve_seconds <= 0:
+        return None
+    nq = len(w.queries)
+    levels = [float(nn_sorted[math.ceil(f * nq) - 1]) for f in (0.20, 0.25, 0.30)]
+    rng = np.random.default_rng(7)
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    out = []
+    for rate in rates:
+        m = max(1, int(rate * args.serve_seconds))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=m)) + 0.01
+        qidx = rng.integers(0, nq, size=m)
+        radii = np.asarray(levels)[rng.integers(0, 3, size=m)]
+        qs = np.ascontiguousarray(w.queries[qidx])
+        with rr.Server(ix, sp, slots=args.serve_slots, step_budget=args.serve_budget) as srv:
+            t_base = srv.clock()
+            arr = arrivals + t_base
+            i = 0
+            while i < m:
+                now = srv.clock()
+                while i < m and arr[i] <= now:
+                    if not srv.submit(qs[i], radii[i], i, float(arr[i])):
+                        break
+                    i += 1
+                if i < m:
+                    wait = arr[i] - srv.clock()
+                    if wait > 2e-4:
+                        time.sleep(min(wait, 2e-3) - 1e-4)
+            srv.drain(timeout=120.0)
+            comps = srv.poll(m + 16)
+            info = srv.info()
+        lat = np.array([c.t_done - c.t_arrival for c in comps]) * 1e3
+        qwait = np.array([c.t_admit - c.t_arrival for c in comps]) * 1e3
+        span = max(c.t_done for c in comps) - (arr[0])
+        ticks = np.array([c.ticks for c in comps])
+        trunc = int(sum(c.truncated for c in comps))
+        rec = dict(offered_qps=rate, requests=m, achieved_qps=round(m / span, 1),
+                   p50_ms=round(float(np.percentile(lat, 50)), 3),
+                   p99_ms=round(float(np.percentile(lat, 99)), 3),
+                   mean_ms=round(float(lat.mean()), 3),
+                   queue_p99_ms=round(float(np.percentile(qwait, 99)), 3),
+                   mean_ticks=round(float(ticks.mean()), 2), server_ticks=info["ticks"],
+                   max_resident=info["max_resident"], truncated=trunc)
+        log(f"serve {rate:>8,.0f} QPS offered: achieved {rec['achieved_qps']:,.0f}, "
+            f"p50 {rec['p50_ms']:.3f} ms, p99 {rec['p99_ms']:.3f} ms, mean ticks "
+            f"{rec['mean_ticks']}, server ticks {info['ticks']}, max resident {info['max_resident']}")
+        out.append(rec)
+    return dict(slots=args.serve_slots, step_budget=args.serve_budget, radius_levels=levels,
+                mode="adaptive", beam=sp.beam, rates=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +138,11 @@ def main():
                     help="profiling mode: skip sweeps, run the setting from --choice --steps times")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run a device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="arrival window per offered rate of the serving run (0: skip)")
+    ap.add_argument("--serve-rates", default="2000,10000,50000")
+    ap.add_argument("--serve-slots", type=int, default=1024)
+    ap.add_argument("--serve-budget", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; this build has no multi-GPU path (asked for {args.gpus})",
@@ -253,6 +314,10 @@ def main():
         f"tasks {st['expanded']}, evals {st['greedy_evals']}, beam visits {st['visits']}, "
         f"beam evals {st['evals']}, cache overflow {st['cache_overflow']}")
 
+    # serving: Poisson arrivals, each request with its own radius, continuous
+    # batching over resident slots (the library's serving loop)
+    serving = serve_leg(rr, ix, w, nn_sorted, sp, args)
+
     # CPU oracle on the host cores, bounded sample
     cpu = None
     if not args.no_cpu:
@@ -301,7 +366,9 @@ def main():
         "plain_beam_at_0.9": plain["beam"] if plain else None,
         "es_qps_at_0.9": round(best["es"]["qps"], 1) if "es" in best else None,
         "adaptive_vs_plain": round(qps / plain["qps"], 2) if plain else None,
-        "p99_latency_ms": None,
+        "p50_latency_ms": serving["rates"][-1]["p50_ms"] if serving else None,
+        "p99_latency_ms": serving["rates"][-1]["p99_ms"] if serving else None,
+        "serving": serving,
         "batch_latency_ms": round(ms_step, 4),
         "gt_scan": {"kernel": "k_scan_int (MFMA i32_16x16x64_i8)", "ms": round(nn_ms, 3),
                     "tops": round(scan_tops, 1), "peak_tops": INT8_PEAK_TOPS,

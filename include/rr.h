@@ -38,7 +38,8 @@ typedef enum {
     RR_ENOMEM = 2, /* host or device allocation failed (allocator returned NULL) */
     RR_EHIP = 3,   /* a HIP runtime call failed; message has hipGetErrorString */
     RR_EIO = 4,    /* file I/O or format error */
-    RR_ESTATE = 5  /* call not valid in the object's state (e.g. not uploaded) */
+    RR_ESTATE = 5, /* call not valid in the object's state (e.g. not uploaded) */
+    RR_EBUSY = 6   /* the server's request queue is full; submit again later */
 } rr_status;
 
 typedef enum { RR_U8 = 0, RR_I8 = 1, RR_F32 = 2 } rr_dtype;
@@ -229,6 +230,74 @@ rr_status rr_autotune(const rr_index *idx, const void *queries_dev, int64_t nq, 
                       const double *radius_dev, const rr_results *truth, double target_recall,
                       int32_t reps, rr_search_params *inout, rr_tune_report *report,
                       const rr_allocator *alloc, void *stream);
+
+/* ---------------- serving: continuous batching ---------------- */
+
+/* A server keeps `slots` queries resident on the device.  A host thread runs
+ * ticks: it admits queued requests into free slots (copying their vectors
+ * and radii to the device), runs the beam kernel over every resident query
+ * with at most `step_budget` visits each (the beam state stays in device
+ * memory between ticks), runs the greedy phase and sort for the queries
+ * whose beam finished, and copies finished results back, freeing their
+ * slots for the next tick.  Requests that arrive while others are on the
+ * device join at the next tick.  A query's result does not depend on which
+ * other queries share its ticks (the search is exact per query).
+ * Footprint per slot: the padded query row, 8 bytes x beam of beam state,
+ * beam result entries; greedy results of one tick share result_capacity. */
+typedef struct rr_server rr_server;
+
+typedef struct {
+    int32_t slots;           /* resident queries (>= 1)                       */
+    int32_t step_budget;     /* beam visits per query per tick (0: no limit)  */
+    int64_t result_capacity; /* greedy-phase results per tick (0: auto)       */
+    int32_t max_pending;     /* queued requests before submit returns EBUSY   */
+} rr_server_config;
+
+typedef struct {
+    uint64_t tag;
+    int64_t count;     /* results (fetch them with rr_server_result)     */
+    int32_t truncated; /* a capacity was reached; the result is partial  */
+    int32_t ticks;     /* ticks the query spent resident                 */
+    double t_arrival;  /* seconds on the server clock                    */
+    double t_admit;
+    double t_done;     /* results are on the host                        */
+    rr_query_stats stats;
+} rr_completion;
+
+typedef struct {
+    int64_t ticks, submitted, admitted, completed, pending, resident, max_resident;
+    double busy_s; /* host time spent in ticks */
+} rr_server_info;
+
+/* The server keeps a pointer to the index (which must outlive it), copies
+ * the parameters, and allocates all device memory now.  Errors: those of
+ * rr_range_search, RR_EINVAL for a bad config. */
+rr_status rr_server_create(const rr_index *idx, const rr_search_params *sp,
+                           const rr_server_config *cfg, const rr_allocator *alloc,
+                           rr_server **out);
+/* Seconds since the server was created (the clock of every timestamp). */
+double rr_server_clock(const rr_server *srv);
+/* Queue one query (d values of the index dtype, host memory, copied now)
+ * with its squared radius.  t_arrival < 0 stamps the current time; a
+ * caller replaying a schedule passes the scheduled time instead.  `tag`
+ * identifies the request and must be unique among unfetched results.
+ * Errors: RR_EBUSY (queue full), RR_EINVAL, RR_ESTATE (server failed). */
+rr_status rr_server_submit(rr_server *srv, const void *query_host, double radius, uint64_t tag,
+                           double t_arrival);
+/* Move up to `max` completion records out (non-blocking). */
+rr_status rr_server_poll(rr_server *srv, rr_completion *out, int32_t max, int32_t *n);
+/* Copy a finished request's ids and distances (int32 for integer data,
+ * float32 for float data; ordered by (distance, id)) and release them.  If
+ * `capacity` is too small nothing is copied, *count is set and RR_ENOMEM is
+ * returned.  RR_EINVAL if the tag is unknown or not finished. */
+rr_status rr_server_result(rr_server *srv, uint64_t tag, int32_t *ids_host, void *dists_host,
+                           int64_t capacity, int64_t *count);
+/* Block until every submitted request has completed (or timeout_s passes:
+ * RR_EBUSY). */
+rr_status rr_server_drain(rr_server *srv, double timeout_s);
+rr_status rr_server_info_get(const rr_server *srv, rr_server_info *info);
+/* Stops the thread after the requests already submitted and frees all. */
+void rr_server_destroy(rr_server *srv);
 
 /* ---------------- results ---------------- */
 

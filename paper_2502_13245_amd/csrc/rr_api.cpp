@@ -44,6 +44,16 @@ static rr_status fail(rr_status st, const char *fmt, ...) {
     return st;
 }
 
+rr_status rr::set_error(rr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
@@ -108,7 +118,7 @@ void Allocator::release(void *p) {
     else (void)hipFree(p);
 }
 
-static int device_cus() {
+int device_cus() {
     static std::mutex mu;
     static int cache[64] = {0};
     int dev = 0;
@@ -129,21 +139,7 @@ static int device_cus() {
 // index
 // --------------------------------------------------------------------------
 
-struct rr_index {
-    int64_t n = 0;
-    int32_t d = 0;
-    int32_t dtype = 0;
-    int32_t R = 0;
-    int32_t entry = 0;
-    std::vector<uint8_t> base; // n x d x esize, unpadded
-    std::vector<int32_t> adj;  // n x R
-    // device
-    bool on_device = false;
-    int device = -1;
-    rr::Allocator alloc;
-    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr;
-    DevIndex dev;
-};
+
 
 static int esize(int dtype) { return dtype == RR_F32 ? 4 : 1; }
 
@@ -452,28 +448,6 @@ extern "C" void rr_index_free(rr_index *ix) {
 // results
 // --------------------------------------------------------------------------
 
-struct rr_results {
-    int64_t nq = 0;
-    int32_t dtype = 0;
-    int32_t precision = 0;
-    int32_t R = 0;
-    int32_t row_bytes = 0;
-    int32_t d = 0;
-    int32_t es = 1;
-    hipStream_t stream = nullptr;
-    rr::Allocator alloc;
-    void *block = nullptr; // one allocation carved into the buffers below
-    SearchBufs sb;
-    int64_t *offsets = nullptr; // [nq + 1] scanned counts
-    void *scan_tmp = nullptr;
-    DevIndex ix;
-    bool stats_valid = true;
-    bool timing = false;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr}; // start, before beam,
-                                                                   // after beam, after greedy phase,
-                                                                   // after greedy kernel
-};
-
 extern "C" void rr_results_free(rr_results *res) {
     if (!res) return;
     for (auto &e : res->ev)
@@ -492,16 +466,16 @@ struct Carver {
     }
 };
 
-static int64_t next_pow2(int64_t x) {
+int64_t rr::next_pow2(int64_t x) {
     int64_t p = 1;
     while (p < x) p <<= 1;
     return p;
 }
 
-static rr_status make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
-                              const rr_search_params *sp, bool with_greedy, int64_t arena_cap,
-                              int64_t item_cap, int64_t hash_cap, int32_t qrow,
-                              const rr_allocator *alloc, void *stream, rr_results **out) {
+rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
+                           const rr_search_params *sp, bool with_greedy, int64_t arena_cap,
+                           int64_t item_cap, int64_t hash_cap, int32_t qrow,
+                           const rr_allocator *alloc, void *stream, rr_results **out) {
     rr_results *res = new (std::nothrow) rr_results();
     if (!res) return fail(RR_ENOMEM, "host allocation failed");
     res->nq = nq;
@@ -596,17 +570,8 @@ static rr_status check_radius(double r) {
     return RR_OK;
 }
 
-extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev, int64_t nq,
-                                     double radius, const double *radius_dev,
-                                     const rr_search_params *sp, const rr_allocator *alloc,
-                                     void *stream, rr_results **out) {
-    if (!out) return fail(RR_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!ix || !sp) return fail(RR_EINVAL, "index or params are NULL");
-    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
-    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
-    if (nq > 0 && !queries_dev) return fail(RR_EINVAL, "queries are NULL");
-    if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
+rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, SearchCfg *cfg_out,
+                             DevIndex *view_out, int32_t *qrow_out, bool *greedy_out) {
     if (sp->mode < RR_PLAIN || sp->mode > RR_DOUBLING) return fail(RR_EINVAL, "unknown mode %d", sp->mode);
     if (sp->mode == RR_DOUBLING) return fail(RR_EINVAL, "doubling search is not available in this build");
     if (sp->beam < 1 || sp->beam > 4096) return fail(RR_EINVAL, "beam must be in [1, 4096]");
@@ -623,6 +588,7 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     if (ix->dev.dtype != ix->dtype) return fail(RR_ESTATE, "index state is inconsistent");
 
     SearchCfg cfg{};
+    cfg.esr = sp->es_radius;
     cfg.mode = sp->mode;
     cfg.beam = sp->beam;
     cfg.es_enable = es ? 1 : 0;
@@ -654,6 +620,30 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
         view.row_bytes = ix->dev.row_bytes_bf16;
     }
     const int32_t qrow = approx ? 2 * view.row_bytes : view.row_bytes;
+    *cfg_out = cfg;
+    *view_out = view;
+    *qrow_out = qrow;
+    *greedy_out = greedy;
+    return RR_OK;
+}
+
+extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                     double radius, const double *radius_dev,
+                                     const rr_search_params *sp, const rr_allocator *alloc,
+                                     void *stream, rr_results **out) {
+    if (!out) return fail(RR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ix || !sp) return fail(RR_EINVAL, "index or params are NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
+    if (nq > 0 && !queries_dev) return fail(RR_EINVAL, "queries are NULL");
+    if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
+    SearchCfg cfg{};
+    DevIndex view;
+    int32_t qrow = 0;
+    bool greedy = false;
+    rr_status pst = prepare_search(ix, sp, &cfg, &view, &qrow, &greedy);
+    if (pst != RR_OK) return pst;
     int64_t gcap = 0, hash_cap = 0, item_cap = 0;
     if (greedy) {
         gcap = sp->result_capacity > 0 ? sp->result_capacity
@@ -687,7 +677,6 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
         HIP_TRY_R(hipEventRecord(res->ev[0], s));
     }
     HIP_TRY_R(launch_prep_queries(view, queries_dev, nq, radius, radius_dev, cfg, sb, s));
-    HIP_TRY_R(launch_set_esr(sb.qth, nq, sp->es_radius, s));
     const int cus = device_cus();
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[1], s));
     HIP_TRY_R(launch_beam(view, nq, cfg, sb, cus, s));

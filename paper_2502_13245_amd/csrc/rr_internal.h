@@ -59,7 +59,17 @@ struct QThresh {
     float lo, hi;    // approximate pass: accept if s <= lo, reject if s > hi
 };
 
+// Resumable state of one query's beam phase (the serving loop runs the beam
+// kernel in ticks with a step budget; B itself is stored beside it).
+struct BeamState {
+    int32_t nB, visits, evals, cursor;
+    int32_t flags; // BS_* below
+    int32_t pad;
+};
+enum { BS_STARTED = 1, BS_DONE = 2, BS_OVF = 4 };
+
 struct SearchCfg {
+    double esr;            // early-stop radius (squared units)
     int32_t mode;
     int32_t beam;
     int32_t es_enable;
@@ -123,6 +133,15 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
                                hipStream_t s);
 hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                        int num_cus, hipStream_t s);
+// serving: the beam kernel over a list of slots, resuming and suspending
+// each slot's state with at most `step_budget` visits per call
+hipError_t launch_beam_slots(const DevIndex &ix, const int32_t *qlist, int64_t nwork,
+                             const SearchCfg &cfg, SearchBufs &sb, BeamState *state, void *st_d,
+                             uint32_t *st_i, int32_t step_budget, int num_cus, hipStream_t s);
+// serving: pad the queries of newly admitted requests into their slots
+hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
+                             const double *radius_dev, const int32_t *dst, const SearchCfg &cfg,
+                             SearchBufs &sb, BeamState *state, hipStream_t s);
 hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                          int num_cus, hipStream_t s, hipEvent_t after_kernel = nullptr);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
@@ -142,4 +161,60 @@ hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, 
                               hipStream_t s);
 hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s);
 
+// error message of the calling thread (rr_last_error)
+rr_status set_error(rr_status st, const char *fmt, ...);
+
+} // namespace rr
+
+// the opaque handles of the C ABI
+struct rr_index {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t dtype = 0;
+    int32_t R = 0;
+    int32_t entry = 0;
+    std::vector<uint8_t> base; // n x d x esize, unpadded
+    std::vector<int32_t> adj;  // n x R
+    // device
+    bool on_device = false;
+    int device = -1;
+    rr::Allocator alloc;
+    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr;
+    rr::DevIndex dev;
+};
+
+struct rr_results {
+    int64_t nq = 0;
+    int32_t dtype = 0;
+    int32_t precision = 0;
+    int32_t R = 0;
+    int32_t row_bytes = 0;
+    int32_t d = 0;
+    int32_t es = 1;
+    hipStream_t stream = nullptr;
+    rr::Allocator alloc;
+    void *block = nullptr; // one allocation carved into the buffers below
+    rr::SearchBufs sb;
+    int64_t *offsets = nullptr; // [nq + 1] scanned counts
+    void *scan_tmp = nullptr;
+    rr::DevIndex ix;
+    bool stats_valid = true;
+    bool timing = false;
+    // timing events: start, before beam, after beam, after the greedy phase,
+    // after the greedy kernel
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace rr {
+// argument checks and kernel configuration shared by the batched search and
+// the serving loop; `greedy` tells whether the greedy/sort stage runs
+rr_status prepare_search(const rr_index *ix, const rr_search_params *sp, SearchCfg *cfg,
+                         DevIndex *view, int32_t *qrow, bool *greedy);
+// device buffers of one search (or of a server's slots when nq = slots)
+rr_status make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
+                       const rr_search_params *sp, bool with_greedy, int64_t arena_cap,
+                       int64_t item_cap, int64_t hash_cap, int32_t qrow,
+                       const rr_allocator *alloc, void *stream, rr_results **out);
+int device_cus();
+int64_t next_pow2(int64_t x);
 } // namespace rr

@@ -417,16 +417,19 @@ __device__ void band(double r2, double maxnorm, int d, double margin, float *lo,
     *lo = __double2float_rd(l);
 }
 
+// pads query qi into row dst[qi] (qi when dst is null) and derives its
+// thresholds; a non-null `state` marks the destination slots as fresh
 __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int32_t row_out,
                                double radius, const double *radius_dev, double esr,
                                QThresh *qth, uint8_t *qpad, double maxnorm, int d,
-                               double margin, int approx) {
+                               double margin, int approx, const int32_t *dst, BeamState *state) {
     const int64_t chunks = row_out / 16;
     const int64_t tot = nq * chunks;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t qi = t / chunks;
         const int64_t c = t % chunks;
+        const int64_t qo = dst ? (int64_t)dst[qi] : qi;
         uint8_t b[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -438,7 +441,7 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
         v.y = b[4] | (b[5] << 8) | (b[6] << 16) | ((uint32_t)b[7] << 24);
         v.z = b[8] | (b[9] << 8) | (b[10] << 16) | ((uint32_t)b[11] << 24);
         v.w = b[12] | (b[13] << 8) | (b[14] << 16) | ((uint32_t)b[15] << 24);
-        *reinterpret_cast<uint4 *>(qpad + qi * row_out + c * 16) = v;
+        *reinterpret_cast<uint4 *>(qpad + qo * row_out + c * 16) = v;
         if (c == 0) {
             QThresh th;
             const double r = radius_dev ? radius_dev[qi] : radius;
@@ -451,7 +454,11 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
             th.lo = -1.f;
             th.hi = -1.f;
             if (approx) band(r, maxnorm, d, margin, &th.lo, &th.hi);
-            qth[qi] = th;
+            qth[qo] = th;
+            if (state) {
+                BeamState bs{};
+                state[qo] = bs;
+            }
         }
     }
 }
@@ -470,7 +477,23 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s,
                        (const uint8_t *)queries, nq, ix.d * esz, row_out, radius, radius_dev,
-                       0.0, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, approx);
+                       cfg.esr, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, approx,
+                       (const int32_t *)nullptr, (BeamState *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
+                             const double *radius_dev, const int32_t *dst, const SearchCfg &cfg,
+                             SearchBufs &sb, BeamState *state, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
+    const int approx = kernel_dtype(ix, cfg) == RR_BF16X;
+    const int32_t row_out = approx ? 2 * ix.row_bytes : ix.row_bytes;
+    const int64_t tot = k * (row_out / 16);
+    int blocks = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s, (const uint8_t *)queries, k,
+                       ix.d * esz, row_out, 0.0, radius_dev, cfg.esr, sb.qth, sb.qpad,
+                       (double)ix.max_norm, ix.d, cfg.margin, approx, dst, state);
     return hipGetLastError();
 }
 
@@ -495,6 +518,13 @@ struct BeamArgs {
     SearchBufs sb;
     int32_t lds_per_wave;
     int32_t bcap;     // beam capacity in LDS
+    // serving: work item k is query qlist[k]; state resumes/suspends B
+    const int32_t *qlist;
+    int64_t nwork;
+    BeamState *state;
+    void *st_d;       // [nq][bcap] keys of the stored beams
+    uint32_t *st_i;   // [nq][bcap] ids (| visited bit)
+    int32_t step_budget; // visits per call and query (0: run to the end)
 };
 
 template <typename D>
@@ -530,10 +560,11 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
     const int b = cfg.beam;
 
     for (;;) {
-        int64_t q = 0;
-        if (lane == 0) q = (int64_t)atomicAdd(&a.sb.counters[CTR_QUEUE], 1ull);
-        q = __shfl(q, 0);
-        if (q >= a.nq) break;
+        int64_t wk = 0;
+        if (lane == 0) wk = (int64_t)atomicAdd(&a.sb.counters[CTR_QUEUE], 1ull);
+        wk = __shfl(wk, 0);
+        if (wk >= a.nwork) break;
+        const int64_t q = a.qlist ? (int64_t)a.qlist[wk] : wk;
 
         const QThresh th = a.sb.qth[q];
         QueryRegs<DTYPE, CPL, G> qr;
@@ -543,24 +574,44 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         wave_sync();
 
         bool ovf = false;
-        // B <- S = {entry}
-        if (lane == 0) {
-            ci[0] = (uint32_t)ix.entry;
-            seen_insert(htab, cs_mask, (uint32_t)ix.entry, ovf);
-        }
-        wave_sync();
-        eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, 1);
         D *bd = bdA, *bdo = bdB;
         uint32_t *bi = biA, *bio = biB;
-        if (lane == 0) {
-            bd[0] = cd[0];
-            bi[0] = (uint32_t)ix.entry;
-        }
-        wave_sync();
         int nB = 1;
         int visits = 0, evals = 1;
         int cursor = 0;
         bool es_fired = false;
+        if (a.state && (a.state[q].flags & BS_STARTED)) {
+            // resume: B as it was stored; the visited cache starts empty,
+            // which is exact because the cache may forget ids
+            const BeamState bs = a.state[q];
+            nB = bs.nB;
+            visits = bs.visits;
+            evals = bs.evals;
+            cursor = bs.cursor;
+            ovf = lane == 0 && (bs.flags & BS_OVF);
+            const D *sd = (const D *)a.st_d + (size_t)q * bcap;
+            const uint32_t *si = a.st_i + (size_t)q * bcap;
+            for (int i = lane; i < nB; i += 64) {
+                bd[i] = sd[i];
+                bi[i] = si[i];
+            }
+            wave_sync();
+        } else {
+            // B <- S = {entry}
+            if (lane == 0) {
+                ci[0] = (uint32_t)ix.entry;
+                seen_insert(htab, cs_mask, (uint32_t)ix.entry, ovf);
+            }
+            wave_sync();
+            eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, 1);
+            if (lane == 0) {
+                bd[0] = cd[0];
+                bi[0] = (uint32_t)ix.entry;
+            }
+            wave_sync();
+        }
+        int steps = 0;
+        bool suspend = false;
 
         for (;;) {
             // p* = first unvisited entry of the sorted beam at or after cursor
@@ -582,6 +633,11 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 es_fired = true;
                 break;
             }
+            if (a.step_budget > 0 && steps >= a.step_budget) {
+                suspend = true; // p* stays unvisited; the next call picks it again
+                break;
+            }
+            ++steps;
             const uint32_t p = bi[ip] & RR_IDMASK;
             wave_sync();
             if (lane == 0) bi[ip] = p | RR_VIS;
@@ -659,6 +715,28 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             cursor = min(ipnew + 1, firstnew);
         }
 
+        if (suspend) {
+            D *sd = (D *)a.st_d + (size_t)q * bcap;
+            uint32_t *si = a.st_i + (size_t)q * bcap;
+            for (int i = lane; i < nB; i += 64) {
+                sd[i] = bd[i];
+                si[i] = bi[i];
+            }
+            const bool any_ovf = __ballot(ovf) != 0ull;
+            if (lane == 0) {
+                BeamState bs;
+                bs.nB = nB;
+                bs.visits = visits;
+                bs.evals = evals;
+                bs.cursor = cursor;
+                bs.flags = BS_STARTED | (any_ovf ? BS_OVF : 0);
+                bs.pad = 0;
+                a.state[q] = bs;
+            }
+            wave_sync();
+            continue;
+        }
+        if (a.state && lane == 0) a.state[q].flags = BS_STARTED | BS_DONE;
         // N = the in-range points of B.  Exact types: an in-range prefix of
         // the sorted beam.  Approximate pass: the prefix with s <= hi holds
         // every possible member; each is re-decided on its exact distance.
@@ -1260,15 +1338,31 @@ hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s) {
     return dtype == RR_F32 ? run_finalize<double>(sb, s) : run_finalize<uint32_t>(sb, s);
 }
 
+struct SlotArgs {
+    const int32_t *qlist = nullptr;
+    int64_t nwork = 0;
+    BeamState *state = nullptr;
+    void *st_d = nullptr;
+    uint32_t *st_i = nullptr;
+    int32_t step_budget = 0;
+};
+
 template <int DTYPE, int CPL, int G>
 static hipError_t run_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
-                           int num_cus, hipStream_t s) {
+                           int num_cus, hipStream_t s, const SlotArgs &sl) {
     using D = typename DistOf<DTYPE>::T;
     BeamArgs a;
     a.ix = ix;
     a.nq = nq;
     a.cfg = cfg;
     a.sb = sb;
+    a.qlist = sl.qlist;
+    a.nwork = sl.qlist ? sl.nwork : nq;
+    a.state = sl.state;
+    a.st_d = sl.st_d;
+    a.st_i = sl.st_i;
+    a.step_budget = sl.step_budget;
+    nq = a.nwork;
     a.bcap = cfg.beam;
     a.lds_per_wave = beam_lds_bytes<D>(cfg.beam, cfg.cache_slots);
     const int waves = cfg.waves;
@@ -1320,20 +1414,39 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
     X(DT, 1, 4) X(DT, 1, 8) X(DT, 1, 16) X(DT, 1, 32) X(DT, 1, 64) X(DT, 2, 64) X(DT, 4, 64)  \
         X(DT, 3, 4) X(DT, 3, 8) X(DT, 3, 16) X(DT, 3, 32) X(DT, 3, 64) X(DT, 6, 64)
 
-hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
-                       int num_cus, hipStream_t s) {
-    if (nq == 0) return hipSuccess;
+static hipError_t dispatch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
+                                SearchBufs &sb, int num_cus, hipStream_t s, const SlotArgs &sl) {
     int32_t cpl = 0, g = 0;
     row_split(ix.row_bytes, &cpl, &g);
     const int kd = kernel_dtype(ix, cfg);
 #define X(DT, C, GG)                                                                          \
-    if (kd == DT && cpl == C && g == GG) return run_beam<DT, C, GG>(ix, nq, cfg, sb, num_cus, s);
+    if (kd == DT && cpl == C && g == GG) return run_beam<DT, C, GG>(ix, nq, cfg, sb, num_cus, s, sl);
     RR_SPLITS(X, RR_U8)
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
     RR_SPLITS(X, RR_BF16X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                       int num_cus, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    return dispatch_beam(ix, nq, cfg, sb, num_cus, s, SlotArgs());
+}
+
+hipError_t launch_beam_slots(const DevIndex &ix, const int32_t *qlist, int64_t nwork,
+                             const SearchCfg &cfg, SearchBufs &sb, BeamState *state, void *st_d,
+                             uint32_t *st_i, int32_t step_budget, int num_cus, hipStream_t s) {
+    if (nwork == 0) return hipSuccess;
+    SlotArgs sl;
+    sl.qlist = qlist;
+    sl.nwork = nwork;
+    sl.state = state;
+    sl.st_d = st_d;
+    sl.st_i = st_i;
+    sl.step_budget = step_budget;
+    return dispatch_beam(ix, nwork, cfg, sb, num_cus, s, sl);
 }
 
 hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,

@@ -1,0 +1,538 @@
+// rr_server.cpp -- continuous batching of range queries (host side).
+//
+// A server keeps `slots` queries resident on the device.  One host thread
+// runs ticks; each tick
+//   1. moves queued requests into free slots (query rows and radii are
+//      copied to the device and padded into their slot),
+//   2. runs the beam kernel over every resident slot with at most
+//      `step_budget` visits per slot: a slot whose beam search (Algorithm 1,
+//      with Algorithm 5's stop) has not finished stores its beam in device
+//      memory and resumes from it on the next tick,
+//   3. runs the greedy phase (Algorithm 2, chosen by Algorithm 6) and the
+//      sort for the slots whose beam finished in this tick,
+//   4. copies the finished slots' results to the host and frees the slots.
+// Requests that arrive while a tick runs join at the next tick, so a long
+// query never holds back short ones by more than one tick of work.
+//
+// A slot resumes with an empty visited cache.  That is exact: the cache only
+// serves to skip re-evaluations, insertion into the beam de-duplicates, and an
+// id that was dropped from a full beam cannot re-enter it because the beam's
+// last key never increases.  A query therefore visits the same points and
+// returns the same result as in a batched search.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rr_internal.h"
+
+using namespace rr;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t tag;
+    double radius;
+    double t_arrival;
+    std::vector<uint8_t> q;
+};
+
+struct Slot {
+    bool busy = false;
+    uint64_t tag = 0;
+    double t_arrival = 0, t_admit = 0;
+    int32_t ticks = 0;
+};
+
+struct Finished {
+    std::vector<int32_t> ids;
+    std::vector<uint8_t> dists; // int32 (integer data) or float32 (float data)
+};
+
+} // namespace
+
+struct rr_server {
+    const rr_index *ix = nullptr;
+    DevIndex view;
+    SearchCfg cfg{};
+    bool greedy = false;
+    int32_t qrow = 0;
+    int32_t S = 0;
+    int32_t step_budget = 0;
+    int32_t max_pending = 0;
+    int64_t qbytes = 0; // d x element size of one submitted query
+    int dsz = 4;        // bytes of one arena distance
+    int device = 0;
+    int cus = 0;
+    hipStream_t stream = nullptr;
+    rr_results *bufs = nullptr; // device buffers for S queries
+    Allocator alloc;
+    void *dblock = nullptr; // state, stored beams, qlist, staging
+    BeamState *d_state = nullptr;
+    void *d_st_d = nullptr;
+    uint32_t *d_st_i = nullptr;
+    int32_t *d_qlist = nullptr;
+    uint8_t *d_stage_q = nullptr;
+    double *d_stage_r = nullptr;
+    int32_t *d_stage_dst = nullptr;
+    // pinned host mirrors
+    void *hblock = nullptr;
+    uint8_t *h_stage_q = nullptr;
+    double *h_stage_r = nullptr;
+    int32_t *h_stage_dst = nullptr;
+    int32_t *h_qlist = nullptr;
+    BeamState *h_state = nullptr;
+    int64_t *h_roff = nullptr;
+    int32_t *h_rcnt = nullptr;
+    rr_query_stats *h_stats = nullptr;
+    unsigned long long *h_ctr = nullptr;
+    int32_t *h_aid = nullptr;
+    uint8_t *h_ad = nullptr;
+    bool hash_dirty = true;
+
+    Clock::time_point t0;
+    std::thread worker;
+    mutable std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    bool failed = false;
+    std::string error;
+    std::deque<Request> pending;
+    std::vector<Slot> slots;
+    std::vector<int32_t> free_slots;
+    std::deque<rr_completion> completions;
+    std::unordered_map<uint64_t, Finished> results;
+    rr_server_info info{};
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+hipError_t tick_device(rr_server *s, int32_t admitted, int32_t nwork) {
+    hipError_t e;
+    SearchBufs &sb = s->bufs->sb;
+    if (admitted > 0) {
+        e = hipMemcpyAsync(s->d_stage_q, s->h_stage_q, (size_t)admitted * s->qbytes,
+                           hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(s->d_stage_r, s->h_stage_r, (size_t)admitted * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(s->d_stage_dst, s->h_stage_dst, (size_t)admitted * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        e = launch_prep_slots(s->view, s->d_stage_q, admitted, s->d_stage_r, s->d_stage_dst, s->cfg,
+                              sb, s->d_state, s->stream);
+        if (e != hipSuccess) return e;
+    }
+    e = hipMemcpyAsync(s->d_qlist, s->h_qlist, (size_t)nwork * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s->stream);
+    if (e != hipSuccess) return e;
+    if (s->greedy) {
+        e = launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s->stream);
+        if (e != hipSuccess) return e;
+        if (s->hash_dirty) {
+            e = launch_fill_u64(sb.hash, sb.hash_cap, ~0ull, s->stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    e = launch_beam_slots(s->view, s->d_qlist, nwork, s->cfg, sb, s->d_state, s->d_st_d, s->d_st_i,
+                          s->step_budget, s->cus, s->stream);
+    if (e != hipSuccess) return e;
+    if (s->greedy) {
+        e = launch_greedy(s->view, s->S, s->cfg, sb, s->cus, s->stream);
+        if (e != hipSuccess) return e;
+    }
+    const size_t S = (size_t)s->S;
+    e = hipMemcpyAsync(s->h_state, s->d_state, S * sizeof(BeamState), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(s->h_roff, sb.res_off, S * sizeof(int64_t), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(s->h_rcnt, sb.res_cnt, S * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(s->h_stats, sb.stats, S * sizeof(rr_query_stats), hipMemcpyDeviceToHost,
+                       s->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(s->h_ctr, sb.counters, CTR_COUNT * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return e;
+    // the arena holds this tick's results
+    const int64_t used = std::min<int64_t>((int64_t)s->h_ctr[CTR_ARENA], sb.arena_cap);
+    if (used > 0) {
+        e = hipMemcpyAsync(s->h_aid, sb.arena_ids, (size_t)used * 4, hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(s->h_ad, sb.arena_dists, (size_t)used * s->dsz, hipMemcpyDeviceToHost,
+                           s->stream);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return e;
+    }
+    if (s->greedy) s->hash_dirty = s->h_ctr[CTR_TASKS] > 0;
+    return hipSuccess;
+}
+
+void worker_main(rr_server *s) {
+    if (hipSetDevice(s->device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->failed = true;
+        s->error = "hipSetDevice failed in the server thread";
+        s->cv_done.notify_all();
+        return;
+    }
+    std::vector<int32_t> active;
+    active.reserve(s->S);
+    for (;;) {
+        int32_t admitted = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] {
+                return s->stop || active.size() > 0 ||
+                       (!s->pending.empty() && !s->free_slots.empty());
+            });
+            if (s->stop && s->pending.empty() && active.empty()) break;
+            const double t = s->now();
+            while (!s->pending.empty() && !s->free_slots.empty()) {
+                Request &r = s->pending.front();
+                const int32_t slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                std::memcpy(s->h_stage_q + (size_t)admitted * s->qbytes, r.q.data(), s->qbytes);
+                s->h_stage_r[admitted] = r.radius;
+                s->h_stage_dst[admitted] = slot;
+                Slot &sl = s->slots[slot];
+                sl.busy = true;
+                sl.tag = r.tag;
+                sl.t_arrival = r.t_arrival;
+                sl.t_admit = t;
+                sl.ticks = 0;
+                active.push_back(slot);
+                ++admitted;
+                s->pending.pop_front();
+            }
+            s->info.admitted += admitted;
+            s->info.pending = (int64_t)s->pending.size();
+            s->info.resident = (int64_t)active.size();
+            s->info.max_resident = std::max<int64_t>(s->info.max_resident, (int64_t)active.size());
+        }
+        const Clock::time_point tb = Clock::now();
+        for (size_t i = 0; i < active.size(); ++i) s->h_qlist[i] = active[i];
+        const hipError_t e = tick_device(s, admitted, (int32_t)active.size());
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->failed = true;
+            s->error = std::string("server tick failed: ") + hipGetErrorString(e);
+            s->cv_done.notify_all();
+            return;
+        }
+        // collect the slots whose search finished in this tick
+        std::vector<rr_completion> done;
+        std::vector<std::pair<uint64_t, Finished>> out;
+        std::vector<int32_t> freed;
+        size_t keep = 0;
+        for (size_t i = 0; i < active.size(); ++i) {
+            const int32_t slot = active[i];
+            Slot &sl = s->slots[slot];
+            ++sl.ticks;
+            if (!(s->h_state[slot].flags & BS_DONE)) {
+                active[keep++] = slot;
+                continue;
+            }
+            const int64_t off = s->h_roff[slot];
+            const int32_t cnt = s->h_rcnt[slot];
+            const int64_t used = std::min<int64_t>((int64_t)s->h_ctr[CTR_ARENA], s->bufs->sb.arena_cap);
+            if (cnt < 0 || (cnt > 0 && (off < 0 || off + cnt > used))) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->failed = true;
+                s->error = "server tick returned an inconsistent result segment";
+                s->cv_done.notify_all();
+                return;
+            }
+            Finished f;
+            f.ids.assign(s->h_aid + off, s->h_aid + off + cnt);
+            if (s->ix->dtype == RR_F32) {
+                f.dists.resize((size_t)cnt * 4);
+                const double *src = (const double *)s->h_ad + off;
+                float *dst = (float *)f.dists.data();
+                for (int32_t j = 0; j < cnt; ++j) dst[j] = (float)src[j];
+            } else {
+                const uint8_t *src = s->h_ad + (size_t)off * 4;
+                f.dists.assign(src, src + (size_t)cnt * 4);
+            }
+            rr_completion c{};
+            c.tag = sl.tag;
+            c.count = cnt;
+            c.stats = s->h_stats[slot];
+            c.truncated = c.stats.truncated;
+            c.ticks = sl.ticks;
+            c.t_arrival = sl.t_arrival;
+            c.t_admit = sl.t_admit;
+            done.push_back(c);
+            out.emplace_back(sl.tag, std::move(f));
+            freed.push_back(slot);
+            sl.busy = false;
+        }
+        active.resize(keep);
+        const double t = s->now();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < done.size(); ++i) {
+                done[i].t_done = t;
+                s->results[done[i].tag] = std::move(out[i].second);
+                s->completions.push_back(done[i]);
+                s->free_slots.push_back(freed[i]);
+            }
+            s->info.completed += (int64_t)done.size();
+            s->info.ticks += 1;
+            s->info.resident = (int64_t)active.size();
+            s->info.busy_s += std::chrono::duration<double>(Clock::now() - tb).count();
+            s->cv_done.notify_all();
+        }
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_done.notify_all();
+}
+
+void destroy_buffers(rr_server *s) {
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->bufs) rr_results_free(s->bufs);
+    s->bufs = nullptr;
+    if (s->dblock) s->alloc.release(s->dblock);
+    s->dblock = nullptr;
+    if (s->hblock) (void)hipHostFree(s->hblock);
+    s->hblock = nullptr;
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    s->stream = nullptr;
+}
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+} // namespace
+
+extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params *sp,
+                                      const rr_server_config *scfg, const rr_allocator *alloc,
+                                      rr_server **out) {
+    if (!out) return set_error(RR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ix || !sp || !scfg) return set_error(RR_EINVAL, "index, params or config is NULL");
+    if (!ix->on_device) return set_error(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (scfg->slots < 1 || scfg->slots > (1 << 20)) return set_error(RR_EINVAL, "slots must be in [1, 2^20]");
+    if (scfg->step_budget < 0) return set_error(RR_EINVAL, "step_budget must be >= 0");
+    if (scfg->result_capacity < 0) return set_error(RR_EINVAL, "result_capacity must be >= 0");
+    if (scfg->max_pending < 0) return set_error(RR_EINVAL, "max_pending must be >= 0");
+    rr_server *s = new (std::nothrow) rr_server();
+    if (!s) return set_error(RR_ENOMEM, "host allocation failed");
+    rr_status st = prepare_search(ix, sp, &s->cfg, &s->view, &s->qrow, &s->greedy);
+    if (st != RR_OK) {
+        delete s;
+        return st;
+    }
+    s->ix = ix;
+    s->S = scfg->slots;
+    s->step_budget = scfg->step_budget;
+    s->max_pending = scfg->max_pending > 0 ? scfg->max_pending : (1 << 20);
+    s->qbytes = (int64_t)ix->d * (ix->dtype == RR_F32 ? 4 : 1);
+    s->dsz = ix->dtype == RR_F32 ? 8 : 4;
+    s->device = ix->device;
+    s->t0 = Clock::now();
+    auto bail = [&](rr_status code, const char *msg, hipError_t e) {
+        destroy_buffers(s);
+        delete s;
+        return set_error(code, "%s: %s", msg, hipGetErrorString(e));
+    };
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return bail(RR_EHIP, "hipSetDevice", e);
+    s->cus = device_cus();
+    e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(RR_EHIP, "hipStreamCreateWithFlags", e);
+
+    const int64_t S = s->S, b = sp->beam;
+    int64_t gcap = 0, item_cap = 0, hash_cap = 0;
+    if (s->greedy) {
+        gcap = scfg->result_capacity > 0 ? scfg->result_capacity : std::min<int64_t>(S * 4096, 1 << 21);
+        item_cap = S * b + gcap;
+        hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024));
+    }
+    const int64_t arena_cap = S * b + gcap;
+    st = make_results(ix, s->view, S, sp, s->greedy, arena_cap, item_cap, hash_cap, s->qrow, alloc,
+                      s->stream, &s->bufs);
+    if (st != RR_OK) {
+        destroy_buffers(s);
+        delete s;
+        return st;
+    }
+    if (alloc && alloc->alloc && alloc->free) {
+        s->alloc.user = *alloc;
+        s->alloc.has_user = true;
+    }
+    s->alloc.stream = s->stream;
+    // device: state, stored beams (keys up to 8 bytes), qlist, staging
+    size_t o = 0;
+    const size_t o_state = o; o = up256(o + (size_t)S * sizeof(BeamState));
+    const size_t o_std = o;   o = up256(o + (size_t)S * b * 8);
+    const size_t o_sti = o;   o = up256(o + (size_t)S * b * 4);
+    const size_t o_ql = o;    o = up256(o + (size_t)S * 4);
+    const size_t o_sq = o;    o = up256(o + (size_t)S * s->qbytes);
+    const size_t o_sr = o;    o = up256(o + (size_t)S * 8);
+    const size_t o_sdst = o;  o = up256(o + (size_t)S * 4);
+    s->dblock = s->alloc.alloc(o);
+    if (!s->dblock) {
+        destroy_buffers(s);
+        delete s;
+        return set_error(RR_ENOMEM, "device allocation of %zu bytes failed", o);
+    }
+    uint8_t *db = (uint8_t *)s->dblock;
+    s->d_state = (BeamState *)(db + o_state);
+    s->d_st_d = db + o_std;
+    s->d_st_i = (uint32_t *)(db + o_sti);
+    s->d_qlist = (int32_t *)(db + o_ql);
+    s->d_stage_q = db + o_sq;
+    s->d_stage_r = (double *)(db + o_sr);
+    s->d_stage_dst = (int32_t *)(db + o_sdst);
+    // pinned host mirrors
+    size_t h = 0;
+    const size_t h_sq = h;   h = up256(h + (size_t)S * s->qbytes);
+    const size_t h_sr = h;   h = up256(h + (size_t)S * 8);
+    const size_t h_sdst = h; h = up256(h + (size_t)S * 4);
+    const size_t h_ql = h;   h = up256(h + (size_t)S * 4);
+    const size_t h_st = h;   h = up256(h + (size_t)S * sizeof(BeamState));
+    const size_t h_ro = h;   h = up256(h + (size_t)S * 8);
+    const size_t h_rc = h;   h = up256(h + (size_t)S * 4);
+    const size_t h_ss = h;   h = up256(h + (size_t)S * sizeof(rr_query_stats));
+    const size_t h_c = h;    h = up256(h + (size_t)CTR_COUNT * 8);
+    const size_t h_ai = h;   h = up256(h + (size_t)arena_cap * 4);
+    const size_t h_ad = h;   h = up256(h + (size_t)arena_cap * s->dsz);
+    e = hipHostMalloc(&s->hblock, h, hipHostMallocDefault);
+    if (e != hipSuccess) return bail(RR_ENOMEM, "hipHostMalloc", e);
+    uint8_t *hb = (uint8_t *)s->hblock;
+    s->h_stage_q = hb + h_sq;
+    s->h_stage_r = (double *)(hb + h_sr);
+    s->h_stage_dst = (int32_t *)(hb + h_sdst);
+    s->h_qlist = (int32_t *)(hb + h_ql);
+    s->h_state = (BeamState *)(hb + h_st);
+    s->h_roff = (int64_t *)(hb + h_ro);
+    s->h_rcnt = (int32_t *)(hb + h_rc);
+    s->h_stats = (rr_query_stats *)(hb + h_ss);
+    s->h_ctr = (unsigned long long *)(hb + h_c);
+    s->h_aid = (int32_t *)(hb + h_ai);
+    s->h_ad = hb + h_ad;
+
+    s->slots.assign((size_t)S, Slot());
+    s->free_slots.reserve((size_t)S);
+    for (int64_t i = S - 1; i >= 0; --i) s->free_slots.push_back((int32_t)i);
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        destroy_buffers(s);
+        delete s;
+        return set_error(RR_ENOMEM, "could not start the server thread");
+    }
+    *out = s;
+    return RR_OK;
+}
+
+extern "C" double rr_server_clock(const rr_server *s) { return s ? s->now() : 0.0; }
+
+extern "C" rr_status rr_server_submit(rr_server *s, const void *query_host, double radius,
+                                      uint64_t tag, double t_arrival) {
+    if (!s || !query_host) return set_error(RR_EINVAL, "server or query is NULL");
+    if (radius != radius) return set_error(RR_EINVAL, "radius is NaN");
+    Request r;
+    r.tag = tag;
+    r.radius = radius;
+    r.q.assign((const uint8_t *)query_host, (const uint8_t *)query_host + s->qbytes);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->failed) return set_error(RR_ESTATE, "%s", s->error.c_str());
+        if (s->stop) return set_error(RR_ESTATE, "server is stopping");
+        if ((int64_t)s->pending.size() >= s->max_pending)
+            return set_error(RR_EBUSY, "request queue is full (%d)", s->max_pending);
+        r.t_arrival = t_arrival >= 0 ? t_arrival : s->now();
+        s->pending.push_back(std::move(r));
+        s->info.submitted += 1;
+        s->info.pending = (int64_t)s->pending.size();
+    }
+    s->cv_work.notify_one();
+    return RR_OK;
+}
+
+extern "C" rr_status rr_server_poll(rr_server *s, rr_completion *out, int32_t max, int32_t *n) {
+    if (!s || !n || (max > 0 && !out)) return set_error(RR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t k = 0;
+    while (k < max && !s->completions.empty()) {
+        out[k++] = s->completions.front();
+        s->completions.pop_front();
+    }
+    *n = k;
+    if (s->failed) return set_error(RR_ESTATE, "%s", s->error.c_str());
+    return RR_OK;
+}
+
+extern "C" rr_status rr_server_result(rr_server *s, uint64_t tag, int32_t *ids_host,
+                                      void *dists_host, int64_t capacity, int64_t *count) {
+    if (!s || !count) return set_error(RR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->results.find(tag);
+    if (it == s->results.end()) return set_error(RR_EINVAL, "no finished request with this tag");
+    const int64_t c = (int64_t)it->second.ids.size();
+    *count = c;
+    if (capacity < c) return set_error(RR_ENOMEM, "capacity %lld < %lld results", (long long)capacity, (long long)c);
+    if (c > 0 && (!ids_host || !dists_host)) return set_error(RR_EINVAL, "output buffers are NULL");
+    if (c > 0) {
+        std::memcpy(ids_host, it->second.ids.data(), (size_t)c * 4);
+        std::memcpy(dists_host, it->second.dists.data(), (size_t)c * 4);
+    }
+    s->results.erase(it);
+    return RR_OK;
+}
+
+extern "C" rr_status rr_server_drain(rr_server *s, double timeout_s) {
+    if (!s) return set_error(RR_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto idle = [&] {
+        return s->failed || (s->pending.empty() && s->info.completed == s->info.submitted);
+    };
+    if (timeout_s < 0) {
+        s->cv_done.wait(lk, idle);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), idle)) {
+        return set_error(RR_EBUSY, "drain timed out");
+    }
+    if (s->failed) return set_error(RR_ESTATE, "%s", s->error.c_str());
+    return RR_OK;
+}
+
+extern "C" rr_status rr_server_info_get(const rr_server *s, rr_server_info *info) {
+    if (!s || !info) return set_error(RR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *info = s->info;
+    return RR_OK;
+}
+
+extern "C" void rr_server_destroy(rr_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
+    destroy_buffers(s);
+    delete s;
+}

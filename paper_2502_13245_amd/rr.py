@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librr.so")
 
-RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_EIO, RR_ESTATE = range(6)
+RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_EIO, RR_ESTATE, RR_EBUSY = range(7)
 U8, I8, F32 = 0, 1, 2
 PLAIN, ES, ADAPTIVE, DOUBLING = 0, 1, 2, 3
 EXACT, BF16_RECHECK = 0, 1
@@ -83,6 +83,26 @@ class TuneReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("step_budget", C.c_int32),
+                ("result_capacity", C.c_int64), ("max_pending", C.c_int32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("count", C.c_int64), ("truncated", C.c_int32),
+                ("ticks", C.c_int32), ("t_arrival", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("stats", QueryStats)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("ticks", "submitted", "admitted", "completed",
+                                          "pending", "resident", "max_resident")] + [
+                ("busy_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
@@ -120,6 +140,15 @@ SIGNATURES = {
     "rr_results_copy": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "rr_results_stats": (C.c_int, [_VP, C.POINTER(QueryStats), C.POINTER(BatchStats)]),
     "rr_results_free": (None, [_VP]),
+    "rr_server_create": (C.c_int, [_VP, C.POINTER(SearchParams), C.POINTER(ServerConfig),
+                                   C.POINTER(Allocator), C.POINTER(_VP)]),
+    "rr_server_clock": (C.c_double, [_VP]),
+    "rr_server_submit": (C.c_int, [_VP, _VP, C.c_double, C.c_uint64, C.c_double]),
+    "rr_server_poll": (C.c_int, [_VP, C.POINTER(Completion), _I32, C.POINTER(C.c_int32)]),
+    "rr_server_result": (C.c_int, [_VP, C.c_uint64, _VP, _VP, _I64, C.POINTER(C.c_int64)]),
+    "rr_server_drain": (C.c_int, [_VP, C.c_double]),
+    "rr_server_info_get": (C.c_int, [_VP, C.POINTER(ServerInfo)]),
+    "rr_server_destroy": (None, [_VP]),
     "rr_autotune": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, _VP, C.c_double, _I32,
                               C.POINTER(SearchParams), C.POINTER(TuneReport),
                               C.POINTER(Allocator), _VP]),
@@ -438,3 +467,92 @@ def nn_dist(index: Index, queries, stream=None):
     _check(lib().rr_nn_dist(index._h, C.c_void_p(q.data_ptr()), q.shape[0],
                             C.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+class Server:
+    """Continuous batching over resident slots (rr_server_*).
+
+    Requests are host vectors; results come back to host memory.  The
+    library's own thread runs the ticks, so ``submit`` never waits for the
+    device.
+    """
+
+    def __init__(self, index: Index, params: SearchParams | None = None, slots=1024,
+                 step_budget=0, result_capacity=0, max_pending=0):
+        if index.device is None:
+            raise RRError(RR_ESTATE, "index is not on the device")
+        self.index = index  # the server reads the index's device memory
+        inf = index.info()
+        self.d = inf["d"]
+        self.np_dtype = {U8: np.uint8, I8: np.int8, F32: np.float32}[inf["dtype"]]
+        self.dist_dtype = np.float32 if inf["dtype"] == F32 else np.int32
+        params = params or search_params()
+        cfg = ServerConfig(int(slots), int(step_budget), int(result_capacity), int(max_pending))
+        out = C.c_void_p()
+        _check(lib().rr_server_create(index._h, C.byref(params), C.byref(cfg), None,
+                                      C.byref(out)))
+        self._h = out
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().rr_server_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def clock(self) -> float:
+        return lib().rr_server_clock(self._h)
+
+    def submit(self, query, radius: float, tag: int, t_arrival: float = -1.0) -> bool:
+        """Queue one request; False if the queue is full (RR_EBUSY)."""
+        q = np.ascontiguousarray(query, dtype=self.np_dtype)
+        if q.size != self.d:
+            raise ValueError(f"query has {q.size} values, the index has d={self.d}")
+        st = lib().rr_server_submit(self._h, q.ctypes.data, float(radius), int(tag),
+                                    float(t_arrival))
+        if st == RR_EBUSY:
+            return False
+        _check(st)
+        return True
+
+    def poll(self, max_items=4096):
+        buf = (Completion * max_items)()
+        n = C.c_int32()
+        _check(lib().rr_server_poll(self._h, buf, max_items, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def result(self, tag: int):
+        """(ids, dists) of a finished request, ordered by (distance, id)."""
+        cnt = C.c_int64()
+        st = lib().rr_server_result(self._h, int(tag), None, None, 0, C.byref(cnt))
+        if st == RR_OK:
+            return np.empty(0, np.int32), np.empty(0, self.dist_dtype)
+        if st != RR_ENOMEM:
+            _check(st)
+        ids = np.empty(cnt.value, np.int32)
+        dists = np.empty(cnt.value, self.dist_dtype)
+        _check(lib().rr_server_result(self._h, int(tag), ids.ctypes.data, dists.ctypes.data,
+                                      cnt.value, C.byref(cnt)))
+        return ids, dists
+
+    def drain(self, timeout=-1.0):
+        _check(lib().rr_server_drain(self._h, float(timeout)))
+
+    def info(self) -> dict:
+        inf = ServerInfo()
+        _check(lib().rr_server_info_get(self._h, C.byref(inf)))
+        return inf.as_dict()
