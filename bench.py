@@ -303,6 +303,7 @@ def main():
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=t, kernel=kernel,
                     bytes_per_launch=int(nbytes), avg_ms=round(ms, 4))
 
+    log(f"greedy levels: {st['levels']}")
     r_beam = roof("k_beam", st["bytes_beam"], float(np.mean(beam_ms)), "k_beam<0, 1, 8>")
     r_greedy = (roof("k_greedy", st["bytes_greedy"], float(np.mean(gk_ms)), "k_greedy<0, 1, 8>")
                 if st["greedy_kernel_ms"] > 0 else None)
@@ -376,7 +377,8 @@ def main():
         "graph_build_s": round(build_s, 1) if build_s else None,
         "greedy": {"phase_ms": round(float(np.mean(greedy_ms)), 4),
                    "kernel_ms": round(float(np.mean(gk_ms)), 4), "levels": st["greedy_levels"],
-                   "items": st["greedy_items"], "tasks": st["expanded"]},
+                   "items": st["greedy_items"], "tasks": st["expanded"],
+                   "levels": st["levels"]},
         "curves": curves,
     }
     print(json.dumps(out), flush=True)

@@ -315,6 +315,15 @@ rr_status rr_results_copy(const rr_results *res, int32_t *ids_dev, void *dists_d
 rr_status rr_results_stats(const rr_results *res, rr_query_stats *per_query_host,
                            rr_batch_stats *agg);
 
+/* Greedy-phase breakdown (per-phase timing of the adaptive search):
+ * for each level l < min(max_levels, *n_levels) of the level-synchronous
+ * expansion, items[l] = points expanded, expand_ms[l] = time to expand
+ * them, regroup_ms[l] = time to group the next level by task (wall-clock
+ * stamps taken inside the kernel).  Any output pointer may be NULL.
+ * *n_levels = 0 if no greedy phase ran.  Synchronizes with the stream. */
+rr_status rr_results_level_profile(const rr_results *res, int32_t max_levels, int64_t *items,
+                                   double *expand_ms, double *regroup_ms, int32_t *n_levels);
+
 void rr_results_free(rr_results *res);
 
 #ifdef __cplusplus

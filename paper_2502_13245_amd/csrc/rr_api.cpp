@@ -505,7 +505,8 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
     size_t o_off = c.take<int64_t>(nq + 1);
     size_t o_scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
     size_t o_tq = 0, o_tc = 0, o_te = 0, o_it = 0, o_ii = 0, o_idist = 0, o_lvl = 0, o_hash = 0,
-           o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0, o_tr = 0, o_tx = 0;
+           o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0, o_tr = 0, o_tx = 0, o_tp = 0, o_ut = 0,
+           o_ui = 0, o_ud = 0, o_lc = 0;
     const int32_t max_levels = 4096;
     if (with_greedy) {
         o_tq = c.take<int32_t>(nq);
@@ -522,6 +523,11 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         o_scur = c.take<unsigned long long>(nq);
         o_sid = c.take<int32_t>(item_cap);
         o_sd = c.take<uint8_t>(item_cap * (int64_t)dsz);
+        o_tp = c.take<unsigned long long>(nq);
+        o_lc = c.take<unsigned long long>(1 + 3 * LEVEL_CLOCKS);
+        o_ut = c.take<int32_t>(item_cap);
+        o_ui = c.take<int32_t>(item_cap);
+        o_ud = c.take<uint8_t>(item_cap * (int64_t)dsz);
     }
     const size_t total = c.take<uint8_t>(1);
     res->block = res->alloc.alloc(total);
@@ -560,6 +566,11 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         sb.seg_cur = (unsigned long long *)(b + o_scur);
         sb.seg_ids = (int32_t *)(b + o_sid);
         sb.seg_dists = b + o_sd;
+        sb.task_prev = (unsigned long long *)(b + o_tp);
+        sb.level_clock = (unsigned long long *)(b + o_lc);
+        sb.u_task = (int32_t *)(b + o_ut);
+        sb.u_id = (int32_t *)(b + o_ui);
+        sb.u_dist = b + o_ud;
     }
     *out = res;
     return RR_OK;
@@ -799,6 +810,8 @@ extern "C" rr_status rr_results_total(const rr_results *res, int64_t *total) {
     int64_t tot = 0;
     HIP_TRY(hipMemcpy(&tot, res->offsets + res->nq, sizeof tot, hipMemcpyDeviceToHost));
     *total = tot;
+    if (ctr[CTR_OVERFLOW] & 32ull)
+        return fail(RR_EHIP, "the greedy phase's grid barrier timed out");
     if (ctr[CTR_OVERFLOW])
         return fail(RR_ENOMEM,
                     "a search capacity was exceeded (code %llu); raise result_capacity or "
@@ -829,6 +842,39 @@ extern "C" rr_status rr_results_copy(const rr_results *res, int32_t *ids_dev, vo
                                 res->sb.res_off, res->sb.res_cnt, res->sb.arena_ids,
                                 res->sb.arena_dists, ids_dev, dists_dev, offsets_dev,
                                 res->scan_tmp, s));
+    return RR_OK;
+}
+
+extern "C" rr_status rr_results_level_profile(const rr_results *res, int32_t max_levels,
+                                              int64_t *items, double *expand_ms,
+                                              double *regroup_ms, int32_t *n_levels) {
+    if (!res || !n_levels) return fail(RR_EINVAL, "results or n_levels are NULL");
+    *n_levels = 0;
+    if (!res->sb.level_clock) return RR_OK; // no greedy phase ran
+    HIP_TRY(hipStreamSynchronize(res->stream));
+    unsigned long long ctr[CTR_COUNT];
+    HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
+    const int32_t lv = (int32_t)std::min<unsigned long long>(ctr[CTR_LEVELS], LEVEL_CLOCKS);
+    std::vector<unsigned long long> clk(1 + 3 * LEVEL_CLOCKS), lc((size_t)std::max(lv, 1));
+    HIP_TRY(hipMemcpy(clk.data(), res->sb.level_clock, clk.size() * sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost));
+    if (lv > 0)
+        HIP_TRY(hipMemcpy(lc.data(), res->sb.level_cnt, lv * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const double ms_per_tick = khz > 0 ? 1.0 / khz : 0.0;
+    const int32_t n = std::min(lv, std::max(max_levels, 0));
+    unsigned long long prev = clk[0];
+    for (int32_t l = 0; l < n; ++l) {
+        const unsigned long long a = clk[1 + 3 * l], c = clk[3 + 3 * l];
+        if (items) items[l] = (int64_t)lc[l];
+        if (expand_ms) expand_ms[l] = a >= prev ? (double)(a - prev) * ms_per_tick : 0.0;
+        if (regroup_ms) regroup_ms[l] = c >= a && c ? (double)(c - a) * ms_per_tick : 0.0;
+        prev = c ? c : a;
+    }
+    *n_levels = n;
     return RR_OK;
 }
 

@@ -104,11 +104,16 @@ struct SearchBufs {
     unsigned long long *task_evals = nullptr; // [nq]
     unsigned long long *task_rechk = nullptr; // [nq] exact rechecks in the band
     int8_t *task_expand = nullptr;            // [nq] 1: run Algorithm 2 from the seeds
+    unsigned long long *task_prev = nullptr;  // [nq] task_cnt before the current level
     int32_t *item_task = nullptr; // [item_cap]
     int32_t *item_id = nullptr;
     void *item_dist = nullptr;
     int64_t item_cap = 0;
+    int32_t *u_task = nullptr;    // [item_cap] a level as emitted, before grouping by task
+    int32_t *u_id = nullptr;
+    void *u_dist = nullptr;
     unsigned long long *level_cnt = nullptr; // [max_levels]
+    unsigned long long *level_clock = nullptr; // [1 + 3 * LEVEL_CLOCKS] greedy phase timestamps
     int32_t max_levels = 0;
     unsigned long long *hash = nullptr; // [hash_cap] (task << 32 | id), ~0 = empty
     int64_t hash_cap = 0;
@@ -118,12 +123,17 @@ struct SearchBufs {
     void *seg_dists = nullptr;
 };
 
+// greedy levels whose phase boundaries are timestamped (wall clock): the
+// kernel start, then per level the ends of expansion, segment scan, regroup
+constexpr int LEVEL_CLOCKS = 64;
+
 enum {
     CTR_QUEUE = 0,     // next query to take
     CTR_ARENA = 1,     // arena cursor
     CTR_TASKS = 2,     // number of expansion tasks
     CTR_OVERFLOW = 3,  // non-zero: some capacity was exceeded
     CTR_LEVELS = 4,    // levels run by the greedy phase
+    CTR_BARRIER = 5,   // arrivals at the greedy kernel's grid barrier
     CTR_COUNT = 8
 };
 

@@ -91,11 +91,15 @@ __device__ __forceinline__ bool seen_insert(uint32_t *tab, uint32_t cs_mask, uin
 // only on the first slot that looked empty.  Within one search a slot only
 // ever changes from empty to a key, so a stale read can only show "empty";
 // the CAS then fails and reveals the key, so the set stays exact.
-__device__ __forceinline__ bool gset_insert(unsigned long long *tab, int64_t cap_mask,
-                                            unsigned long long key, bool &full) {
+__device__ __forceinline__ uint64_t gset_bucket(int64_t cap_mask, unsigned long long key) {
     uint64_t h = (uint64_t)hash32((uint32_t)key ^ hash32((uint32_t)(key >> 32))) * 0x9E3779B97F4A7C15ull;
     h ^= h >> 29;
-    const uint64_t b0 = h & (uint64_t)cap_mask & ~7ull;
+    return h & (uint64_t)cap_mask & ~7ull;
+}
+
+__device__ __forceinline__ bool gset_insert(unsigned long long *tab, int64_t cap_mask,
+                                            unsigned long long key, bool &full) {
+    const uint64_t b0 = gset_bucket(cap_mask, key);
 #pragma unroll 1
     for (int pb = 0; pb < 16; ++pb) {
         const uint64_t b = (b0 + 8ull * (uint64_t)pb) & (uint64_t)cap_mask;
@@ -119,6 +123,48 @@ __device__ __forceinline__ bool gset_insert(unsigned long long *tab, int64_t cap
     }
     full = true;
     return false;
+}
+
+// Two keys at once (either may be absent): both bucket reads, then both
+// CASes, are in flight together.  The first four slots of each bucket decide
+// the common case; anything else takes gset_insert's full probe.
+// -2: key present; 0..3: first empty slot; -1: undecided
+__device__ __forceinline__ int gset_scan4(uint4 w0, uint4 w1, unsigned long long key) {
+    const unsigned long long v[4] = {((unsigned long long)w0.y << 32) | w0.x,
+                                     ((unsigned long long)w0.w << 32) | w0.z,
+                                     ((unsigned long long)w1.y << 32) | w1.x,
+                                     ((unsigned long long)w1.w << 32) | w1.z};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (v[j] == key) return -2;
+        if (v[j] == ~0ull) return j;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void gset_insert2(unsigned long long *tab, int64_t cap_mask,
+                                             unsigned long long keyA, bool okA,
+                                             unsigned long long keyB, bool okB, bool &newA,
+                                             bool &newB, bool &full) {
+    const uint64_t bA = okA ? gset_bucket(cap_mask, keyA) : 0, bB = okB ? gset_bucket(cap_mask, keyB) : 0;
+    const uint4 *pA = reinterpret_cast<const uint4 *>(tab + bA);
+    const uint4 *pB = reinterpret_cast<const uint4 *>(tab + bB);
+    const uint4 a0 = pA[0], a1 = pA[1], b0 = pB[0], b1 = pB[1];
+    const int sA = okA ? gset_scan4(a0, a1, keyA) : -2;
+    const int sB = okB ? gset_scan4(b0, b1, keyB) : -2;
+    unsigned long long oA = 0, oB = 0;
+    if (sA >= 0) oA = atomicCAS(&tab[bA + sA], ~0ull, keyA);
+    if (sB >= 0) oB = atomicCAS(&tab[bB + sB], ~0ull, keyB);
+    newA = false;
+    newB = false;
+    if (okA && sA != -2) {
+        if (sA >= 0 && oA == ~0ull) newA = true;
+        else if (!(sA >= 0 && oA == keyA)) newA = gset_insert(tab, cap_mask, keyA, full);
+    }
+    if (okB && sB != -2) {
+        if (sB >= 0 && oB == ~0ull) newB = true;
+        else if (!(sB >= 0 && oB == keyB)) newB = gset_insert(tab, cap_mask, keyB, full);
+    }
 }
 
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
@@ -865,6 +911,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             if (lane == 0) {
                 a.sb.task_q[t] = (int32_t)q;
                 a.sb.task_cnt[t] = (unsigned long long)written;
+                a.sb.task_prev[t] = (unsigned long long)written;
                 a.sb.task_evals[t] = 0ull;
                 a.sb.task_rechk[t] = 0ull;
                 a.sb.task_expand[t] = expand ? 1 : 0;
@@ -887,34 +934,69 @@ struct GreedyArgs {
     SearchBufs sb;
 };
 
-constexpr int GREEDY_WAVES = 4;     // waves per workgroup
-constexpr int GREEDY_CACHE = 1024;  // per-wave LDS cache of ids known to the global set
-constexpr int GREEDY_STAGE = 256;   // per-wave staged outputs before a global reservation
+// Work layout.  The items of one level are grouped by task: level 0 is
+// written that way by the beam kernel, and each later level is regrouped
+// once it is complete.  Every workgroup expands one contiguous block of a
+// level, so its waves mostly expand points of the same task, and they share
+// one LDS cache of the (task, id) keys they already sent to the global set.
+// Neighbour ids repeat heavily inside a block (points of one ball share most
+// of their neighbours), and the cache keeps those repeats away from the
+// global hash table, whose random probes bound this kernel.
+constexpr int GREEDY_CACHE = 8192;  // workgroup-shared LDS cache of (task, id) keys
+constexpr int GREEDY_STAGE = 128;   // per-wave staged outputs before a global reservation
+constexpr int GREEDY_QUEUE = 192;   // per-wave queue of candidates awaiting distances
 
-template <typename D, typename O> struct GreedyLds {
-    uint32_t ci[GREEDY_WAVES][64];
-    D cd[GREEDY_WAVES][64];
-    uint32_t cache[GREEDY_WAVES][GREEDY_CACHE];
-    uint32_t st_id[GREEDY_WAVES][GREEDY_STAGE];
-    int32_t st_task[GREEDY_WAVES][GREEDY_STAGE];
-    O st_d[GREEDY_WAVES][GREEDY_STAGE];
-    int32_t st_n[GREEDY_WAVES];
+// waves per workgroup (one workgroup per CU): 16, or 8 where the distance
+// code needs more than the 128 registers a 1024-lane workgroup leaves
+template <int DTYPE, int CPL> constexpr int greedy_waves() {
+    return (DTYPE == RR_F32 || DTYPE == RR_BF16X || CPL >= 6) ? 8 : 16;
+}
+
+template <typename D, typename O, int GW> struct GreedyLds {
+    unsigned long long cache[GREEDY_CACHE];
+    uint32_t ci[GW][GREEDY_QUEUE];
+    D cd[GW][GREEDY_QUEUE];
+    uint32_t st_id[GW][GREEDY_STAGE];
+    int32_t st_task[GW][GREEDY_STAGE];
+    O st_d[GW][GREEDY_STAGE];
+    int32_t st_n[GW];
     unsigned long long wg_base;
+    unsigned long long part[GW * 64]; // task-segment scan
 };
 
-// write a wave's staged outputs to items [dst, dst + n); every slot below
-// item_cap is written, so the next level never reads an unwritten item
-template <typename D, typename O>
-__device__ __forceinline__ void greedy_emit(GreedyLds<D, O> &L, int wid, int n, int64_t dst,
+// true if `key` was already in the workgroup cache; otherwise it is added
+// (evicting another key if its probe window is full: the cache may forget)
+__device__ __forceinline__ bool wg_cache_seen(unsigned long long *cache, unsigned long long key) {
+    const uint32_t h = hash32((uint32_t)key ^ hash32((uint32_t)(key >> 32)));
+#pragma unroll 1
+    for (int p = 0; p < 8; ++p) {
+        const uint32_t s = (h + (uint32_t)p) & (GREEDY_CACHE - 1);
+        const unsigned long long v = cache[s];
+        if (v == key) return true;
+        if (v == ~0ull) {
+            const unsigned long long old = atomicCAS(&cache[s], ~0ull, key);
+            if (old == ~0ull) return false;
+            if (old == key) return true;
+        }
+    }
+    cache[h & (GREEDY_CACHE - 1)] = key;
+    return false;
+}
+
+// write a wave's staged outputs to the unsorted next level [dst, dst + n);
+// every slot below item_cap is written, so the regrouping never reads an
+// unwritten item
+template <typename D, typename O, int GW>
+__device__ __forceinline__ void greedy_emit(GreedyLds<D, O, GW> &L, int wid, int n, int64_t dst,
                                             const SearchBufs &sb) {
     const int lane = lane_id();
-    O *idist = (O *)sb.item_dist;
+    O *udist = (O *)sb.u_dist;
     for (int i = lane; i < n; i += 64) {
         const int64_t o = dst + i;
         if (o < sb.item_cap) {
-            sb.item_task[o] = L.st_task[wid][i];
-            sb.item_id[o] = (int32_t)L.st_id[wid][i];
-            idist[o] = L.st_d[wid][i];
+            sb.u_task[o] = L.st_task[wid][i];
+            sb.u_id[o] = (int32_t)L.st_id[wid][i];
+            udist[o] = L.st_d[wid][i];
         }
     }
     // results per task, one atomic per run of equal tasks (runs are contiguous)
@@ -936,23 +1018,128 @@ __device__ __forceinline__ void greedy_emit(GreedyLds<D, O> &L, int wid, int n, 
     if (dst + n > sb.item_cap && lane == 0) atomicOr(&sb.counters[CTR_OVERFLOW], 4ull);
 }
 
+// one workgroup: seg_off[t] = start of task t's items in the next level,
+// from the per-task growth task_cnt - task_prev; resets the scatter cursors
+__device__ void greedy_segments(unsigned long long *part, const SearchBufs &sb, int64_t ntasks,
+                                int64_t next_base) {
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    const int64_t per = (ntasks + nth - 1) / nth;
+    const int64_t lo = min(ntasks, (int64_t)tid * per), hi = min(ntasks, lo + per);
+    unsigned long long s = 0;
+    for (int64_t t = lo; t < hi; ++t) s += sb.task_cnt[t] - sb.task_prev[t];
+    part[tid] = s;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the partial sums
+    for (int off = 1; off < nth; off <<= 1) {
+        const unsigned long long v = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    unsigned long long run = part[tid] - s;
+    for (int64_t t = lo; t < hi; ++t) {
+        const unsigned long long c = sb.task_cnt[t];
+        sb.seg_off[t] = next_base + (int64_t)run;
+        sb.seg_cur[t] = 0ull;
+        run += c - sb.task_prev[t];
+        sb.task_prev[t] = c;
+    }
+}
+
+// regroup the unsorted level [lo, hi) by task into the item arrays; one
+// cursor atomic per run of equal tasks
+template <typename O>
+__device__ void greedy_regroup(const SearchBufs &sb, int64_t lo, int64_t hi) {
+    const int lane = lane_id();
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t tw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const O *ud = (const O *)sb.u_dist;
+    O *idist = (O *)sb.item_dist;
+    for (int64_t c = lo + gw * 64; c < hi; c += tw * 64) {
+        const int64_t i = c + lane;
+        const bool valid = i < hi;
+        const int32_t t = valid ? sb.u_task[i] : -1;
+        const int32_t tprev = __shfl_up(t, 1);
+        const bool head = valid && (lane == 0 || tprev != t);
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long vm = __ballot(valid);
+        unsigned long long o = 0;
+        int hl = 0;
+        if (valid) {
+            hl = 63 - __clzll((long long)(hm & ((2ull << lane) - 1ull)));
+        }
+        if (head) {
+            const unsigned long long later = hm & ~((2ull << lane) - 1ull);
+            const int end = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)vm);
+            o = atomicAdd(&sb.seg_cur[t], (unsigned long long)(end - lane));
+        }
+        const unsigned long long ob = __shfl(o, hl);
+        const int64_t pos = valid ? sb.seg_off[t] + (int64_t)ob + (lane - hl) : -1;
+        if (valid && pos >= lo && pos < hi) {
+            sb.item_task[pos] = t;
+            sb.item_id[pos] = sb.u_id[i];
+            idist[pos] = ud[i];
+        }
+    }
+}
+
+// Grid-wide barrier of a cooperative launch (every workgroup resident):
+// workgroups count their arrivals on one counter that only grows, so the
+// k-th barrier waits for k * gridDim.x arrivals.  The agent-scope release
+// before arriving and acquire after leaving make the workgroup's writes
+// visible to every other workgroup, as a grid sync must; this costs a few
+// microseconds where the cooperative-groups sync costs about 25.  The spin
+// is bounded: past the limit the search is marked as failed (overflow bit
+// 32) instead of waiting forever.
+__device__ __forceinline__ void grid_barrier(unsigned long long *ctr, unsigned long long target,
+                                             unsigned long long *overflow) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1l << 26)) {
+                atomicOr(overflow, 32ull);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
 template <int DTYPE, int CPL, int G>
-__global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
+__global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(GreedyArgs a) {
     using D = typename DistOf<DTYPE>::T;
     using O = typename DistOf<DTYPE>::O;
-    __shared__ GreedyLds<D, O> L;
-    cg::grid_group grid = cg::this_grid();
+    constexpr int GREEDY_WAVES = greedy_waves<DTYPE, CPL>();
+    extern __shared__ __align__(16) uint8_t greedy_smem[];
+    GreedyLds<D, O, GREEDY_WAVES> &L = *reinterpret_cast<GreedyLds<D, O, GREEDY_WAVES> *>(greedy_smem);
+    unsigned long long barriers = 0;
+    auto grid_sync = [&]() {
+        ++barriers;
+        grid_barrier(&a.sb.counters[CTR_BARRIER], barriers * gridDim.x, &a.sb.counters[CTR_OVERFLOW]);
+    };
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * GREEDY_WAVES + wid;
-    const int64_t tw = (int64_t)gridDim.x * GREEDY_WAVES;
     const DevIndex &ix = a.ix;
     const int R = ix.R;
-    uint32_t *ci = L.ci[wid];
-    D *cd = L.cd[wid];
-    uint32_t *cache = L.cache[wid];
+    uint32_t *qi = L.ci[wid]; // candidate queue: ids inserted into the global set
+    D *qd = L.cd[wid];        // their distances once evaluated
     const int64_t hmask = a.sb.hash_cap - 1;
     const int64_t ntasks = (int64_t)a.sb.counters[CTR_TASKS];
+    // phase timestamps (block 0, one lane): kernel start, then per level the
+    // ends of expansion, segment scan and regroup
+    const bool clock_lane = blockIdx.x == 0 && threadIdx.x == 0;
+    auto stamp = [&](int lv, int k) {
+        if (clock_lane && lv < LEVEL_CLOCKS) a.sb.level_clock[1 + 3 * lv + k] = wall_clock64();
+    };
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 1 + 3 * LEVEL_CLOCKS; i += blockDim.x)
+            a.sb.level_clock[i] = i == 0 ? wall_clock64() : 0ull;
     int64_t base = 0;
     int lvl = 0;
     for (; lvl < a.sb.max_levels - 1; ++lvl) {
@@ -960,112 +1147,163 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
                                                        __HIP_MEMORY_SCOPE_AGENT);
         if (cnt == 0) break;
         const int64_t next_base = base + cnt;
+        for (int i = threadIdx.x; i < GREEDY_CACHE; i += blockDim.x) L.cache[i] = ~0ull;
         if (lane == 0) L.st_n[wid] = 0;
-        // a contiguous block of items per wave keeps one task's items together
-        const int64_t per = (cnt + tw - 1) / tw;
-        const int64_t i0 = gw * per, i1 = min(cnt, i0 + per);
-        int32_t cur = -1;
-        bool cur_expand = false;
+        __syncthreads();
+        // this workgroup's block of the level (items beyond item_cap were dropped)
+        const int64_t avail = max((int64_t)0, min(cnt, a.sb.item_cap - base));
+        const int64_t per = (avail + gridDim.x - 1) / gridDim.x;
+        const int64_t i0 = min(avail, (int64_t)blockIdx.x * per), i1 = min(avail, i0 + per);
+
+        // the queue holds candidates of one task, `qtask`, whose query is in qr
+        int qn = 0;
+        int32_t qtask = -1;
         unsigned long long run_evals = 0, run_rechk = 0;
         QThresh th{};
         QueryRegs<DTYPE, CPL, G> qr;
-        const int64_t i_end = min(i1, a.sb.item_cap - base);
-        auto item_ok = [&](int32_t t, int32_t p) {
-            return t >= 0 && t < ntasks && p >= 0 && (int64_t)p < ix.n;
-        };
-        // one-item pipeline: the next item's adjacency row is in flight while
-        // the current item probes the hash set and gathers its rows
-        int32_t t_nx = -1, p_nx = -1, f_nx = -1;
-        if (i0 < i_end) {
-            t_nx = a.sb.item_task[base + i0];
-            p_nx = a.sb.item_id[base + i0];
-            if (item_ok(t_nx, p_nx) && lane < R) f_nx = ix.adj[(size_t)p_nx * (size_t)R + lane];
-        }
-        for (int64_t it = i0; it < i_end; ++it) {
-            const int32_t t = t_nx, p = p_nx;
-            const int32_t f = f_nx;
-            t_nx = -1;
-            p_nx = -1;
-            f_nx = -1;
-            if (it + 1 < i_end) {
-                t_nx = a.sb.item_task[base + it + 1];
-                p_nx = a.sb.item_id[base + it + 1];
-                if (item_ok(t_nx, p_nx) && lane < R) f_nx = ix.adj[(size_t)p_nx * (size_t)R + lane];
+
+        // distances of the queued candidates in one gather; in-range ones are
+        // staged for the next level
+        auto flush = [&]() {
+            const int k = qn;
+            if (k == 0) return;
+            eval_rows<DTYPE, CPL, G>(ix, qr, qi, qd, k);
+            for (int b0 = 0; b0 < k; b0 += 64) {
+                const int i = b0 + lane;
+                bool inr = false;
+                O myd = dmax<O>();
+                uint32_t myi = 0;
+                if (i < k) {
+                    myi = qi[i];
+                    if constexpr (DTYPE == RR_BF16X) {
+                        // approximate distance above hi: provably outside the
+                        // ball; otherwise the exact distance decides
+                        if (qd[i] <= th.hi) {
+                            myd = exact_dist_f32(ix, myi, qr.row);
+                            inr = myd <= th.r;
+                        }
+                    } else {
+                        myd = qd[i];
+                        inr = in_range<D>(qd[i], th);
+                    }
+                }
+                if constexpr (DTYPE == RR_BF16X) {
+                    const int nb = __popcll(__ballot(i < k && qd[i] > th.lo && qd[i] <= th.hi));
+                    run_rechk += (unsigned long long)nb;
+                }
+                const unsigned long long im = __ballot(inr);
+                const int m = __popcll(im);
+                if (m == 0) continue;
+                int sn = L.st_n[wid];
+                if (sn + m > GREEDY_STAGE) {
+                    // stage full: reserve for it now
+                    unsigned long long o = 0;
+                    if (lane == 0) o = atomicAdd(&a.sb.level_cnt[lvl + 1], (unsigned long long)sn);
+                    o = __shfl(o, 0);
+                    greedy_emit(L, wid, sn, next_base + (int64_t)o, a.sb);
+                    wave_sync();
+                    sn = 0;
+                }
+                if (inr) {
+                    const int o = sn + mbcnt(im);
+                    L.st_id[wid][o] = myi;
+                    L.st_task[wid][o] = qtask;
+                    L.st_d[wid][o] = myd;
+                }
+                wave_sync();
+                if (lane == 0) L.st_n[wid] = sn + m;
+                wave_sync();
             }
-            if (!item_ok(t, p)) continue; // never written
-            if (t != cur) {
-                if (cur >= 0 && lane == 0 && run_evals) atomicAdd(&a.sb.task_evals[cur], run_evals);
-                if (cur >= 0 && lane == 0 && run_rechk) atomicAdd(&a.sb.task_rechk[cur], run_rechk);
-                run_evals = 0;
-                run_rechk = 0;
-                cur = t;
-                cur_expand = a.sb.task_expand[t] != 0;
+            qn = 0;
+        };
+        auto close_task = [&]() {
+            if (qtask >= 0 && lane == 0) {
+                if (run_evals) atomicAdd(&a.sb.task_evals[qtask], run_evals);
+                if (run_rechk) atomicAdd(&a.sb.task_rechk[qtask], run_rechk);
+            }
+            run_evals = 0;
+            run_rechk = 0;
+        };
+        // queue the lanes' ids in `mask` (new members of task t's set)
+        auto enqueue = [&](int32_t t, unsigned long long mask, bool mine, int32_t f) {
+            if (t != qtask) {
+                flush();
+                close_task();
+                qtask = t;
                 const int32_t q = a.sb.task_q[t];
                 th = a.sb.qth[q];
                 qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
-                for (int i = lane; i < GREEDY_CACHE; i += 64) cache[i] = RR_EMPTY32;
-                wave_sync();
             }
-            if (!cur_expand) continue; // results only: sorted and emitted later
-            bool full = false, ovf = false;
-            bool cand = false;
-            if (f >= 0 && !seen_insert(cache, GREEDY_CACHE - 1, (uint32_t)f, ovf))
-                cand = gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | (uint32_t)f, full);
-            const unsigned long long cm = __ballot(cand);
-            const int k = __popcll(cm);
-            if (cand) ci[mbcnt(cm)] = (uint32_t)f;
+            if (mine) qi[qn + mbcnt(mask)] = (uint32_t)f;
             wave_sync();
-            if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
-            if (k == 0) continue;
+            const int k = __popcll(mask);
+            qn += k;
             run_evals += (unsigned long long)k;
-            eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
-            bool inr = false;
-            O myd = dmax<O>();
-            uint32_t myi = 0;
-            if (lane < k) {
-                myi = ci[lane];
-                if constexpr (DTYPE == RR_BF16X) {
-                    // approximate distance above hi: provably outside the ball;
-                    // otherwise the exact distance decides
-                    const float sx = cd[lane];
-                    if (sx <= th.hi) {
-                        myd = exact_dist_f32(ix, myi, qr.row);
-                        inr = myd <= th.r;
-                    }
-                } else {
-                    myd = cd[lane];
-                    inr = in_range<D>(cd[lane], th);
+        };
+
+        // item j of this wave is i0 + wid + GREEDY_WAVES * j; items are taken
+        // in pairs.  Item records are loaded two pairs ahead, adjacency rows and
+        // expansion flags one pair ahead.
+        auto load_item = [&](int64_t it, int32_t &t, int32_t &p) {
+            t = -1;
+            p = -1;
+            if (it < i1) {
+                t = a.sb.item_task[base + it];
+                p = a.sb.item_id[base + it];
+                if (!(t >= 0 && t < ntasks && p >= 0 && (int64_t)p < ix.n)) {
+                    t = -1; // never written
+                    p = -1;
                 }
             }
-            if constexpr (DTYPE == RR_BF16X) {
-                const int nb = __popcll(__ballot(lane < k && cd[lane] > th.lo && cd[lane] <= th.hi));
-                run_rechk += (unsigned long long)nb;
+        };
+        auto load_adj = [&](int32_t t, int32_t p, int32_t &f, int &e) {
+            f = -1;
+            e = 0;
+            if (t >= 0) {
+                e = a.sb.task_expand[t];
+                if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
             }
-            const unsigned long long im = __ballot(inr);
-            const int m = __popcll(im);
-            if (m == 0) continue;
-            int sn = L.st_n[wid];
-            if (sn + m > GREEDY_STAGE) {
-                // stage full: reserve for it now
-                unsigned long long o = 0;
-                if (lane == 0) o = atomicAdd(&a.sb.level_cnt[lvl + 1], (unsigned long long)sn);
-                o = __shfl(o, 0);
-                greedy_emit<D, O>(L, wid, sn, next_base + (int64_t)o, a.sb);
-                wave_sync();
-                sn = 0;
-            }
-            if (inr) {
-                const int o = sn + mbcnt(im);
-                L.st_id[wid][o] = myi;
-                L.st_task[wid][o] = t;
-                L.st_d[wid][o] = myd;
-            }
-            wave_sync();
-            if (lane == 0) L.st_n[wid] = sn + m;
-            wave_sync();
+        };
+        const int64_t S = GREEDY_WAVES;
+        int64_t it = i0 + wid;
+        int32_t tA, pA, tB, pB, fA, fB, tA1, pA1, tB1, pB1;
+        int eA, eB;
+        load_item(it, tA, pA);
+        load_item(it + S, tB, pB);
+        load_adj(tA, pA, fA, eA);
+        load_adj(tB, pB, fB, eB);
+        load_item(it + 2 * S, tA1, pA1);
+        load_item(it + 3 * S, tB1, pB1);
+        for (; it < i1; it += 2 * S) {
+            int32_t fA1, fB1, tA2, pA2, tB2, pB2;
+            int eA1, eB1;
+            load_adj(tA1, pA1, fA1, eA1);
+            load_adj(tB1, pB1, fB1, eB1);
+            load_item(it + 4 * S, tA2, pA2);
+            load_item(it + 5 * S, tB2, pB2);
+
+            // this pair: neighbours not yet known to the workgroup cache go to
+            // the global set; the ones inserted now are new members
+            const bool okA = tA >= 0 && eA && fA >= 0;
+            const bool okB = tB >= 0 && eB && fB >= 0;
+            const unsigned long long keyA = ((unsigned long long)(uint32_t)tA << 32) | (uint32_t)fA;
+            const unsigned long long keyB = ((unsigned long long)(uint32_t)tB << 32) | (uint32_t)fB;
+            const bool cA = okA && !wg_cache_seen(L.cache, keyA);
+            const bool cB = okB && !wg_cache_seen(L.cache, keyB);
+            bool nA = false, nB = false, full = false;
+            gset_insert2(a.sb.hash, hmask, keyA, cA, keyB, cB, nA, nB, full);
+            if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
+            const unsigned long long mA = __ballot(nA), mB = __ballot(nB);
+            if (mA) enqueue(tA, mA, nA, fA);
+            if (mB) enqueue(tB, mB, nB, fB);
+            if (qn >= 64) flush();
+
+            tA = tA1; pA = pA1; fA = fA1; eA = eA1;
+            tB = tB1; pB = pB1; fB = fB1; eB = eB1;
+            tA1 = tA2; pA1 = pA2; tB1 = tB2; pB1 = pB2;
         }
-        if (cur >= 0 && lane == 0 && run_evals) atomicAdd(&a.sb.task_evals[cur], run_evals);
-        if (cur >= 0 && lane == 0 && run_rechk) atomicAdd(&a.sb.task_rechk[cur], run_rechk);
+        flush();
+        close_task();
         // one reservation per workgroup for what the waves still hold
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1078,9 +1316,24 @@ __global__ __launch_bounds__(256) void k_greedy(GreedyArgs a) {
             int64_t off = (int64_t)L.wg_base;
             for (int w = 0; w < wid; ++w) off += L.st_n[w];
             const int sn = L.st_n[wid];
-            if (sn > 0) greedy_emit<D, O>(L, wid, sn, next_base + off, a.sb);
+            if (sn > 0) greedy_emit(L, wid, sn, next_base + off, a.sb);
         }
-        grid.sync();
+        grid_sync();
+        stamp(lvl, 0);
+        // regroup the next level by task
+        const int64_t ncnt = (int64_t)__hip_atomic_load(&a.sb.level_cnt[lvl + 1], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        if (ncnt == 0) {
+            ++lvl;
+            break;
+        }
+        if (blockIdx.x == 0) greedy_segments(L.part, a.sb, ntasks, next_base);
+        grid_sync();
+        stamp(lvl, 1);
+        const int64_t stored = max((int64_t)0, min(ncnt, a.sb.item_cap - next_base));
+        greedy_regroup<O>(a.sb, next_base, next_base + stored);
+        grid_sync();
+        stamp(lvl, 2);
         base = next_base;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1393,15 +1646,21 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
     a.ix = ix;
     a.cfg = cfg;
     a.sb = sb;
+    using O = typename DistOf<DTYPE>::O;
     auto kern = k_greedy<DTYPE, CPL, G>;
+    constexpr int GW = greedy_waves<DTYPE, CPL>();
+    const size_t shmem = sizeof(GreedyLds<D, O, GW>);
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, GW * 64, shmem);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    if (per_cu > 8) per_cu = 8;
-    dim3 grid((unsigned)(per_cu * num_cus)), block(256);
+    if (per_cu > 2) per_cu = 2;
+    dim3 grid((unsigned)(per_cu * num_cus)), block(GW * 64);
     void *args[] = {&a};
-    e = hipLaunchCooperativeKernel((const void *)kern, grid, block, args, 0, s);
+    e = hipLaunchCooperativeKernel((const void *)kern, grid, block, args, shmem, s);
     if (e != hipSuccess) return e;
     if (after_kernel) {
         e = hipEventRecord(after_kernel, s);

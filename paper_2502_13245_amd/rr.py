@@ -139,6 +139,9 @@ SIGNATURES = {
     "rr_results_total": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "rr_results_copy": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "rr_results_stats": (C.c_int, [_VP, C.POINTER(QueryStats), C.POINTER(BatchStats)]),
+    "rr_results_level_profile": (C.c_int, [_VP, _I32, C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int32)]),
     "rr_results_free": (None, [_VP]),
     "rr_server_create": (C.c_int, [_VP, C.POINTER(SearchParams), C.POINTER(ServerConfig),
                                    C.POINTER(Allocator), C.POINTER(_VP)]),
@@ -368,7 +371,20 @@ class PendingResults:
                 self._h, st.ctypes.data_as(C.POINTER(QueryStats)) if self.nq else None,
                 C.byref(b)))
             agg = b.as_dict()
+            agg["levels"] = self.level_profile()
         return Results(offsets, ids[:total], dists[:total], st, agg)
+
+    def level_profile(self, max_levels=64):
+        """Per level of the greedy phase: points expanded and the time spent
+        expanding them and regrouping the next level (ms)."""
+        items = (C.c_int64 * max_levels)()
+        exp_ms = (C.c_double * max_levels)()
+        reg_ms = (C.c_double * max_levels)()
+        n = C.c_int32()
+        _check(lib().rr_results_level_profile(self._h, max_levels, items, exp_ms, reg_ms,
+                                              C.byref(n)))
+        return [dict(items=items[i], expand_ms=round(exp_ms[i], 4), regroup_ms=round(reg_ms[i], 4))
+                for i in range(n.value)]
 
 
 def search_params(mode="adaptive", beam=32, es_enable=False, es_visit_limit=20, es_radius=0.0,
