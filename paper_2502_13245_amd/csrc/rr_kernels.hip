@@ -1091,7 +1091,7 @@ __device__ void greedy_regroup(const SearchBufs &sb, int64_t lo, int64_t hi) {
 // visible to every other workgroup, as a grid sync must; this costs a few
 // microseconds where the cooperative-groups sync costs about 25.  The spin
 // is bounded: past the limit the search is marked as failed (overflow bit
-// 32) instead of waiting forever.
+// 64) instead of waiting forever.
 __device__ __forceinline__ void grid_barrier(unsigned long long *ctr, unsigned long long target,
                                              unsigned long long *overflow) {
     __syncthreads();
@@ -1102,7 +1102,7 @@ __device__ __forceinline__ void grid_barrier(unsigned long long *ctr, unsigned l
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1l << 26)) {
-                atomicOr(overflow, 32ull);
+                atomicOr(overflow, 64ull);
                 break;
             }
         }
@@ -1414,16 +1414,15 @@ template <typename D> __global__ void k_scatter(SearchBufs sb) {
 // Sort one segment by (d, id) with the whole workgroup.  Segments that fit
 // in LDS use a bitonic network; longer ones are sorted in runs of that size
 // and merged pairwise through `tmp` (same length) by rank computation.
-constexpr int SORT_LDS = 8192;
 constexpr int SORT_THREADS = 1024;
 
 template <typename D>
 __device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int64_t n, D *sd,
-                                   uint32_t *si) {
+                                   uint32_t *si, int run_len) {
     const int t = threadIdx.x, nt = blockDim.x;
-    // 1) sort runs of SORT_LDS in LDS
-    for (int64_t r0 = 0; r0 < n; r0 += SORT_LDS) {
-        const int m = (int)min((int64_t)SORT_LDS, n - r0);
+    // 1) sort runs of run_len in LDS
+    for (int64_t r0 = 0; r0 < n; r0 += run_len) {
+        const int m = (int)min((int64_t)run_len, n - r0);
         int p2 = 1;
         while (p2 < m) p2 <<= 1;
         for (int i = t; i < p2; i += nt) {
@@ -1467,7 +1466,7 @@ __device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int6
     D *src_d = d, *dst_d = td;
     int32_t *src_i = id, *dst_i = tid_;
     bool in_tmp = false;
-    for (int64_t w = SORT_LDS; w < n; w <<= 1) {
+    for (int64_t w = run_len; w < n; w <<= 1) {
         for (int64_t i = t; i < n; i += nt) {
             const int64_t run = i / w;
             const int64_t a0 = (run & ~1ll) * w;           // left run start
@@ -1516,28 +1515,110 @@ __device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int6
     }
 }
 
+// Segments of up to sort_cap keys are sorted in LDS: every wave sorts
+// 64-key chunks in registers, then merge passes double the sorted runs
+// (each key's output position is its index in its own run plus its rank in
+// the partner run, found by binary search), one barrier per pass.  Keys
+// (distance, id) are unique within a task; padding keys get distinct ids
+// so ranks stay unique.  Longer segments take the global merge path.
+template <typename D> constexpr int sort_cap() { return sizeof(D) == 4 ? 8192 : 4096; }
+
+template <typename D>
+__device__ int lds_sort(D *ad, uint32_t *ai, D *bd, uint32_t *bi, int p) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = lane_id(), wid = tid >> 6, nw = nth >> 6;
+    for (int c = wid; c < (p >> 6); c += nw) {
+        D x = ad[c * 64 + lane];
+        uint32_t xi = ai[c * 64 + lane];
+        wave_sort(x, xi);
+        ad[c * 64 + lane] = x;
+        ai[c * 64 + lane] = xi;
+    }
+    __syncthreads();
+    D *sd = ad, *dd = bd;
+    uint32_t *si = ai, *di = bi;
+    int in_b = 0;
+    for (int w = 64; w < p; w <<= 1) {
+        for (int i = tid; i < p; i += nth) {
+            const int run = i / w;
+            const int a0 = (run & ~1) * w, b0 = a0 + w;
+            const D x = sd[i];
+            const uint32_t xi = si[i];
+            int pos;
+            if (b0 >= p) {
+                pos = i; // no partner run
+            } else {
+                const bool left = (run & 1) == 0;
+                int lo = left ? b0 : a0, hi = left ? min(p, b0 + w) : b0;
+                const int start = lo;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (key_less(sd[mid], si[mid], x, xi)) lo = mid + 1;
+                    else hi = mid;
+                }
+                pos = left ? a0 + (i - a0) + (lo - start) : a0 + (i - b0) + (lo - start);
+            }
+            dd[pos] = x;
+            di[pos] = xi;
+        }
+        __syncthreads();
+        D *td = sd;
+        sd = dd;
+        dd = td;
+        uint32_t *ti = si;
+        si = di;
+        di = ti;
+        in_b ^= 1;
+    }
+    return in_b;
+}
+
 template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort_emit(SearchBufs sb) {
     extern __shared__ __align__(16) uint8_t sort_smem[];
-    D *sd = (D *)sort_smem;
-    uint32_t *si = (uint32_t *)(sort_smem + SORT_LDS * sizeof(D));
+    constexpr int CAP = sort_cap<D>();
+    D *ad = (D *)sort_smem;
+    uint32_t *ai = (uint32_t *)(ad + CAP);
+    D *bd = (D *)(ai + CAP);
+    uint32_t *bi = (uint32_t *)(bd + CAP);
     __shared__ int64_t s_off;
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
     D *segd = (D *)sb.seg_dists;
     D *tmpd = (D *)sb.item_dist;
-    D *ad = (D *)sb.arena_dists;
+    D *outd = (D *)sb.arena_dists;
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
         const int32_t q = sb.task_q[t];
-        block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0, sb.item_id + s0, n, sd, si);
         if (threadIdx.x == 0) s_off = (int64_t)atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)n);
         __syncthreads();
         const int64_t off = s_off;
         const bool ok = off + n <= sb.arena_cap;
-        if (ok) {
-            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-                sb.arena_ids[off + i] = sb.seg_ids[s0 + i];
-                ad[off + i] = segd[s0 + i];
+        if (n <= CAP) {
+            const int p = max(64, (int)((n + 63) & ~63ll));
+            for (int i = threadIdx.x; i < p; i += blockDim.x) {
+                if (i < n) {
+                    ad[i] = segd[s0 + i];
+                    ai[i] = (uint32_t)sb.seg_ids[s0 + i];
+                } else {
+                    ad[i] = dmax<D>();
+                    ai[i] = RR_EMPTY32 - (uint32_t)(i - n);
+                }
             }
+            __syncthreads();
+            const int in_b = lds_sort<D>(ad, ai, bd, bi, p);
+            const D *rd = in_b ? bd : ad;
+            const uint32_t *ri = in_b ? bi : ai;
+            if (ok)
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    sb.arena_ids[off + i] = (int32_t)ri[i];
+                    outd[off + i] = rd[i];
+                }
+        } else {
+            block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0, sb.item_id + s0, n, ad, ai, CAP);
+            if (ok)
+                for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                    sb.arena_ids[off + i] = sb.seg_ids[s0 + i];
+                    outd[off + i] = segd[s0 + i];
+                }
         }
         if (threadIdx.x == 0) {
             sb.res_off[q] = off;
@@ -1577,7 +1658,7 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 // group the items of every task by task, sort each group by (d, id) and
 // append it to the result arena (greedy phase and brute force)
 template <typename D> static hipError_t run_finalize(SearchBufs &sb, hipStream_t s) {
-    const size_t shmem = (size_t)SORT_LDS * (sizeof(D) + 4);
+    const size_t shmem = (size_t)2 * sort_cap<D>() * (sizeof(D) + 4);
     hipError_t e = hipFuncSetAttribute((const void *)k_seg_sort_emit<D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
