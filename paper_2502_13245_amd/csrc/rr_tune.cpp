@@ -140,7 +140,9 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
             top_beam = b;
         }
         if (rec >= target_recall) {
-            if (best_beam < 0 || ms < best_ms) {
+            // a wider beam must be clearly faster (3%) to replace a narrower
+            // one: timing noise alone should not move the choice between runs
+            if (best_beam < 0 || ms < 0.97 * best_ms) {
                 best_beam = b;
                 best_ms = ms;
                 best_rec = rec;
