@@ -80,18 +80,22 @@ def gaussian_mixture_unit(n: int, nq: int, d: int, k: int, sigma: float, seed: i
     """float32 unit-norm mixture: centres g/|g|, points normalize(c + sigma_k z)."""
     r_c, r_s, r_l, r_x, r_ql, r_qx = _streams(seed)
     g = r_c.standard_normal(size=(k, d))
-    centers = g / np.linalg.norm(g, axis=1, keepdims=True)
+    centers = (g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
     scale = sigma * np.exp(r_s.uniform(-spread, spread, size=k)) if spread > 0 else np.full(k, sigma)
+    scale = scale.astype(np.float32)
 
     def draw(m, rl, rx):
+        # noise drawn and combined in float32 (large d x n stays affordable);
+        # the unit normalisation is done in float64
         lab = _labels(rl, k, m, zipf)
         out = np.empty((m, d), dtype=np.float32)
         for a in range(0, m, chunk):
             b = min(m, a + chunk)
-            z = rx.standard_normal(size=(b - a, d))
-            v = centers[lab[a:b]] + scale[lab[a:b], None] * z
-            v /= np.linalg.norm(v, axis=1, keepdims=True)
-            out[a:b] = v.astype(np.float32)
+            v = rx.standard_normal(size=(b - a, d), dtype=np.float32)
+            v *= scale[lab[a:b], None]
+            v += centers[lab[a:b]]
+            nrm = np.sqrt(np.einsum("ij,ij->i", v, v, dtype=np.float64))
+            out[a:b] = v / nrm[:, None].astype(np.float32)
         return out, lab
 
     base, _ = draw(n, r_l, r_x)
@@ -184,6 +188,24 @@ def random_graph_fast(n: int, R: int, seed: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # the workloads used by the tests and the benchmark
 # ---------------------------------------------------------------------------
+
+def shifted_graph(n: int, R: int, seed: int, chunk: int = 1 << 20) -> np.ndarray:
+    """Seeded R-out graph for very large n, generated in O(n R) vector work:
+    row i lists (i + h_i + o_j) mod n with R distinct offsets o_j in
+    [1, n/2) and a per-row shift h_i in [0, n/2), so h_i + o_j lies in
+    [1, n - 1): no self loops and no repeated ids.  No locality at all, like
+    random_graph_fast, at a fraction of its cost."""
+    if n < 4 or R >= n // 2:
+        raise ValueError("shifted_graph needs n >= 4 and R < n / 2")
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5A]))
+    off = rng.choice(np.arange(1, n // 2, dtype=np.int64), size=R, replace=False)
+    adj = np.empty((n, R), np.int32)
+    for s in range(0, n, chunk):
+        i = np.arange(s, min(n, s + chunk), dtype=np.int64)
+        h = rng.integers(0, n // 2, size=len(i), dtype=np.int64)
+        adj[s:s + len(i)] = ((i + h)[:, None] + off[None, :]) % n
+    return adj
+
 
 def config_small_u8(seed: int = 0) -> Workload:
     """10,000 base + 1,000 queries, d=128 uint8, 100-centre mixture (sigma 20,

@@ -117,3 +117,16 @@ def test_library_builder_thread_count_invariant():
     g1 = rr.Index.build(base, R=16, L=32, alpha=1.2, threads=1, seed=11).graph()
     g8 = rr.Index.build(base, R=16, L=32, alpha=1.2, threads=8, seed=11).graph()
     np.testing.assert_array_equal(g1[0], g8[0])
+
+
+def test_shifted_graph_is_a_valid_index_graph():
+    """The fast large-n test graph: no self loops, no repeated ids, ids in
+    range (the library's own validation accepts it)."""
+    n, R = 200_003, 32
+    adj = synth.shifted_graph(n, R, 7)
+    assert adj.shape == (n, R) and adj.min() >= 0 and adj.max() < n
+    assert not (adj == np.arange(n)[:, None]).any()
+    s = np.sort(adj, axis=1)
+    assert not (s[:, 1:] == s[:, :-1]).any()
+    rr.Index.from_graph(np.zeros((n, 2), np.uint8), adj, 0)
+    np.testing.assert_array_equal(adj, synth.shifted_graph(n, R, 7))
