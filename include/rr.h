@@ -221,7 +221,8 @@ typedef struct {
  * the same queries and radii (rr_brute_force).  Keeps mode, early-stop and
  * precision fields of *inout and writes beam, waves_per_group and
  * cache_slots: first the fastest beam (from a fixed ladder) whose range
- * recall (sum |K & K'| / sum |K|, Definition 2.2) is >= target, then the
+ * recall (sum |K & K'| / sum |K|, Definition 2.2) is >= target (a wider
+ * beam replaces a narrower one only if it is at least 3% faster), then the
  * fastest kernel shape for that beam (shapes never change results).  Each
  * setting is timed as the median of `reps` calls with HIP events on
  * `stream`.  If no beam reaches the target the highest-recall one is kept
