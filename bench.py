@@ -234,11 +234,14 @@ def main():
         "es": (dict(es_visit_limit=10, es_radius=radius), [32, 64, 128, 256, 512, 1024, 2048, 4096]),
         "adaptive": (es_kw, [8, 16, 24, 32, 48, 64, 96, 128]),
         "adaptive_noes": (dict(es_enable=False), [8, 16, 24, 32, 48, 64, 96, 128]),
+        "doubling": (dict(max_beam=8192, result_capacity=4_000_000), [4, 8, 16, 32, 64]),
+        "doubling_es": (dict(max_beam=8192, result_capacity=4_000_000, es_enable=True,
+                             es_visit_limit=10, es_radius=radius), [4, 8, 16, 32, 64]),
     }
     best = {}
     curves = {}
     for name, (kw, beams) in sweeps.items():
-        mode = "adaptive" if name.startswith("adaptive") else name
+        mode = name.split("_")[0]
         curves[name] = []
         for b in beams:
             try:
@@ -340,6 +343,8 @@ def main():
         log(f"cpu oracle: {cpu['value']:,.0f} QPS on {threads} threads")
 
     plain = best.get("plain")
+    dbl = max((best[k] for k in ("doubling", "doubling_es") if k in best), key=lambda x: x["qps"],
+              default=None)
     out = {
         "metric": "range QPS at 0.9 range recall (adaptive search, 1 GPU)",
         "value": round(qps, 1),
@@ -367,6 +372,9 @@ def main():
         "plain_beam_at_0.9": plain["beam"] if plain else None,
         "es_qps_at_0.9": round(best["es"]["qps"], 1) if "es" in best else None,
         "adaptive_vs_plain": round(qps / plain["qps"], 2) if plain else None,
+        "doubling_qps_at_0.9": round(dbl["qps"], 1) if dbl else None,
+        "doubling_beam_at_0.9": dbl["beam"] if dbl else None,
+        "adaptive_vs_doubling": round(qps / dbl["qps"], 2) if dbl else None,
         "p50_latency_ms": serving["rates"][-1]["p50_ms"] if serving else None,
         "p99_latency_ms": serving["rates"][-1]["p99_ms"] if serving else None,
         "serving": serving,

@@ -51,8 +51,14 @@ typedef enum { RR_U8 = 0, RR_I8 = 1, RR_F32 = 2 } rr_dtype;
  *  RR_ADAPTIVE Algorithm 6: beam search (with Algorithm 5 when es_enable),
  *              N = in-range points of B; if |N| >= lambda*b the result is
  *              Algorithm 2 (GreedySearch) seeded with N, else N.
- *  RR_DOUBLING Algorithm 3: beam search from S u V with b doubled until
- *              |N| < lambda*b (Algorithm 5 inside when es_enable). */
+ *  RR_DOUBLING Algorithm 3: rounds of beam search from S (every point
+ *              visited so far; the entry at first) with b doubled until
+ *              |N| < lambda*b (Algorithm 5 inside every round when
+ *              es_enable); a round at b >= max_beam that would need another
+ *              doubling ends the search with `truncated` set.  Exact
+ *              precision only; the widest round (the first b*2^k >= max_beam)
+ *              must fit the LDS: max_beam <= 8192 for integer data, 4096 for
+ *              float data (RR_EINVAL otherwise). */
 typedef enum { RR_PLAIN = 0, RR_ES = 1, RR_ADAPTIVE = 2, RR_DOUBLING = 3 } rr_mode;
 
 /* Distance arithmetic of the search on float32 data.
@@ -98,7 +104,7 @@ typedef struct {
     int32_t precision;      /* rr_precision                                */
     double recheck_margin;  /* band half-width, relative to the unsquared radius */
     int64_t max_results_per_query; /* greedy/doubling cap; sets `truncated` */
-    int64_t max_beam;       /* doubling cap on b; sets `truncated`          */
+    int64_t max_beam;       /* doubling cap on b (default 4096); sets `truncated` */
     int64_t result_capacity;/* results the greedy/doubling phases may hold for the
                                whole batch (0 = auto); exceeding it is reported */
     int32_t cache_slots;    /* LDS visited-cache entries per query (pow2, 0 = auto) */
@@ -109,7 +115,9 @@ typedef struct {
 /* Per-query counters written by the search kernels. */
 typedef struct {
     int32_t visits;        /* |V| of the beam phase (all rounds for doubling) */
-    int32_t evals;         /* distance evaluations of the beam phase          */
+    int32_t evals;         /* distance evaluations of the beam phase (doubling:
+                              computed distances; a round reuses the stored
+                              distances of S)                                  */
     int32_t greedy_visits; /* |V| of the greedy phase                         */
     int32_t greedy_evals;  /* distance evaluations of the greedy phase        */
     int32_t count;         /* results returned                                */

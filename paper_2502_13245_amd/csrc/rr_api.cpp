@@ -195,7 +195,7 @@ extern "C" void rr_default_search_params(rr_search_params *p) {
     p->precision = RR_EXACT;
     p->recheck_margin = 0.02;
     p->max_results_per_query = 1 << 20;
-    p->max_beam = 1 << 14;
+    p->max_beam = 4096;
     p->result_capacity = 0;
     p->cache_slots = 0;
     p->waves_per_group = 0;
@@ -453,6 +453,7 @@ extern "C" void rr_results_free(rr_results *res) {
     for (auto &e : res->ev)
         if (e) (void)hipEventDestroy(e);
     res->alloc.release(res->block);
+    res->alloc.release(res->extra);
     delete res;
 }
 
@@ -584,9 +585,13 @@ static rr_status check_radius(double r) {
 rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, SearchCfg *cfg_out,
                              DevIndex *view_out, int32_t *qrow_out, bool *greedy_out) {
     if (sp->mode < RR_PLAIN || sp->mode > RR_DOUBLING) return fail(RR_EINVAL, "unknown mode %d", sp->mode);
-    if (sp->mode == RR_DOUBLING) return fail(RR_EINVAL, "doubling search is not available in this build");
     if (sp->beam < 1 || sp->beam > 4096) return fail(RR_EINVAL, "beam must be in [1, 4096]");
-    const bool es = sp->mode == RR_ES || (sp->mode == RR_ADAPTIVE && sp->es_enable);
+    const bool doubling = sp->mode == RR_DOUBLING;
+    if (doubling && sp->precision != RR_EXACT)
+        return fail(RR_EINVAL, "doubling search runs in exact precision only");
+    if (doubling && sp->max_beam < sp->beam) return fail(RR_EINVAL, "max_beam must be >= beam");
+    if (doubling && ix->n >= (1ll << 30)) return fail(RR_EINVAL, "doubling search needs n < 2^30");
+    const bool es = sp->mode == RR_ES || ((sp->mode == RR_ADAPTIVE || doubling) && sp->es_enable);
     if (es && sp->es_visit_limit < 1) return fail(RR_EINVAL, "es_visit_limit must be >= 1");
     if (es && std::isnan(sp->es_radius)) return fail(RR_EINVAL, "es_radius is NaN");
     if (!(sp->lambda >= 0.0)) return fail(RR_EINVAL, "lambda must be >= 0");
@@ -610,17 +615,30 @@ rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, Sea
     if (cs & (cs - 1)) return fail(RR_EINVAL, "cache_slots must be a power of two");
     if (cs < 64 || cs > 16384) return fail(RR_EINVAL, "cache_slots must be in [64, 16384]");
     cfg.cache_slots = cs;
-    const size_t per_wave = (size_t)(ix->dtype == RR_F32 ? 24 : 16) * sp->beam + 64 * 12 + cs * 4 + 128;
+    // doubling: the widest round is the first beam * 2^k >= max_beam, and
+    // its beam lives in LDS
+    int64_t bcap = sp->beam;
+    if (doubling)
+        while (bcap < sp->max_beam && bcap < (1 << 20)) bcap *= 2;
+    const size_t per_wave = (size_t)(ix->dtype == RR_F32 ? 24 : 16) * bcap + 64 * 12 + cs * 4 + 128;
     const size_t lds_cap = 160 * 1024;
-    if (per_wave > lds_cap) return fail(RR_EINVAL, "beam/cache_slots exceed the LDS of one CU");
+    if (per_wave > lds_cap) {
+        if (doubling)
+            return fail(RR_EINVAL, "max_beam: a doubling round of width %lld does not fit the LDS of "
+                                   "one CU (at most 8192 for integer data, 4096 for float data)",
+                        (long long)bcap);
+        return fail(RR_EINVAL, "beam/cache_slots exceed the LDS of one CU");
+    }
     int waves = sp->waves_per_group;
-    if (waves <= 0) waves = (int)std::max<size_t>(1, std::min<size_t>(4, lds_cap / per_wave));
+    if (waves <= 0) waves = (int)std::max<size_t>(1, std::min<size_t>(doubling ? 2 : 4, lds_cap / per_wave));
     if (waves > 8) return fail(RR_EINVAL, "waves_per_group must be <= 8");
     if (per_wave * waves > lds_cap) return fail(RR_EINVAL, "beam/cache_slots/waves exceed LDS");
     cfg.waves = waves;
     cfg.max_results_per_query = sp->max_results_per_query;
     cfg.max_beam = sp->max_beam;
     cfg.margin = sp->recheck_margin;
+    cfg.lambda = sp->lambda;
+    cfg.bcap = (int32_t)bcap;
 
     // the bf16 pass sends every result list through the sort/emit stage
     const bool approx = sp->precision == RR_BF16_RECHECK;
@@ -655,10 +673,12 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     bool greedy = false;
     rr_status pst = prepare_search(ix, sp, &cfg, &view, &qrow, &greedy);
     if (pst != RR_OK) return pst;
+    const bool doubling = sp->mode == RR_DOUBLING;
     int64_t gcap = 0, hash_cap = 0, item_cap = 0;
-    if (greedy) {
+    if (greedy || doubling)
         gcap = sp->result_capacity > 0 ? sp->result_capacity
                                        : std::min<int64_t>(std::max<int64_t>(nq, 1) * 4096, 1 << 21);
+    if (greedy) {
         item_cap = nq * (int64_t)sp->beam + gcap;
         hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024)); // >= 8 and a power of two
     }
@@ -677,6 +697,19 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
             return fail(RR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
         }                                                                                     \
     } while (0)
+    const int cus = device_cus();
+    // doubling: one S region (every visit of the query's rounds) per wave
+    const int64_t s_cap = 16 * (int64_t)cfg.bcap;
+    if (doubling && nq > 0) {
+        int64_t waves_total = 0;
+        HIP_TRY_R(launch_doubling(view, nq, cfg, sb, nullptr, s_cap, cus, s, &waves_total));
+        const size_t pool = (size_t)waves_total * (size_t)s_cap * (ix->dtype == RR_F32 ? 12 : 8);
+        res->extra = res->alloc.alloc(pool);
+        if (!res->extra) {
+            rr_results_free(res);
+            return fail(RR_ENOMEM, "device allocation of %zu bytes (doubling S regions) failed", pool);
+        }
+    }
     HIP_TRY_R(launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s));
     if (greedy) {
         HIP_TRY_R(launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s));
@@ -688,9 +721,9 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
         HIP_TRY_R(hipEventRecord(res->ev[0], s));
     }
     HIP_TRY_R(launch_prep_queries(view, queries_dev, nq, radius, radius_dev, cfg, sb, s));
-    const int cus = device_cus();
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[1], s));
-    HIP_TRY_R(launch_beam(view, nq, cfg, sb, cus, s));
+    if (doubling) HIP_TRY_R(launch_doubling(view, nq, cfg, sb, res->extra, s_cap, cus, s, nullptr));
+    else HIP_TRY_R(launch_beam(view, nq, cfg, sb, cus, s));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[2], s));
     if (greedy) HIP_TRY_R(launch_greedy(view, nq, cfg, sb, cus, s, res->timing ? res->ev[4] : nullptr));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[3], s));

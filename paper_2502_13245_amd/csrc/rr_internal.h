@@ -81,6 +81,8 @@ struct SearchCfg {
     int64_t max_results_per_query;
     int64_t max_beam;
     double margin;         // relative recheck band
+    double lambda;         // Algorithm 3's stop: |N| < lambda * b
+    int32_t bcap;          // doubling: the widest beam a round can use
 };
 
 // Device-side state of one batched search (all arrays on the device).
@@ -152,6 +154,11 @@ hipError_t launch_beam_slots(const DevIndex &ix, const int32_t *qlist, int64_t n
 hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
                              const double *radius_dev, const int32_t *dst, const SearchCfg &cfg,
                              SearchBufs &sb, BeamState *state, hipStream_t s);
+// doubling search (Algorithm 3); with waves_total set it only reports the
+// number of waves, each of which needs an S region of s_cap entries
+hipError_t launch_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                           void *s_pool, int64_t s_cap, int num_cus, hipStream_t s,
+                           int64_t *waves_total);
 hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                          int num_cus, hipStream_t s, hipEvent_t after_kernel = nullptr);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
@@ -204,6 +211,7 @@ struct rr_results {
     hipStream_t stream = nullptr;
     rr::Allocator alloc;
     void *block = nullptr; // one allocation carved into the buffers below
+    void *extra = nullptr; // doubling: the per-wave S regions
     rr::SearchBufs sb;
     int64_t *offsets = nullptr; // [nq + 1] scanned counts
     void *scan_tmp = nullptr;

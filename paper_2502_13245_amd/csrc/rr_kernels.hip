@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "rr_internal.h"
 
@@ -925,6 +926,295 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// doubling search: Algorithm 3 (with Algorithm 5's stop in every round when
+// enabled), one wavefront per query
+// --------------------------------------------------------------------------
+
+// Each round is Algorithm 1 with width b started from S, the set of points
+// visited in earlier rounds (the entry in round 1).  The search ends when the
+// round's in-range points number fewer than lambda * b; otherwise b doubles,
+// and a round that ends at b >= max_beam marks the result truncated.  A beam
+// started from all of S is trimmed to its b best keys right after its first
+// visit, which takes S's best key, so starting from the b best keys of S
+// gives the same beam; the visited-cache argument of the beam kernel then
+// applies unchanged.  S is kept as the list of visits of every round, with
+// repeats (a repeated point has the same key and is dropped when the list is
+// merged into the beam), in a region of HBM owned by the wave.
+template <typename T> __device__ __forceinline__ T load_l2(const T *p) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+    using U = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
+    const U u = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    T v;
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+
+struct DoublingArgs {
+    DevIndex ix;
+    SearchCfg cfg;
+    SearchBufs sb;
+    int64_t nq;
+    int32_t lds_per_wave;
+    int32_t bcap;      // the widest beam a round can use
+    uint8_t *s_pool;   // per wave: s_cap keys, then s_cap ids
+    int64_t s_cap;
+};
+
+template <int DTYPE, int CPL, int G>
+__global__ __launch_bounds__(512) void k_doubling(DoublingArgs a) {
+    using D = typename DistOf<DTYPE>::T;
+    using O = typename DistOf<DTYPE>::O;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    uint8_t *my = smem + (size_t)wid * a.lds_per_wave;
+    auto al = [](int64_t x) { return (int64_t)((x + 15) & ~15ll); };
+    const int bcap = a.bcap;
+    const int cs = a.cfg.cache_slots;
+    D *const bdA = (D *)my;
+    D *const bdB = (D *)(my + al((int64_t)bcap * sizeof(D)));
+    D *const cd = (D *)(my + 2 * al((int64_t)bcap * sizeof(D)));
+    uint8_t *p2 = my + 2 * al((int64_t)bcap * sizeof(D)) + al(64 * sizeof(D));
+    uint32_t *const biA = (uint32_t *)p2;
+    uint32_t *const biB = (uint32_t *)(p2 + al((int64_t)bcap * 4));
+    uint32_t *const ci = (uint32_t *)(p2 + 2 * al((int64_t)bcap * 4));
+    uint32_t *const htab = (uint32_t *)(p2 + 2 * al((int64_t)bcap * 4) + al(64 * 4));
+    const uint32_t cs_mask = (uint32_t)cs - 1u;
+    const DevIndex &ix = a.ix;
+    const SearchCfg &cfg = a.cfg;
+    const int R = ix.R;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    D *const sd = (D *)(a.s_pool + (size_t)gw * (size_t)a.s_cap * (sizeof(D) + 4));
+    uint32_t *const si = (uint32_t *)(sd + a.s_cap);
+
+    for (;;) {
+        int64_t q = 0;
+        if (lane == 0) q = (int64_t)atomicAdd(&a.sb.counters[CTR_QUEUE], 1ull);
+        q = __shfl(q, 0);
+        if (q >= a.nq) break;
+
+        const QThresh th = a.sb.qth[q];
+        QueryRegs<DTYPE, CPL, G> qr;
+        qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
+
+        D *bd = bdA, *bdo = bdB;
+        uint32_t *bi = biA, *bio = biB;
+        int nB = 0;
+        bool ovf = false, trunc = false, es_any = false;
+        int b = cfg.beam, rounds = 0, cN = 0;
+        int64_t ns = 0, visits_all = 0, evals_all = 0;
+
+        // merge the k (<= 64) candidates held by the lanes into B, trimmed to
+        // b; candidates equal to a key of B or to another candidate are
+        // dropped.  Returns the new position of B[ip] and of the first kept
+        // candidate (for the scan cursor).
+        auto merge = [&](D myd, uint32_t myi, int k, int ip, int &ipnew, int &firstnew) {
+            wave_sort(myd, myi);
+            const D pd = __shfl_up(myd, 1);
+            const uint32_t pi = __shfl_up(myi, 1);
+            int lb = 0;
+            bool keep = false;
+            if (lane < k) {
+                lb = lower_bound_key(bd, bi, nB, myd, myi);
+                keep = !(lb < nB && bd[lb] == myd && (bi[lb] & RR_IDMASK) == myi) &&
+                       !(lane > 0 && pd == myd && pi == myi);
+            }
+            const unsigned long long km = __ballot(keep);
+            const int k2 = __popcll(km);
+            const int r2 = mbcnt(km);
+            wave_sync();
+            if (keep) {
+                cd[r2] = myd;
+                ci[r2] = myi;
+            }
+            wave_sync();
+            const int nB2 = min(b, nB + k2);
+            int ipn = ip;
+            for (int i = lane; i < nB; i += 64) {
+                const D di = bd[i];
+                const uint32_t ii = bi[i];
+                const int np = i + lower_bound_key(cd, ci, k2, di, ii & RR_IDMASK);
+                if (np < b) {
+                    bdo[np] = di;
+                    bio[np] = ii;
+                }
+                if (i == ip) ipn = np;
+            }
+            ipnew = ip >= 0 ? __shfl(ipn, ip & 63) : -1;
+            int fn = 1 << 30;
+            if (keep) {
+                const int np = r2 + lb;
+                if (np < b) {
+                    bdo[np] = myd;
+                    bio[np] = myi;
+                }
+                if (r2 == 0) fn = np;
+            }
+            firstnew = k2 > 0 ? __shfl(fn, __ffsll((long long)km) - 1) : (1 << 30);
+            wave_sync();
+            D *td = bd;
+            bd = bdo;
+            bdo = td;
+            uint32_t *ti = bi;
+            bi = bio;
+            bio = ti;
+            nB = nB2;
+        };
+
+        for (;;) {
+            for (int i = lane; i < cs; i += 64) htab[i] = RR_EMPTY32;
+            wave_sync();
+            nB = 0;
+            int evals = 0;
+            if (rounds == 0) {
+                // B <- S = {entry}
+                if (lane == 0) {
+                    ci[0] = (uint32_t)ix.entry;
+                    seen_insert(htab, cs_mask, (uint32_t)ix.entry, ovf);
+                }
+                wave_sync();
+                eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, 1);
+                if (lane == 0) {
+                    bd[0] = cd[0];
+                    bi[0] = (uint32_t)ix.entry;
+                }
+                wave_sync();
+                nB = 1;
+                evals = 1;
+            } else {
+                // B <- the b best keys of S.  S was written by lane 0; the
+                // stores are completed, then read at L2 (agent-scope loads
+                // bypass the per-CU cache, which may hold an older query's S)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                int ipn, fn;
+                for (int64_t c0 = 0; c0 < ns; c0 += 64) {
+                    const int k = (int)min((int64_t)64, ns - c0);
+                    D myd = dmax<D>();
+                    uint32_t myi = RR_EMPTY32;
+                    if (lane < k) {
+                        myd = load_l2(sd + c0 + lane);
+                        myi = load_l2(si + c0 + lane);
+                    }
+                    merge(myd, myi, k, -1, ipn, fn);
+                }
+            }
+            int cursor = 0, visits = 0;
+            bool es_fired = false;
+            for (;;) {
+                int ip = -1;
+                for (int base = cursor & ~63; base < nB; base += 64) {
+                    const int i = base + lane;
+                    const bool unv = i >= cursor && i < nB && !(bi[i] & RR_VIS);
+                    const unsigned long long m = __ballot(unv);
+                    if (m) {
+                        ip = base + __ffsll((long long)m) - 1;
+                        break;
+                    }
+                }
+                if (ip < 0) break;
+                const D dp = bd[ip];
+                // Algorithm 5 within the round: min_B d > r, v >= vl, d(p*) > esr
+                if (cfg.es_enable && visits >= cfg.vl && !in_range<D>(bd[0], th) &&
+                    beyond_esr<D>(dp, th)) {
+                    es_fired = true;
+                    break;
+                }
+                const uint32_t p = bi[ip] & RR_IDMASK;
+                wave_sync();
+                if (lane == 0) bi[ip] = p | RR_VIS;
+                ++visits;
+                // S <- S u {p*}
+                if (ns < a.s_cap) {
+                    if (lane == 0) {
+                        sd[ns] = dp;
+                        si[ns] = p;
+                    }
+                    ++ns;
+                } else {
+                    trunc = true;
+                }
+                int32_t f = -1;
+                if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
+                bool cand = false;
+                if (f >= 0) cand = !seen_insert(htab, cs_mask, (uint32_t)f, ovf);
+                const unsigned long long cm = __ballot(cand);
+                const int k = __popcll(cm);
+                if (cand) ci[mbcnt(cm)] = (uint32_t)f;
+                wave_sync();
+                evals += k;
+                if (k == 0) {
+                    cursor = ip + 1;
+                    continue;
+                }
+                eval_rows<DTYPE, CPL, G>(ix, qr, ci, cd, k);
+                D myd = dmax<D>();
+                uint32_t myi = RR_EMPTY32;
+                if (lane < k) {
+                    myd = cd[lane];
+                    myi = ci[lane];
+                }
+                wave_sync();
+                int ipnew, firstnew;
+                merge(myd, myi, k, ip, ipnew, firstnew);
+                cursor = min(ipnew + 1, firstnew);
+            }
+            visits_all += visits;
+            evals_all += evals;
+            es_any = es_any || es_fired;
+            ++rounds;
+            cN = 0;
+            for (int base = 0; base < nB; base += 64) {
+                const int i = base + lane;
+                const int c = __popcll(__ballot(i < nB && in_range<D>(bd[i], th)));
+                cN += c;
+                if (c < 64) break;
+            }
+            if ((double)cN < cfg.lambda * (double)b) break;
+            if ((int64_t)b >= cfg.max_beam || 2 * b > bcap) {
+                trunc = true;
+                break;
+            }
+            b *= 2;
+        }
+
+        rr_query_stats st;
+        st.visits = (int32_t)min(visits_all, (int64_t)INT32_MAX);
+        st.evals = (int32_t)min(evals_all, (int64_t)INT32_MAX);
+        st.greedy_visits = 0;
+        st.greedy_evals = 0;
+        st.count = cN;
+        st.final_beam = b;
+        st.es_fired = es_any ? 1 : 0;
+        st.expanded = 0;
+        st.truncated = trunc ? 1 : 0;
+        st.cache_overflow = __ballot(ovf) ? 1 : 0;
+        st.rechecked = 0;
+        st.rounds = rounds;
+        int64_t off = 0;
+        if (lane == 0 && cN > 0) off = (int64_t)atomicAdd(&a.sb.counters[CTR_ARENA], (unsigned long long)cN);
+        off = __shfl(off, 0);
+        if (cN > 0 && off + cN > a.sb.arena_cap) {
+            st.truncated = 1;
+            st.count = 0;
+            if (lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 1ull);
+        } else {
+            O *ad = (O *)a.sb.arena_dists;
+            for (int i = lane; i < cN; i += 64) {
+                a.sb.arena_ids[off + i] = (int32_t)(bi[i] & RR_IDMASK);
+                ad[off + i] = (O)bd[i];
+            }
+        }
+        if (lane == 0) {
+            a.sb.res_off[q] = off;
+            a.sb.res_cnt[q] = st.count;
+            a.sb.stats[q] = st;
+        }
+        wave_sync();
+    }
+}
+
+// --------------------------------------------------------------------------
 // greedy phase: Algorithm 2 for all tasks at once, level-synchronous
 // --------------------------------------------------------------------------
 
@@ -1765,6 +2055,67 @@ static hipError_t dispatch_beam(const DevIndex &ix, int64_t nq, const SearchCfg 
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
     RR_SPLITS(X, RR_BF16X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <int DTYPE, int CPL, int G>
+static hipError_t run_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
+                               SearchBufs &sb, void *s_pool, int64_t s_cap, int num_cus,
+                               hipStream_t s, int64_t *waves_total) {
+    using D = typename DistOf<DTYPE>::T;
+    DoublingArgs a;
+    a.ix = ix;
+    a.cfg = cfg;
+    a.sb = sb;
+    a.nq = nq;
+    a.bcap = cfg.bcap;
+    a.lds_per_wave = beam_lds_bytes<D>(cfg.bcap, cfg.cache_slots);
+    a.s_pool = (uint8_t *)s_pool;
+    a.s_cap = s_cap;
+    const int waves = cfg.waves;
+    const size_t shmem = (size_t)a.lds_per_wave * waves;
+    auto kern = k_doubling<DTYPE, CPL, G>;
+    if (shmem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves * 64, shmem);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int64_t blocks = (int64_t)per_cu * num_cus;
+    const int64_t need = (nq + waves - 1) / waves;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    if (waves_total) {
+        // sizing call: report the grid, launch nothing
+        *waves_total = blocks * waves;
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(waves * 64), shmem, s, a);
+    return hipGetLastError();
+}
+
+// waves_total != nullptr: only report how many waves the launch will use (the
+// size of the per-wave S regions); otherwise launch with that many waves.
+hipError_t launch_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                           void *s_pool, int64_t s_cap, int num_cus, hipStream_t s,
+                           int64_t *waves_total) {
+    if (nq == 0) {
+        if (waves_total) *waves_total = 0;
+        return hipSuccess;
+    }
+    int32_t cpl = 0, g = 0;
+    row_split(ix.row_bytes, &cpl, &g);
+    const int kd = kernel_dtype(ix, cfg);
+#define X(DT, C, GG)                                                                          \
+    if (kd == DT && cpl == C && g == GG)                                                      \
+        return run_doubling<DT, C, GG>(ix, nq, cfg, sb, s_pool, s_cap, num_cus, s, waves_total);
+    RR_SPLITS(X, RR_U8)
+    RR_SPLITS(X, RR_I8)
+    RR_SPLITS(X, RR_F32)
 #undef X
     return hipErrorInvalidValue;
 }

@@ -336,6 +336,7 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     if (scfg->step_budget < 0) return set_error(RR_EINVAL, "step_budget must be >= 0");
     if (scfg->result_capacity < 0) return set_error(RR_EINVAL, "result_capacity must be >= 0");
     if (scfg->max_pending < 0) return set_error(RR_EINVAL, "max_pending must be >= 0");
+    if (sp->mode == RR_DOUBLING) return set_error(RR_EINVAL, "the server runs single-round modes only");
     rr_server *s = new (std::nothrow) rr_server();
     if (!s) return set_error(RR_ENOMEM, "host allocation failed");
     rr_status st = prepare_search(ix, sp, &s->cfg, &s->view, &s->qrow, &s->greedy);

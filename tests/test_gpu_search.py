@@ -75,6 +75,71 @@ def test_adaptive_bit_exact(rr, small_u8, beam, es):
         assert g.stats["expanded"].sum() > 0
 
 
+def _compare_doubling(g, o, label):
+    """Doubling: bit-exact lists plus the counters that fix the rounds (beam
+    evaluation counts differ by definition: a round reuses S's distances)."""
+    off, ids, d = g.numpy()
+    np.testing.assert_array_equal(off, o.offsets, err_msg=f"{label} offsets")
+    np.testing.assert_array_equal(ids, o.ids, err_msg=f"{label} ids")
+    np.testing.assert_array_equal(d.astype(np.int64), o.dists.astype(np.int64),
+                                  err_msg=f"{label} dists")
+    for f in ("visits", "rounds", "final_beam", "truncated", "es_fired", "count"):
+        np.testing.assert_array_equal(g.stats[f], o.stats[f], err_msg=f"{label} {f}")
+
+
+@pytest.mark.parametrize("beam,max_beam,es", [(2, 64, False), (4, 1024, False), (8, 256, True),
+                                              (3, 100, False), (1, 8192, True)])
+def test_doubling_bit_exact(rr, small_u8, beam, max_beam, es):
+    """Algorithm 3: rounds from every point visited so far with b doubled;
+    small max_beam values truncate some queries (compared too)."""
+    kw = dict(es_enable=es, es_visit_limit=10, es_radius=small_u8["r"])
+    flush_print(f"doubling beam={beam} max_beam={max_beam} es={es}")
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="doubling", beam=beam,
+                        max_beam=max_beam, **kw)
+    o = _orc(small_u8, mode=oracle.DOUBLING, beam=beam, max_beam=max_beam, **kw)
+    _compare_doubling(g, o, f"doubling b={beam} max={max_beam}")
+    assert (o.stats["rounds"] > 1).any()
+
+
+def test_doubling_heavy_and_float(rr):
+    """Doubling on queries with thousands of results (many rounds, up to the
+    8192 integer limit) and on float32 data (within the float tolerance)."""
+    w = synth.gaussian_mixture_int(20000, 64, 32, 4, 30.0, 21)
+    adj, entry = oracle.build_vamana(w.base, 16, 32, 1.2, synth.permutation(20000, 3))
+    r = oracle.percentile_radius(w.base, w.queries, 0.1)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    flush_print("doubling heavy")
+    g = rr.range_search(ix, torch.from_numpy(w.queries).cuda(), r, mode="doubling", beam=8,
+                        max_beam=8192, result_capacity=1_000_000)
+    o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=oracle.DOUBLING, beam=8,
+                            max_beam=8192)
+    _compare_doubling(g, o, "doubling heavy")
+    assert o.stats["rounds"].max() >= 8
+    wf = synth.gaussian_mixture_unit(4000, 300, 96, 40, 0.3 / np.sqrt(96), 14, spread=0.3)
+    adjf, ef = oracle.build_vamana(wf.base, 32, 64, 1.2, synth.permutation(4000, 2))
+    rf = oracle.percentile_radius(wf.base, wf.queries, 0.002)
+    ixf = rr.Index.from_graph(wf.base, adjf, ef).to_device("cuda:0")
+    flush_print("doubling f32")
+    gf = rr.range_search(ixf, torch.from_numpy(wf.queries).cuda(), rf, mode="doubling", beam=4,
+                         max_beam=4096)
+    of = oracle.range_search(wf.base, adjf, ef, wf.queries, rf, mode=oracle.DOUBLING, beam=4,
+                             max_beam=4096)
+    compare_float(gf, of, rf, label="doubling f32")
+    np.testing.assert_array_equal(gf.stats["visits"], of.stats["visits"])
+    np.testing.assert_array_equal(gf.stats["rounds"], of.stats["rounds"])
+
+
+def test_doubling_argument_checks(rr, small_u8):
+    with pytest.raises(rr.RRError):  # the widest round would not fit the LDS
+        rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="doubling", beam=8,
+                        max_beam=16384)
+    with pytest.raises(rr.RRError):
+        rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="doubling", beam=8,
+                        max_beam=4)
+    with pytest.raises(rr.RRError):
+        rr.Server(small_u8["ix"], rr.search_params(mode="doubling", beam=8))
+
+
 @pytest.mark.parametrize("waves,cache", [(1, 64), (2, 256), (8, 1024), (4, 4096)])
 def test_kernel_shapes_do_not_change_results(rr, small_u8, waves, cache):
     """A small visited cache forgets ids (more evaluations) but never changes
