@@ -1308,6 +1308,18 @@ __device__ __forceinline__ void greedy_emit(GreedyLds<D, O, GW> &L, int wid, int
     if (dst + n > sb.item_cap && lane == 0) atomicOr(&sb.counters[CTR_OVERFLOW], 4ull);
 }
 
+// in-place inclusive scan of part[0, blockDim.x) by the whole workgroup
+// (Hillis-Steele, log2(blockDim.x) barrier pairs)
+__device__ void block_inclusive_scan(unsigned long long *part) {
+    const int tid = threadIdx.x;
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const unsigned long long v = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+}
+
 // one workgroup: seg_off[t] = start of task t's items in the next level,
 // from the per-task growth task_cnt - task_prev; resets the scatter cursors
 __device__ void greedy_segments(unsigned long long *part, const SearchBufs &sb, int64_t ntasks,
@@ -1320,13 +1332,7 @@ __device__ void greedy_segments(unsigned long long *part, const SearchBufs &sb, 
     for (int64_t t = lo; t < hi; ++t) s += sb.task_cnt[t] - sb.task_prev[t];
     part[tid] = s;
     __syncthreads();
-    // inclusive Hillis-Steele scan of the partial sums
-    for (int off = 1; off < nth; off <<= 1) {
-        const unsigned long long v = tid >= off ? part[tid - off] : 0ull;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
+    block_inclusive_scan(part);
     unsigned long long run = part[tid] - s;
     for (int64_t t = lo; t < hi; ++t) {
         const unsigned long long c = sb.task_cnt[t];
@@ -1642,22 +1648,14 @@ __global__ void k_task_scan(SearchBufs sb) {
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
     const int tid = threadIdx.x;
     const int64_t per = (nt + blockDim.x - 1) / blockDim.x;
-    const int64_t lo = tid * per, hi = min(nt, lo + per);
+    const int64_t lo = min(nt, (int64_t)tid * per), hi = min(nt, lo + per);
     unsigned long long s = 0;
     for (int64_t i = lo; i < hi; ++i) s += sb.task_cnt[i];
     part[tid] = s;
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long run = 0;
-        for (int i = 0; i < (int)blockDim.x; ++i) {
-            unsigned long long v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        sb.seg_off[nt] = (int64_t)run;
-    }
-    __syncthreads();
-    unsigned long long run = part[tid];
+    block_inclusive_scan(part);
+    if (tid == (int)blockDim.x - 1) sb.seg_off[nt] = (int64_t)part[tid];
+    unsigned long long run = part[tid] - s;
     for (int64_t i = lo; i < hi; ++i) {
         sb.seg_off[i] = (int64_t)run;
         run += sb.task_cnt[i];
@@ -2215,20 +2213,40 @@ __global__ void k_scan_add(int64_t *out, int64_t n, const int64_t *tile_sum) {
         out[i] += tile_sum[i / SCAN_TILE];
 }
 
+// CSR copy: workgroup w writes output positions [w * COPY_SPAN, ...), so a
+// query with many results is spread over many workgroups; each position
+// finds its query by binary search among the queries of its span.
+constexpr int COPY_SPAN = 4096;
+
+__device__ int64_t last_le(const int64_t *offsets, int64_t lo, int64_t hi, int64_t x) {
+    // largest q in [lo, hi] with offsets[q] <= x (offsets[lo] <= x assumed)
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <typename DIN, typename DOUT>
-__global__ void k_copy_segments(const int64_t *res_off, const int32_t *res_cnt,
-                                const int64_t *offsets, int64_t nq, const int32_t *aid,
-                                const DIN *ad, int32_t *ids, DOUT *dists) {
-    const int lane = lane_id();
-    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t tw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t q = w; q < nq; q += tw) {
-        const int64_t src = res_off[q], dst = offsets[q];
-        const int32_t c = res_cnt[q];
-        for (int i = lane; i < c; i += 64) {
-            ids[dst + i] = aid[src + i];
-            dists[dst + i] = (DOUT)ad[src + i];
+__global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, int64_t nq,
+                                const int32_t *aid, const DIN *ad, int32_t *ids, DOUT *dists) {
+    __shared__ int64_t s_q[2];
+    const int64_t total = offsets[nq];
+    for (int64_t b0 = (int64_t)blockIdx.x * COPY_SPAN; b0 < total;
+         b0 += (int64_t)gridDim.x * COPY_SPAN) {
+        const int64_t b1 = min(total, b0 + COPY_SPAN);
+        if (threadIdx.x == 0) s_q[0] = last_le(offsets, 0, nq - 1, b0);
+        if (threadIdx.x == 1) s_q[1] = last_le(offsets, 0, nq - 1, b1 - 1);
+        __syncthreads();
+        const int64_t qlo = s_q[0], qhi = s_q[1];
+        for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+            const int64_t q = qlo == qhi ? qlo : last_le(offsets, qlo, qhi, i);
+            const int64_t src = res_off[q] + (i - offsets[q]);
+            ids[i] = aid[src];
+            dists[i] = (DOUT)ad[src];
         }
+        __syncthreads();
     }
 }
 
@@ -2257,15 +2275,16 @@ hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, con
     (void)qpad;
     hipError_t e = launch_scan_counts(res_cnt, nq, offsets, scan_tmp, s);
     if (e != hipSuccess || nq == 0) return e;
-    const int blocks = (int)std::min<int64_t>((nq + 3) / 4, 4096);
+    (void)res_cnt;
+    const int blocks = 2048;
     if (dtype == RR_F32)
         hipLaunchKernelGGL((k_copy_segments<double, float>), dim3(blocks), dim3(256), 0, s,
-                           res_off, res_cnt, offsets, nq, arena_ids, (const double *)arena_dists,
-                           ids, (float *)dists);
+                           res_off, offsets, nq, arena_ids, (const double *)arena_dists, ids,
+                           (float *)dists);
     else
         hipLaunchKernelGGL((k_copy_segments<uint32_t, int32_t>), dim3(blocks), dim3(256), 0, s,
-                           res_off, res_cnt, offsets, nq, arena_ids,
-                           (const uint32_t *)arena_dists, ids, (int32_t *)dists);
+                           res_off, offsets, nq, arena_ids, (const uint32_t *)arena_dists, ids,
+                           (int32_t *)dists);
     return hipGetLastError();
 }
 
