@@ -79,6 +79,8 @@ def _load():
         lib.orc_range_search.argtypes = [vp, C.c_int, i64, i32, C.POINTER(C.c_int32), i32, i32,
                                          vp, i64, dp, C.POINTER(_Params), C.c_int,
                                          C.POINTER(_Result)]
+        lib.orc_es_profile.argtypes = [vp, C.c_int, i64, i32, C.POINTER(C.c_int32), i32, i32, vp,
+                                       i64, dp, i64, i64, C.c_int, vp, vp]
         lib.orc_medoid.restype = C.c_int32
         lib.orc_medoid.argtypes = [vp, C.c_int, i64, i32]
         lib.orc_build_vamana.argtypes = [vp, C.c_int, i64, i32, i32, i32, C.c_double, i32,
@@ -217,6 +219,26 @@ def range_search(base, adj, entry, queries, radius, mode=PLAIN, beam=32, es_enab
     if rc != 0:
         raise ValueError("orc_range_search: invalid arguments")
     return _take(res, True)
+
+
+def es_profile(base, adj, entry, queries, radius, beam, step, threads=None):
+    """Early-stopping metrics of the paper's appendix at visit count `step`
+    of Algorithm 1 (beam `beam`, no stopping rule).  Returns (metrics[nq, 4]
+    = d_visited, d_top1, d_top10, d_start; flags[nq, 2] = reached, found)."""
+    base, queries = _c(base), _c(queries)
+    adj = _c(adj, np.int32)
+    nq = queries.shape[0]
+    r = _radius_array(radius, nq)
+    metrics = np.empty((nq, 4), np.float64)
+    flags = np.empty((nq, 2), np.int8)
+    rc = _load().orc_es_profile(base.ctypes.data, _dtype_code(base), base.shape[0], base.shape[1],
+                                adj.ctypes.data_as(C.POINTER(C.c_int32)), adj.shape[1],
+                                int(entry), queries.ctypes.data, nq,
+                                r.ctypes.data_as(C.POINTER(C.c_double)), int(beam), int(step),
+                                _threads(threads), metrics.ctypes.data, flags.ctypes.data)
+    if rc != 0:
+        raise ValueError("orc_es_profile: invalid arguments")
+    return metrics, flags
 
 
 def medoid(base) -> int:

@@ -265,11 +265,23 @@ typedef struct {
     int es_fired;
 } beam_stats_t;
 
+/* The early-stopping metrics of the paper's appendix, taken when the search
+ * is about to make its (step+1)-th visit (v = step, p* chosen): the distance
+ * of p* (d_visited), the closest and 10th closest distance in B (d_top1,
+ * d_top10; +inf while |B| < 10), the distance of the start point (d_start),
+ * whether B already holds a point within r (found), and whether the search
+ * got that far (reached). */
+typedef struct {
+    int64_t step;
+    double d_visited, d_top1, d_top10, d_start;
+    int reached, found;
+} probe_t;
+
 /* On return, B (sorted by (d, id), |B| <= b once trimmed) and the visited
  * list V in visiting order. */
 static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64_t nS, double r,
                         int64_t b, const es_t *es, scratch_t *sc, clist_t *B, clist_t *V,
-                        beam_stats_t *st) {
+                        beam_stats_t *st, probe_t *probe) {
     const points_t *P = G->P;
     B->n = 0;
     V->n = 0;
@@ -289,6 +301,11 @@ static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64
         cl_push(B, ds, s);
     }
     qsort(B->a, (size_t)B->n, sizeof(cand_t), cand_cmp);
+    if (probe) {
+        probe->reached = 0;
+        probe->found = 0;
+        probe->d_start = B->n ? B->a[0].d : INFINITY; /* the start set is {entry} here */
+    }
     for (;;) {
         /* while B \ V != {}: p* = argmin over B \ V */
         int64_t ip = -1;
@@ -298,6 +315,13 @@ static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64
                 break;
             }
         if (ip < 0) break;
+        if (probe && st->visits == probe->step) {
+            probe->reached = 1;
+            probe->d_visited = B->a[ip].d;
+            probe->d_top1 = B->a[0].d;
+            probe->d_top10 = B->n >= 10 ? B->a[9].d : INFINITY;
+            probe->found = B->a[0].d <= r;
+        }
         /* early stopping (Algorithm 5): min_B d > r, v >= vl, d(p*) > esr */
         if (es && es->enable) {
             double minB = B->a[0].d;
@@ -601,7 +625,7 @@ static void rs_body(void *arg, int64_t qi, int tid) {
         S[0] = c->entry;
         int64_t nN = 0;
         for (;;) {
-            beam_search(&c->G, q, S, nS, r, b, &es, sc, &B, &V, &bs);
+            beam_search(&c->G, q, S, nS, r, b, &es, sc, &B, &V, &bs, NULL);
             st->visits += bs.visits;
             st->evals += bs.evals; /* distinct per round; rounds re-evaluate */
             st->es_fired |= bs.es_fired;
@@ -637,7 +661,7 @@ static void rs_body(void *arg, int64_t qi, int tid) {
         int32_t S0 = c->entry;
         int use_es = (sp->mode == ORC_ES || sp->mode == ORC_ADAPTIVE) && sp->es_enable;
         es.enable = use_es;
-        beam_search(&c->G, q, &S0, 1, r, sp->beam, &es, sc, &B, &V, &bs);
+        beam_search(&c->G, q, &S0, 1, r, sp->beam, &es, sc, &B, &V, &bs, NULL);
         st->visits = bs.visits;
         st->evals = bs.evals;
         st->es_fired = bs.es_fired;
@@ -691,6 +715,71 @@ int orc_range_search(const void *base, int dtype, int64_t n, int32_t d, const in
     free(c.scr);
     res_flatten(res, c.qr);
     free(c.qr);
+    return 0;
+}
+
+/* Early-stopping metrics per query (probe_t) of Algorithm 1 without a
+ * stopping rule, beam b, at visit count `step` (the paper's appendix
+ * histograms are taken the same way).  metrics: nq x 4 doubles (d_visited,
+ * d_top1, d_top10, d_start); flags: nq x 2 (reached, found). */
+typedef struct {
+    graph_t G;
+    const void *queries;
+    const double *radius;
+    int32_t entry;
+    int64_t beam, step;
+    double *metrics;
+    int8_t *flags;
+    scratch_t *scr;
+} ep_ctx_t;
+
+static void ep_body(void *arg, int64_t qi, int tid) {
+    ep_ctx_t *c = (ep_ctx_t *)arg;
+    const points_t *P = c->G.P;
+    scratch_t *sc = &c->scr[tid];
+    const void *q = (const char *)c->queries + (size_t)qi * (size_t)P->d * elem_size(P->dtype);
+    es_t no_es = {0, 0, 0.0};
+    clist_t B = {0}, V = {0};
+    beam_stats_t bs;
+    probe_t pr;
+    memset(&pr, 0, sizeof pr);
+    pr.step = c->step;
+    beam_search(&c->G, q, &c->entry, 1, c->radius[qi], c->beam, &no_es, sc, &B, &V, &bs, &pr);
+    scratch_reset(sc);
+    double *m = c->metrics + 4 * qi;
+    m[0] = pr.reached ? pr.d_visited : NAN;
+    m[1] = pr.reached ? pr.d_top1 : NAN;
+    m[2] = pr.reached ? pr.d_top10 : NAN;
+    m[3] = pr.d_start;
+    c->flags[2 * qi] = (int8_t)pr.reached;
+    c->flags[2 * qi + 1] = (int8_t)(pr.reached && pr.found);
+    free(B.a);
+    free(V.a);
+}
+
+int orc_es_profile(const void *base, int dtype, int64_t n, int32_t d, const int32_t *adj, int32_t R,
+                   int32_t entry, const void *queries, int64_t nq, const double *radius,
+                   int64_t beam, int64_t step, int threads, double *metrics, int8_t *flags) {
+    if (n < 1 || d < 1 || R < 0 || entry < 0 || entry >= n || nq < 0 || beam < 1 || step < 0)
+        return -1;
+    points_t P = {base, dtype, n, d};
+    ep_ctx_t c;
+    c.G.P = &P;
+    c.G.adj = adj;
+    c.G.R = R;
+    c.queries = queries;
+    c.radius = radius;
+    c.entry = entry;
+    c.beam = beam;
+    c.step = step;
+    c.metrics = metrics;
+    c.flags = flags;
+    const int nt = threads < 1 ? 1 : threads;
+    c.scr = (scratch_t *)calloc((size_t)nt, sizeof(scratch_t));
+    for (int t = 0; t < nt; t++) scratch_init(&c.scr[t], n);
+    parallel_for(nq, nt, ep_body, &c);
+    for (int t = 0; t < nt; t++) scratch_free(&c.scr[t]);
+    free(c.scr);
     return 0;
 }
 
@@ -850,7 +939,7 @@ static void insert_body(void *arg, int64_t bi, int tid) {
     clist_t B = {0}, V = {0};
     beam_stats_t bs;
     es_t no_es = {0, 0, 0.0};
-    beam_search(&G, row_ptr(P, p), &c->entry, 1, INFINITY, c->L, &no_es, sc, &B, &V, &bs);
+    beam_search(&G, row_ptr(P, p), &c->entry, 1, INFINITY, c->L, &no_es, sc, &B, &V, &bs, NULL);
     scratch_reset(sc);
     /* candidates C u N_out(p) */
     int64_t nc = V.n + g->R;

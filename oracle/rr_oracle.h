@@ -73,6 +73,13 @@ int orc_range_search(const void *base, int dtype, int64_t n, int32_t d, const in
                      const double *radius, const orc_search_params *sp, int threads,
                      orc_result *res);
 
+/* early-stopping metrics at visit count `step` of Algorithm 1 (no stopping
+ * rule): metrics nq x 4 = d_visited, d_top1, d_top10, d_start (NaN for the
+ * first three if the search ended earlier); flags nq x 2 = reached, found */
+int orc_es_profile(const void *base, int dtype, int64_t n, int32_t d, const int32_t *adj, int32_t R,
+                   int32_t entry, const void *queries, int64_t nq, const double *radius,
+                   int64_t beam, int64_t step, int threads, double *metrics, int8_t *flags);
+
 int32_t orc_medoid(const void *base, int dtype, int64_t n, int32_t d);
 
 int orc_build_vamana(const void *base, int dtype, int64_t n, int32_t d, int32_t R, int32_t L,

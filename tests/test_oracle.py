@@ -432,3 +432,41 @@ def test_pair_dists_and_percentile_match_cdist():
         assert oracle.percentile_radius(base, qs, p) == np.sort(D.ravel())[k - 1]
     nn = np.sort(D.min(1))
     assert oracle.empty_fraction_radius(base, qs, 0.25) == nn[int(np.ceil(0.25 * 30)) - 1]
+
+
+@pytest.mark.parametrize("case", GOLD["es_profile_line10"]["cases"], ids=lambda c: c["name"])
+def test_es_profile_hand_examples(case):
+    """The early-stopping metrics at a fixed step, derived by hand on the
+    10-point line graph."""
+    g = GOLD["line10"]
+    base = np.array(g["points"], np.uint8)
+    adj = np.array(g["adj"], np.int32)
+    q = np.array([g["query"]], np.uint8)
+    m, f = oracle.es_profile(base, adj, g["entry"], q, case["radius"], case["beam"], case["step"])
+    assert f[0].tolist() == [case["reached"], case["found"]]
+    if case["reached"]:
+        top10 = np.inf if case["d_top10"] is None else case["d_top10"]
+        assert m[0].tolist() == [case["d_visited"], case["d_top1"], top10, case["d_start"]]
+    else:
+        assert np.isnan(m[0, :3]).all()
+
+
+def test_es_profile_predicts_the_stop_at_vl():
+    """Algorithm 5 stops exactly at v = vl iff at that step no point of B is
+    within r and d(p*) > esr: the metrics at step vl must predict which
+    queries an early-stopped search ends after vl visits."""
+    rng = np.random.default_rng(4)
+    base = rng.integers(0, 40, size=(600, 6)).astype(np.uint8)
+    queries = rng.integers(0, 40, size=(80, 6)).astype(np.uint8)
+    adj, entry = oracle.build_vamana(base, 12, 24, 1.2, np.arange(600))
+    r = oracle.percentile_radius(base, queries, 0.003)
+    for vl, qt in ((3, 0.3), (6, 0.5), (10, 0.7)):
+        m, f = oracle.es_profile(base, adj, entry, queries, r, 16, vl)
+        open_q = (f[:, 0] == 1) & (f[:, 1] == 0)
+        esr = float(np.quantile(m[open_q, 0], qt))  # a cutoff inside the observed spread
+        es = oracle.range_search(base, adj, entry, queries, r, mode=oracle.ES, beam=16,
+                                 es_visit_limit=vl, es_radius=esr)
+        predicted = (f[:, 0] == 1) & (f[:, 1] == 0) & (m[:, 0] > esr)
+        stopped_at_vl = (es.stats["es_fired"] == 1) & (es.stats["visits"] == vl)
+        np.testing.assert_array_equal(predicted, stopped_at_vl)
+        assert predicted.any() and (open_q & ~predicted).any()
