@@ -266,7 +266,13 @@ def main():
     sp, tune = rr.autotune(ix, q, radius, truth_h, target=args.target, reps=5, mode="adaptive",
                            **es_kw)
     log(f"autotune: {tune}")
-    A = dict(mode="adaptive", beam=sp.beam, recall=tune["recall"],
+    # then Algorithm 5's parameters for that beam, from the early-stopping
+    # metrics (the hand setting vl=10, esr=r competes)
+    sp, es_tune = rr.tune_early_stop(ix, q, radius, truth_h, target=args.target, reps=5, params=sp)
+    es_kw = dict(es_enable=bool(sp.es_enable), es_visit_limit=sp.es_visit_limit,
+                 es_radius=sp.es_radius)
+    log(f"early-stop tuning: {es_tune}")
+    A = dict(mode="adaptive", beam=sp.beam, recall=es_tune["recall"],
              kw=dict(es_kw, waves_per_group=sp.waves_per_group, cache_slots=sp.cache_slots))
     if args.choice:
         json.dump(dict(radius=radius, mode=A["mode"], beam=A["beam"], kw=A["kw"]),
@@ -332,13 +338,14 @@ def main():
             m = min(m, nq - ids_done)
             t = time.perf_counter()
             oracle.range_search(w.base, adj, entry, w.queries[ids_done:ids_done + m], radius,
-                                mode=oracle.ADAPTIVE, beam=A["beam"], es_enable=True,
-                                es_visit_limit=10, es_radius=radius, threads=threads)
+                                mode=oracle.ADAPTIVE, beam=A["beam"],
+                                es_enable=es_kw["es_enable"], es_visit_limit=es_kw["es_visit_limit"],
+                                es_radius=es_kw["es_radius"], threads=threads)
             t_cpu += time.perf_counter() - t
             ids_done += m
             m *= 2
         cpu = dict(value=round(ids_done / t_cpu, 1), unit="queries/s", cores=threads, kind="oracle",
-                   sample=f"first {ids_done} of {nq} queries, adaptive b={A['beam']} with early stop,"
+                   sample=f"first {ids_done} of {nq} queries, adaptive b={A['beam']} with the tuned early stop,"
                           f" {t_cpu:.1f}s")
         log(f"cpu oracle: {cpu['value']:,.0f} QPS on {threads} threads")
 
@@ -360,14 +367,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"u8 d=128, {n} base, {nq} queries, 1000-centre mixture; "
                                f"Vamana R=64 L=128 alpha=1.2; radius at 75% empty queries",
-                   "radius": radius, "beam": A["beam"], "es_visit_limit": 10,
-                   "es_radius": radius, "recall": round(A["recall"], 4),
+                   "radius": radius, "beam": A["beam"], "es_enable": es_kw["es_enable"],
+                   "es_visit_limit": es_kw["es_visit_limit"], "es_radius": es_kw["es_radius"], "recall": round(A["recall"], 4),
                    "result_hist_0_10_1e2_1e3_1e4_1e5": hist, "max_results": int(counts.max())},
         "roofline": dominant,
         "roofline_beam": r_beam,
         "roofline_greedy": r_greedy,
         "cpu_baseline": cpu,
         "autotune": tune,
+        "es_tune": es_tune,
         "plain_qps_at_0.9": round(plain["qps"], 1) if plain else None,
         "plain_beam_at_0.9": plain["beam"] if plain else None,
         "es_qps_at_0.9": round(best["es"]["qps"], 1) if "es" in best else None,

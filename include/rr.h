@@ -213,6 +213,21 @@ rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t n
 rr_status rr_nn_dist(const rr_index *idx, const void *queries_dev, int64_t nq,
                      double *nn_dev, void *stream);
 
+/* Early-stopping metrics (Section 4.3 and the paper's early-stopping
+ * appendix): Algorithm 1 with beam `beam` and no stopping rule over the nq
+ * queries, recording for each query the state when it is about to make its
+ * (step+1)-th visit (v = step, p* chosen):
+ *   metrics_host[4q .. 4q+3] = d_visited = d(p*), d_top1 = min_B d,
+ *     d_top10 = the 10th smallest d in B (+inf while |B| < 10), d_start =
+ *     d(entry); the first three are NaN if the search ended before step;
+ *   flags_host[2q] = reached, flags_host[2q+1] = found (min_B d <= r).
+ * Squared distances, exact precision.  Host outputs; synchronizes.
+ * Errors: RR_EINVAL (arguments), RR_ESTATE (index not on the device). */
+rr_status rr_es_profile(const rr_index *idx, const void *queries_dev, int64_t nq, double radius,
+                        const double *radius_dev, int32_t beam, int32_t step,
+                        double *metrics_host, int8_t *flags_host, const rr_allocator *alloc,
+                        void *stream);
+
 /* ---------------- autotuning (batched search) ---------------- */
 
 typedef struct {
@@ -240,6 +255,34 @@ rr_status rr_autotune(const rr_index *idx, const void *queries_dev, int64_t nq, 
                       int32_t reps, rr_search_params *inout, rr_tune_report *report,
                       const rr_allocator *alloc, void *stream);
 
+typedef struct {
+    int32_t tried;          /* settings timed                              */
+    int32_t es_enable;      /* chosen: 0 if no early stop was better        */
+    int32_t es_visit_limit; /* chosen vl                                    */
+    double es_radius;       /* chosen esr (squared units)                   */
+    double ms;              /* median call time of the choice               */
+    double recall;          /* its range recall against `truth`             */
+    int32_t met_target;
+} rr_es_tune_report;
+
+/* Choose Algorithm 5's parameters for a search (mode, beam and the other
+ * fields of *inout are kept; es_enable, es_visit_limit, es_radius are
+ * written).  For vl in {5, 10, 20, 40} the metrics of rr_es_profile at step
+ * vl give, over the queries that have results (in `truth`) but no point
+ * within r yet, the distances d(p*) an early stop would cut; esr candidates
+ * are their maximum (cuts none of them at vl) and their 99th and 95th
+ * percentiles.  Every candidate, the caller's setting (if it has early
+ * stop enabled) and the search without early stop are timed
+ * (median of `reps`, HIP events) and the fastest one whose range recall
+ * against `truth` reaches the target is kept (else the most accurate).
+ * The paper sets esr by inspecting the same histograms.  Synchronizes.
+ * Errors: RR_EINVAL (NULL, nq < 1, reps < 1, plain mode), those of
+ * rr_range_search. */
+rr_status rr_tune_early_stop(const rr_index *idx, const void *queries_dev, int64_t nq,
+                             double radius, const double *radius_dev, const rr_results *truth,
+                             double target_recall, int32_t reps, rr_search_params *inout,
+                             rr_es_tune_report *report, const rr_allocator *alloc, void *stream);
+
 /* ---------------- serving: continuous batching ---------------- */
 
 /* A server keeps `slots` queries resident on the device.  A host thread runs
@@ -256,10 +299,12 @@ rr_status rr_autotune(const rr_index *idx, const void *queries_dev, int64_t nq, 
 typedef struct rr_server rr_server;
 
 typedef struct {
-    int32_t slots;           /* resident queries (>= 1)                       */
+    int32_t slots;           /* resident queries (>= 1; 0: from hbm_budget)  */
     int32_t step_budget;     /* beam visits per query per tick (0: no limit)  */
     int64_t result_capacity; /* greedy-phase results per tick (0: auto)       */
     int32_t max_pending;     /* queued requests before submit returns EBUSY   */
+    int64_t hbm_budget;      /* with slots = 0: device bytes the server may
+                                use; slots = the most whose buffers fit      */
 } rr_server_config;
 
 typedef struct {
@@ -275,12 +320,18 @@ typedef struct {
 
 typedef struct {
     int64_t ticks, submitted, admitted, completed, pending, resident, max_resident;
-    double busy_s; /* host time spent in ticks */
+    double busy_s;        /* host time spent in ticks */
+    int64_t slots;        /* resident query slots */
+    int64_t device_bytes; /* device memory held by the server */
 } rr_server_info;
 
 /* The server keeps a pointer to the index (which must outlive it), copies
- * the parameters, and allocates all device memory now.  Errors: those of
- * rr_range_search, RR_EINVAL for a bad config. */
+ * the parameters, and allocates all device memory now.  Admission is by
+ * footprint: with cfg->slots = 0 the slot count is the largest whose device
+ * buffers (per slot: padded query, thresholds, stored beam, its share of the
+ * result arena and greedy items; shared per tick: the greedy set and
+ * result_capacity) fit in cfg->hbm_budget bytes.  Errors: those of
+ * rr_range_search, RR_EINVAL for a bad config (or a budget below one slot). */
 rr_status rr_server_create(const rr_index *idx, const rr_search_params *sp,
                            const rr_server_config *cfg, const rr_allocator *alloc,
                            rr_server **out);

@@ -733,6 +733,55 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     return RR_OK;
 }
 
+extern "C" rr_status rr_es_profile(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                   double radius, const double *radius_dev, int32_t beam,
+                                   int32_t step, double *metrics_host, int8_t *flags_host,
+                                   const rr_allocator *alloc, void *stream) {
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
+    if (nq > 0 && (!queries_dev || !metrics_host || !flags_host)) return fail(RR_EINVAL, "NULL buffer");
+    if (step < 0) return fail(RR_EINVAL, "step must be >= 0");
+    if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
+    rr_search_params sp;
+    rr_default_search_params(&sp);
+    sp.mode = RR_PLAIN;
+    sp.beam = beam;
+    SearchCfg cfg{};
+    DevIndex view;
+    int32_t qrow = 0;
+    bool greedy = false;
+    rr_status st = prepare_search(ix, &sp, &cfg, &view, &qrow, &greedy);
+    if (st != RR_OK) return st;
+    rr_results *res = nullptr;
+    st = make_results(ix, view, nq, &sp, false, std::max<int64_t>(nq * (int64_t)beam, 1), 0, 0, qrow,
+                      alloc, stream, &res);
+    if (st != RR_OK) return st;
+    if (nq == 0) {
+        rr_results_free(res);
+        return RR_OK;
+    }
+    res->extra = res->alloc.alloc((size_t)nq * (4 * sizeof(double) + 2));
+    if (!res->extra) {
+        rr_results_free(res);
+        return fail(RR_ENOMEM, "device allocation failed");
+    }
+    double *m = (double *)res->extra;
+    int8_t *f = (int8_t *)(m + 4 * nq);
+    hipStream_t s = (hipStream_t)stream;
+    SearchBufs &sb = res->sb;
+    hipError_t e = launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s);
+    if (e == hipSuccess) e = launch_prep_queries(view, queries_dev, nq, radius, radius_dev, cfg, sb, s);
+    if (e == hipSuccess) e = launch_beam_probe(view, nq, cfg, sb, step, m, f, device_cus(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(metrics_host, m, (size_t)nq * 4 * sizeof(double),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags_host, f, (size_t)nq * 2, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    rr_results_free(res);
+    if (e != hipSuccess) return fail(RR_EHIP, "es profile: %s", hipGetErrorString(e));
+    return RR_OK;
+}
+
 static rr_status brute_force_once(const rr_index *ix, const void *queries_dev, int64_t nq,
                                   double radius, const double *radius_dev,
                                   const rr_allocator *alloc, void *stream, int64_t cap,

@@ -145,6 +145,10 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
                                hipStream_t s);
 hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                        int num_cus, hipStream_t s);
+// the beam kernel recording the early-stopping metrics at visit count `step`
+hipError_t launch_beam_probe(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                             int32_t step, double *metrics, int8_t *flags, int num_cus,
+                             hipStream_t s);
 // serving: the beam kernel over a list of slots, resuming and suspending
 // each slot's state with at most `step_budget` visits per call
 hipError_t launch_beam_slots(const DevIndex &ix, const int32_t *qlist, int64_t nwork,

@@ -572,6 +572,12 @@ struct BeamArgs {
     void *st_d;       // [nq][bcap] keys of the stored beams
     uint32_t *st_i;   // [nq][bcap] ids (| visited bit)
     int32_t step_budget; // visits per call and query (0: run to the end)
+    // early-stopping metrics at visit count probe_step (null: not recorded):
+    // probe_m[q][4] = d_visited, d_top1, d_top10, d_start; probe_f[q][2] =
+    // reached, found
+    int32_t probe_step;
+    double *probe_m;
+    int8_t *probe_f;
 };
 
 template <typename D>
@@ -654,6 +660,15 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             if (lane == 0) {
                 bd[0] = cd[0];
                 bi[0] = (uint32_t)ix.entry;
+                if (a.probe_m) {
+                    const double nan = __builtin_nan("");
+                    a.probe_m[4 * q] = nan;
+                    a.probe_m[4 * q + 1] = nan;
+                    a.probe_m[4 * q + 2] = nan;
+                    a.probe_m[4 * q + 3] = (double)cd[0];
+                    a.probe_f[2 * q] = 0;
+                    a.probe_f[2 * q + 1] = 0;
+                }
             }
             wave_sync();
         }
@@ -674,6 +689,13 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             }
             if (ip < 0) break;
             const D dp = bd[ip];
+            if (a.probe_m && visits == a.probe_step && lane == 0) {
+                a.probe_m[4 * q] = (double)dp;
+                a.probe_m[4 * q + 1] = (double)bd[0];
+                a.probe_m[4 * q + 2] = nB >= 10 ? (double)bd[9] : __builtin_inf();
+                a.probe_f[2 * q] = 1;
+                a.probe_f[2 * q + 1] = in_range<D>(bd[0], th) ? 1 : 0;
+            }
             // Algorithm 5: min_B d > r, v >= vl, d(p*) > esr
             if (cfg.es_enable && visits >= cfg.vl && !in_range<D>(bd[0], th) &&
                 beyond_esr<D>(dp, th)) {
@@ -1967,6 +1989,9 @@ struct SlotArgs {
     void *st_d = nullptr;
     uint32_t *st_i = nullptr;
     int32_t step_budget = 0;
+    int32_t probe_step = 0;
+    double *probe_m = nullptr;
+    int8_t *probe_f = nullptr;
 };
 
 template <int DTYPE, int CPL, int G>
@@ -1984,6 +2009,9 @@ static hipError_t run_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
     a.st_d = sl.st_d;
     a.st_i = sl.st_i;
     a.step_budget = sl.step_budget;
+    a.probe_step = sl.probe_step;
+    a.probe_m = sl.probe_m;
+    a.probe_f = sl.probe_f;
     nq = a.nwork;
     a.bcap = cfg.beam;
     a.lds_per_wave = beam_lds_bytes<D>(cfg.beam, cfg.cache_slots);
@@ -2122,6 +2150,17 @@ hipError_t launch_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, Sea
                        int num_cus, hipStream_t s) {
     if (nq == 0) return hipSuccess;
     return dispatch_beam(ix, nq, cfg, sb, num_cus, s, SlotArgs());
+}
+
+hipError_t launch_beam_probe(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
+                             int32_t step, double *metrics, int8_t *flags, int num_cus,
+                             hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    SlotArgs sl;
+    sl.probe_step = step;
+    sl.probe_m = metrics;
+    sl.probe_f = flags;
+    return dispatch_beam(ix, nq, cfg, sb, num_cus, s, sl);
 }
 
 hipError_t launch_beam_slots(const DevIndex &ix, const int32_t *qlist, int64_t nwork,

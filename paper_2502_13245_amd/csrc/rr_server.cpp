@@ -323,6 +323,58 @@ void destroy_buffers(rr_server *s) {
 
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+struct Caps {
+    int64_t gcap, item_cap, hash_cap, arena_cap;
+};
+
+Caps server_caps(int64_t S, int64_t b, bool greedy, int64_t result_capacity) {
+    Caps c{0, 0, 0, 0};
+    if (greedy) {
+        c.gcap = result_capacity > 0 ? result_capacity : std::min<int64_t>(S * 4096, 1 << 21);
+        c.item_cap = S * b + c.gcap;
+        c.hash_cap = next_pow2(std::max<int64_t>(4 * c.item_cap, 1024));
+    }
+    c.arena_cap = S * b + c.gcap;
+    return c;
+}
+
+// device bytes of a server with S slots (the buffers rr_server_create and
+// the per-search buffers allocate, 256-byte aligned pieces rounded up)
+int64_t server_bytes(int64_t S, int64_t b, bool greedy, int64_t result_capacity, int32_t qrow,
+                     int64_t qbytes, int dsz) {
+    const Caps c = server_caps(S, b, greedy, result_capacity);
+    int64_t t = 0;
+    auto add = [&](int64_t bytes) { t += (int64_t)up256((size_t)std::max<int64_t>(bytes, 1)); };
+    add(S * qrow);
+    add(S * (int64_t)sizeof(QThresh));
+    add(CTR_COUNT * 8);
+    add(S * 8);
+    add(S * 4);
+    add(S * (int64_t)sizeof(rr_query_stats));
+    add(c.arena_cap * 4);
+    add(c.arena_cap * dsz);
+    add((S + 1) * 8);
+    add((int64_t)results_copy_tmp_bytes(S));
+    if (greedy) {
+        add(S * 4);
+        add(S * 8 * 3);
+        add(S);
+        add(c.item_cap * (8 + dsz) * 2); // items and the unsorted level
+        add(4096 * 8);
+        add(c.hash_cap * 8);
+        add((S + 1) * 8 + S * 8 * 2);
+        add(c.item_cap * (4 + dsz));
+        add((1 + 3 * LEVEL_CLOCKS) * 8);
+    }
+    // server buffers: state, stored beams, qlist, staging
+    add(S * (int64_t)sizeof(BeamState));
+    add(S * b * 12);
+    add(S * 4);
+    add(S * qbytes);
+    add(S * 12);
+    return t;
+}
+
 } // namespace
 
 extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params *sp,
@@ -332,7 +384,9 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     *out = nullptr;
     if (!ix || !sp || !scfg) return set_error(RR_EINVAL, "index, params or config is NULL");
     if (!ix->on_device) return set_error(RR_ESTATE, "index is not on the device (rr_index_to_device)");
-    if (scfg->slots < 1 || scfg->slots > (1 << 20)) return set_error(RR_EINVAL, "slots must be in [1, 2^20]");
+    if (scfg->slots < 0 || scfg->slots > (1 << 20)) return set_error(RR_EINVAL, "slots must be in [0, 2^20]");
+    if (scfg->slots == 0 && scfg->hbm_budget <= 0)
+        return set_error(RR_EINVAL, "slots = 0 needs an hbm_budget");
     if (scfg->step_budget < 0) return set_error(RR_EINVAL, "step_budget must be >= 0");
     if (scfg->result_capacity < 0) return set_error(RR_EINVAL, "result_capacity must be >= 0");
     if (scfg->max_pending < 0) return set_error(RR_EINVAL, "max_pending must be >= 0");
@@ -346,6 +400,26 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     }
     s->ix = ix;
     s->S = scfg->slots;
+    if (s->S == 0) {
+        // admission by footprint: the most slots whose buffers fit the budget
+        const int64_t qb = (int64_t)ix->d * (ix->dtype == RR_F32 ? 4 : 1);
+        const int ds = ix->dtype == RR_F32 ? 8 : 4;
+        int64_t lo = 0, hi = 1 << 20;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (server_bytes(mid, sp->beam, s->greedy, scfg->result_capacity, s->qrow, qb, ds) <=
+                scfg->hbm_budget)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        if (lo < 1) {
+            delete s;
+            return set_error(RR_EINVAL, "hbm_budget %lld bytes does not hold one slot",
+                             (long long)scfg->hbm_budget);
+        }
+        s->S = (int32_t)lo;
+    }
     s->step_budget = scfg->step_budget;
     s->max_pending = scfg->max_pending > 0 ? scfg->max_pending : (1 << 20);
     s->qbytes = (int64_t)ix->d * (ix->dtype == RR_F32 ? 4 : 1);
@@ -364,13 +438,10 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     if (e != hipSuccess) return bail(RR_EHIP, "hipStreamCreateWithFlags", e);
 
     const int64_t S = s->S, b = sp->beam;
-    int64_t gcap = 0, item_cap = 0, hash_cap = 0;
-    if (s->greedy) {
-        gcap = scfg->result_capacity > 0 ? scfg->result_capacity : std::min<int64_t>(S * 4096, 1 << 21);
-        item_cap = S * b + gcap;
-        hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024));
-    }
-    const int64_t arena_cap = S * b + gcap;
+    const Caps caps = server_caps(S, b, s->greedy, scfg->result_capacity);
+    const int64_t item_cap = caps.item_cap, hash_cap = caps.hash_cap, arena_cap = caps.arena_cap;
+    s->info.slots = S;
+    s->info.device_bytes = server_bytes(S, b, s->greedy, scfg->result_capacity, s->qrow, s->qbytes, s->dsz);
     st = make_results(ix, s->view, S, sp, s->greedy, arena_cap, item_cap, hash_cap, s->qrow, alloc,
                       s->stream, &s->bufs);
     if (st != RR_OK) {

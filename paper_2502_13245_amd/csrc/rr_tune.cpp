@@ -110,7 +110,8 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
                                  double radius, const double *radius_dev, const rr_results *truth,
                                  double target_recall, int32_t reps, rr_search_params *inout,
                                  rr_tune_report *report, const rr_allocator *alloc, void *stream) {
-    if (!ix || !truth || !inout || nq < 1 || reps < 1) return RR_EINVAL;
+    if (!ix || !truth || !inout || nq < 1 || reps < 1)
+        return rr::set_error(RR_EINVAL, "autotune: NULL argument, nq < 1 or reps < 1");
     Csr gt;
     rr_status st = fetch_ids(truth, nq, stream, &gt);
     if (st != RR_OK) return st;
@@ -183,6 +184,109 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
         report->cache_slots = best_c;
         report->ms = shape_ms;
         report->recall = met ? best_rec : top_rec;
+        report->met_target = met ? 1 : 0;
+    }
+    return RR_OK;
+}
+
+extern "C" rr_status rr_tune_early_stop(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                        double radius, const double *radius_dev,
+                                        const rr_results *truth, double target_recall,
+                                        int32_t reps, rr_search_params *inout,
+                                        rr_es_tune_report *report, const rr_allocator *alloc,
+                                        void *stream) {
+    if (!ix || !truth || !inout || nq < 1 || reps < 1)
+        return rr::set_error(RR_EINVAL, "tune_early_stop: NULL argument, nq < 1 or reps < 1");
+    if (inout->mode == RR_PLAIN)
+        return rr::set_error(RR_EINVAL, "tune_early_stop: plain mode has no stopping rule");
+    Csr gt;
+    rr_status st = fetch_ids(truth, nq, stream, &gt);
+    if (st != RR_OK) return st;
+    int tried = 0;
+    rr_search_params best = *inout, sp = *inout;
+    sp.timing = 0;
+    // the search without early stop (ES mode: its stop is the point, so the
+    // reference is the setting as given)
+    if (sp.mode != RR_ES) sp.es_enable = 0;
+    double best_ms = 0.0, best_rec = 0.0;
+    bool met = false;
+    {
+        Csr found;
+        double ms = 0;
+        st = time_setting(ix, queries_dev, nq, radius, radius_dev, sp, reps, alloc, stream, &ms, &found);
+        if (st != RR_OK) return st;
+        ++tried;
+        best = sp;
+        best_ms = ms;
+        best_rec = recall(gt, found, nq);
+        met = best_rec >= target_recall;
+    }
+    auto consider = [&](const rr_search_params &cand) -> rr_status {
+        Csr found;
+        double ms = 0;
+        rr_status s2 = time_setting(ix, queries_dev, nq, radius, radius_dev, cand, reps, alloc, stream,
+                                    &ms, &found);
+        if (s2 != RR_OK) return s2;
+        ++tried;
+        const double rec = recall(gt, found, nq);
+        const bool ok = rec >= target_recall;
+        if ((ok && (!met || ms < best_ms)) || (!ok && !met && rec > best_rec)) {
+            best = cand;
+            best_ms = ms;
+            best_rec = rec;
+            met = ok;
+        }
+        return RR_OK;
+    };
+    // the caller's own setting competes too
+    if (inout->es_enable && inout->mode != RR_ES) {
+        sp = *inout;
+        sp.timing = 0;
+        st = consider(sp);
+        if (st != RR_OK) return st;
+    }
+    std::vector<double> m((size_t)nq * 4);
+    std::vector<int8_t> f((size_t)nq * 2);
+    for (int vl : {5, 10, 20, 40}) {
+        st = rr_es_profile(ix, queries_dev, nq, radius, radius_dev, inout->beam, vl, m.data(), f.data(),
+                           alloc, stream);
+        if (st != RR_OK) return st;
+        // queries with results that have not found one by step vl: an esr
+        // below their d(p*) would stop them there
+        std::vector<double> open;
+        for (int64_t q = 0; q < nq; ++q)
+            if (gt.off[q + 1] > gt.off[q] && f[2 * q] && !f[2 * q + 1]) open.push_back(m[4 * q]);
+        std::vector<double> cands;
+        if (open.empty()) {
+            cands.push_back(radius_dev ? 0.0 : radius);
+        } else {
+            std::sort(open.begin(), open.end());
+            cands.push_back(open.back()); // stops none of them at step vl
+            for (double qt : {0.99, 0.95}) {
+                const size_t i = (size_t)std::floor(qt * (double)(open.size() - 1));
+                if (open[i] < cands.back()) cands.push_back(open[i]);
+            }
+        }
+        for (double esr : cands) {
+            sp = *inout;
+            sp.timing = 0;
+            sp.es_enable = 1;
+            sp.es_visit_limit = vl;
+            sp.es_radius = esr;
+            st = consider(sp);
+            if (st != RR_OK) return st;
+        }
+    }
+    inout->es_enable = best.es_enable;
+    inout->es_visit_limit = best.es_visit_limit;
+    inout->es_radius = best.es_radius;
+    if (report) {
+        report->tried = tried;
+        report->es_enable = best.es_enable;
+        report->es_visit_limit = best.es_visit_limit;
+        report->es_radius = best.es_radius;
+        report->ms = best_ms;
+        report->recall = best_rec;
         report->met_target = met ? 1 : 0;
     }
     return RR_OK;

@@ -83,9 +83,19 @@ class TuneReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ESTuneReport(C.Structure):
+    _fields_ = [("tried", C.c_int32), ("es_enable", C.c_int32), ("es_visit_limit", C.c_int32),
+                ("es_radius", C.c_double), ("ms", C.c_double), ("recall", C.c_double),
+                ("met_target", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("step_budget", C.c_int32),
-                ("result_capacity", C.c_int64), ("max_pending", C.c_int32)]
+                ("result_capacity", C.c_int64), ("max_pending", C.c_int32),
+                ("hbm_budget", C.c_int64)]
 
 
 class Completion(C.Structure):
@@ -97,7 +107,7 @@ class Completion(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("ticks", "submitted", "admitted", "completed",
                                           "pending", "resident", "max_resident")] + [
-                ("busy_s", C.c_double)]
+                ("busy_s", C.c_double), ("slots", C.c_int64), ("device_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -155,6 +165,11 @@ SIGNATURES = {
     "rr_autotune": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, _VP, C.c_double, _I32,
                               C.POINTER(SearchParams), C.POINTER(TuneReport),
                               C.POINTER(Allocator), _VP]),
+    "rr_tune_early_stop": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, _VP, C.c_double, _I32,
+                                     C.POINTER(SearchParams), C.POINTER(ESTuneReport),
+                                     C.POINTER(Allocator), _VP]),
+    "rr_es_profile": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, _I32, _I32, _VP, _VP,
+                                C.POINTER(Allocator), _VP]),
 }
 
 _lib = None
@@ -475,6 +490,36 @@ def autotune(index: Index, queries, radius, truth: PendingResults, target=0.9, r
     return sp, rep.as_dict()
 
 
+def tune_early_stop(index: Index, queries, radius, truth: PendingResults, target=0.9, reps=3,
+                    params: SearchParams | None = None, stream=None, **kw):
+    """rr_tune_early_stop: Algorithm 5's (vl, esr) for the recall target.
+    Returns (SearchParams, report dict)."""
+    sp = params if params is not None else search_params(**kw)
+    q = queries.contiguous()
+    nq = q.shape[0]
+    r0, rdev, keep = _radius_args(radius, nq, q.device)
+    rep = ESTuneReport()
+    _check(lib().rr_tune_early_stop(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev, truth._h,
+                                    float(target), int(reps), C.byref(sp), C.byref(rep),
+                                    index._alloc.ref(), _stream_handle(stream)))
+    return sp, rep.as_dict()
+
+
+def es_profile(index: Index, queries, radius, beam, step, stream=None):
+    """rr_es_profile: (metrics[nq, 4] = d_visited, d_top1, d_top10, d_start;
+    flags[nq, 2] = reached, found) at visit count `step` of a plain beam
+    search of width `beam`."""
+    q = queries.contiguous()
+    nq = q.shape[0]
+    r0, rdev, keep = _radius_args(radius, nq, q.device)
+    m = np.empty((nq, 4), np.float64)
+    f = np.empty((nq, 2), np.int8)
+    _check(lib().rr_es_profile(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev, int(beam),
+                               int(step), m.ctypes.data, f.ctypes.data, index._alloc.ref(),
+                               _stream_handle(stream)))
+    return m, f
+
+
 def nn_dist(index: Index, queries, stream=None):
     """Squared distance from each query to its nearest base point (torch float64)."""
     import torch
@@ -498,7 +543,7 @@ class Server:
     """
 
     def __init__(self, index: Index, params: SearchParams | None = None, slots=1024,
-                 step_budget=0, result_capacity=0, max_pending=0):
+                 step_budget=0, result_capacity=0, max_pending=0, hbm_budget=0):
         if index.device is None:
             raise RRError(RR_ESTATE, "index is not on the device")
         self.index = index  # the server reads the index's device memory
@@ -507,7 +552,8 @@ class Server:
         self.np_dtype = {U8: np.uint8, I8: np.int8, F32: np.float32}[inf["dtype"]]
         self.dist_dtype = np.float32 if inf["dtype"] == F32 else np.int32
         params = params or search_params()
-        cfg = ServerConfig(int(slots), int(step_budget), int(result_capacity), int(max_pending))
+        cfg = ServerConfig(int(slots), int(step_budget), int(result_capacity), int(max_pending),
+                           int(hbm_budget))
         out = C.c_void_p()
         _check(lib().rr_server_create(index._h, C.byref(params), C.byref(cfg), None,
                                       C.byref(out)))

@@ -332,3 +332,35 @@ def test_autotune_meets_target_and_keeps_results(rr, nav_u8):
     compare_exact(tuned, o, label="tuned")
     bf = oracle.brute_force(ctx["w"].base, ctx["w"].queries, ctx["r"])
     assert abs(oracle.range_recall(bf, o) - rep["recall"]) < 1e-9
+
+
+@pytest.mark.parametrize("beam,step", [(8, 5), (32, 10), (100, 20), (16, 0)])
+def test_es_profile_matches_oracle(rr, small_u8, beam, step):
+    """Early-stopping metrics at a fixed step (d_visited, d_top1, d_top10,
+    d_start, reached, found): bit-exact against the oracle on integer data."""
+    flush_print(f"es profile beam={beam} step={step}")
+    m, f = rr.es_profile(small_u8["ix"], small_u8["q"], small_u8["r"], beam, step)
+    om, of = oracle.es_profile(small_u8["w"].base, small_u8["adj"], small_u8["entry"],
+                               small_u8["w"].queries, small_u8["r"], beam, step)
+    np.testing.assert_array_equal(f, of)
+    np.testing.assert_array_equal(m, om)
+    assert f[:, 0].all() or step > 0
+
+
+def test_tune_early_stop_meets_target(rr, nav_u8):
+    """rr_tune_early_stop picks (vl, esr) from the metrics; the chosen search
+    reaches the recall target by the oracle's own brute force and equals the
+    oracle's search with those parameters."""
+    ctx = nav_u8
+    truth = rr.brute_force_async(ctx["ix"], ctx["q"], ctx["r"])
+    flush_print("tune early stop")
+    sp, rep = rr.tune_early_stop(ctx["ix"], ctx["q"], ctx["r"], truth, target=0.85, reps=2,
+                                 mode="adaptive", beam=16)
+    flush_print(f"  {rep}")
+    assert rep["met_target"] == 1 and rep["tried"] >= 2
+    g = rr.range_search(ctx["ix"], ctx["q"], ctx["r"], params=sp)
+    o = _orc(ctx, mode=oracle.ADAPTIVE, beam=16, es_enable=bool(sp.es_enable),
+             es_visit_limit=sp.es_visit_limit, es_radius=sp.es_radius)
+    compare_exact(g, o, label="tuned es")
+    bf = oracle.brute_force(ctx["w"].base, ctx["w"].queries, ctx["r"])
+    assert oracle.range_recall(bf, o) >= 0.85

@@ -162,3 +162,33 @@ def test_server_errors(rr, nav):
             srv.result(t)
         with pytest.raises(rr.RRError):
             srv.result(accepted[0])  # results are released once fetched
+
+
+def test_admission_by_footprint(rr, nav):
+    """slots = 0: the slot count is the largest whose buffers fit the given
+    device-memory budget; served results are unchanged."""
+    sp = rr.search_params(mode="adaptive", beam=12)
+    with pytest.raises(rr.RRError):
+        rr.Server(nav["ix"], sp, slots=0, hbm_budget=1000)
+    with pytest.raises(rr.RRError):
+        rr.Server(nav["ix"], sp, slots=0)
+    budgets = []
+    for budget in (64 << 20, 256 << 20):
+        with rr.Server(nav["ix"], sp, slots=0, hbm_budget=budget) as srv:
+            inf = srv.info()
+            assert 1 <= inf["slots"] and inf["device_bytes"] <= budget
+            budgets.append(inf["slots"])
+    assert budgets[1] > budgets[0]
+    flush_print(f"footprint admission: slots {budgets}")
+    w = nav["w"]
+    with rr.Server(nav["ix"], sp, slots=0, hbm_budget=64 << 20, step_budget=4) as srv:
+        for qi in range(len(w.queries)):
+            assert srv.submit(w.queries[qi], float(nav["radii"][qi]), qi)
+        srv.drain(timeout=60.0)
+        got = {c.tag: srv.result(c.tag) for c in srv.poll(len(w.queries) + 8)}
+    o = oracle.range_search(w.base, nav["adj"], nav["entry"], w.queries, nav["radii"],
+                            mode=oracle.ADAPTIVE, beam=12)
+    for qi in range(len(w.queries)):
+        oi, od = o.query(qi)
+        np.testing.assert_array_equal(got[qi][0], oi)
+        np.testing.assert_array_equal(got[qi][1].astype(np.int64), od.astype(np.int64))
