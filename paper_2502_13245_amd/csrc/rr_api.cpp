@@ -892,7 +892,7 @@ extern "C" rr_status rr_results_total(const rr_results *res, int64_t *total) {
     int64_t tot = 0;
     HIP_TRY(hipMemcpy(&tot, res->offsets + res->nq, sizeof tot, hipMemcpyDeviceToHost));
     *total = tot;
-    if (ctr[CTR_OVERFLOW] & 64ull)
+    if (ctr[CTR_OVERFLOW] & OVERFLOW_BARRIER)
         return fail(RR_EHIP, "the greedy phase's grid barrier timed out");
     if (ctr[CTR_OVERFLOW])
         return fail(RR_ENOMEM,

@@ -129,6 +129,12 @@ struct SearchBufs {
 // kernel start, then per level the ends of expansion, segment scan, regroup
 constexpr int LEVEL_CLOCKS = 64;
 
+// bits of counters[CTR_OVERFLOW]: 1 beam results beyond the arena, 2 / 4
+// greedy items beyond item_cap, 8 the (task, id) set full, 16 too many
+// levels, 32 finalized results beyond the arena, 64 brute-force hits beyond
+// their capacity, OVERFLOW_BARRIER a grid barrier that gave up waiting
+constexpr unsigned long long OVERFLOW_BARRIER = 256ull;
+
 enum {
     CTR_QUEUE = 0,     // next query to take
     CTR_ARENA = 1,     // arena cursor

@@ -1409,7 +1409,7 @@ __device__ void greedy_regroup(const SearchBufs &sb, int64_t lo, int64_t hi) {
 // visible to every other workgroup, as a grid sync must; this costs a few
 // microseconds where the cooperative-groups sync costs about 25.  The spin
 // is bounded: past the limit the search is marked as failed (overflow bit
-// 64) instead of waiting forever.
+// 256) instead of waiting forever.
 __device__ __forceinline__ void grid_barrier(unsigned long long *ctr, unsigned long long target,
                                              unsigned long long *overflow) {
     __syncthreads();
@@ -1420,7 +1420,7 @@ __device__ __forceinline__ void grid_barrier(unsigned long long *ctr, unsigned l
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1l << 26)) {
-                atomicOr(overflow, 64ull);
+                atomicOr(overflow, OVERFLOW_BARRIER);
                 break;
             }
         }
@@ -2255,7 +2255,7 @@ __global__ void k_scan_add(int64_t *out, int64_t n, const int64_t *tile_sum) {
 // CSR copy: workgroup w writes output positions [w * COPY_SPAN, ...), so a
 // query with many results is spread over many workgroups; each position
 // finds its query by binary search among the queries of its span.
-constexpr int COPY_SPAN = 4096;
+constexpr int COPY_SPAN = 1024;
 
 __device__ int64_t last_le(const int64_t *offsets, int64_t lo, int64_t hi, int64_t x) {
     // largest q in [lo, hi] with offsets[q] <= x (offsets[lo] <= x assumed)

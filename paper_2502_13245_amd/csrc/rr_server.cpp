@@ -185,7 +185,7 @@ hipError_t tick_device(rr_server *s, int32_t admitted, int32_t nwork) {
         if (e != hipSuccess) return e;
     }
     if (s->greedy) s->hash_dirty = s->h_ctr[CTR_TASKS] > 0;
-    if (s->h_ctr[CTR_OVERFLOW] & 64ull) return hipErrorLaunchTimeOut; // grid barrier gave up
+    if (s->h_ctr[CTR_OVERFLOW] & OVERFLOW_BARRIER) return hipErrorLaunchTimeOut; // grid barrier gave up
     return hipSuccess;
 }
 
