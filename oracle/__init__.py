@@ -44,7 +44,15 @@ def build(force: bool = True) -> str:
 class _Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("beam", C.c_int32), ("es_enable", C.c_int32),
                 ("es_visit_limit", C.c_int32), ("es_radius", C.c_double),
-                ("lam", C.c_double), ("max_beam", C.c_int64)]
+                ("lam", C.c_double), ("max_beam", C.c_int64), ("metric", C.c_int32)]
+
+
+L2, IP = 0, 1
+_METRICS = {"l2": L2, "ip": IP}
+
+
+def _metric(m) -> int:
+    return _METRICS[m] if isinstance(m, str) else int(m)
 
 
 class _Stats(C.Structure):
@@ -71,16 +79,16 @@ def _load():
         lib = C.CDLL(_LIB)
         vp, i64, i32, dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
         lib.orc_dist.restype = C.c_double
-        lib.orc_dist.argtypes = [C.c_int, vp, vp, i32]
+        lib.orc_dist.argtypes = [C.c_int, vp, vp, i32, C.c_int]
         lib.orc_brute_force.argtypes = [vp, C.c_int, i64, i32, vp, i64, dp, C.c_int,
-                                        C.POINTER(_Result)]
-        lib.orc_nn_dist.argtypes = [vp, C.c_int, i64, i32, vp, i64, C.c_int, dp]
-        lib.orc_pair_dists.argtypes = [vp, C.c_int, i64, i32, vp, i64, C.c_int, dp]
+                                        C.POINTER(_Result), C.c_int]
+        lib.orc_nn_dist.argtypes = [vp, C.c_int, i64, i32, vp, i64, C.c_int, dp, C.c_int]
+        lib.orc_pair_dists.argtypes = [vp, C.c_int, i64, i32, vp, i64, C.c_int, dp, C.c_int]
         lib.orc_range_search.argtypes = [vp, C.c_int, i64, i32, C.POINTER(C.c_int32), i32, i32,
                                          vp, i64, dp, C.POINTER(_Params), C.c_int,
                                          C.POINTER(_Result)]
         lib.orc_es_profile.argtypes = [vp, C.c_int, i64, i32, C.POINTER(C.c_int32), i32, i32, vp,
-                                       i64, dp, i64, i64, C.c_int, vp, vp]
+                                       i64, dp, i64, i64, C.c_int, vp, vp, C.c_int]
         lib.orc_medoid.restype = C.c_int32
         lib.orc_medoid.argtypes = [vp, C.c_int, i64, i32]
         lib.orc_build_vamana.argtypes = [vp, C.c_int, i64, i32, i32, i32, C.c_double, i32,
@@ -165,15 +173,17 @@ def _radius_array(radius, nq):
     return np.ascontiguousarray(r)
 
 
-def dist(a: np.ndarray, b: np.ndarray) -> float:
-    """Squared L2 of two vectors (exact for integer data, FP64 for float32)."""
+def dist(a: np.ndarray, b: np.ndarray, metric="l2") -> float:
+    """Squared L2 (or, with metric="ip", the negated inner product) of two
+    vectors (exact for integer data, FP64 for float32)."""
     a, b = _c(a), _c(b)
     if a.dtype != b.dtype or a.shape != b.shape:
         raise ValueError("dtype/shape mismatch")
-    return _load().orc_dist(_dtype_code(a), a.ctypes.data, b.ctypes.data, a.shape[-1])
+    return _load().orc_dist(_dtype_code(a), a.ctypes.data, b.ctypes.data, a.shape[-1],
+                            _metric(metric))
 
 
-def brute_force(base, queries, radius, threads=None) -> Result:
+def brute_force(base, queries, radius, threads=None, metric="l2") -> Result:
     """Definition 2.1 by enumeration: K_q = {p : d(p, q) <= r_q}."""
     base, queries = _c(base), _c(queries)
     nq = queries.shape[0]
@@ -182,19 +192,19 @@ def brute_force(base, queries, radius, threads=None) -> Result:
     rc = _load().orc_brute_force(base.ctypes.data, _dtype_code(base), base.shape[0], base.shape[1],
                                  queries.ctypes.data, nq,
                                  r.ctypes.data_as(C.POINTER(C.c_double)), _threads(threads),
-                                 C.byref(res))
+                                 C.byref(res), _metric(metric))
     if rc != 0:
         raise ValueError("orc_brute_force: invalid arguments")
     return _take(res, False)
 
 
-def nn_dist(base, queries, threads=None) -> np.ndarray:
-    """Squared distance from each query to its nearest base point."""
+def nn_dist(base, queries, threads=None, metric="l2") -> np.ndarray:
+    """Distance from each query to its nearest base point."""
     base, queries = _c(base), _c(queries)
     out = np.zeros(queries.shape[0], dtype=np.float64)
     rc = _load().orc_nn_dist(base.ctypes.data, _dtype_code(base), base.shape[0], base.shape[1],
                              queries.ctypes.data, queries.shape[0], _threads(threads),
-                             out.ctypes.data_as(C.POINTER(C.c_double)))
+                             out.ctypes.data_as(C.POINTER(C.c_double)), _metric(metric))
     if rc != 0:
         raise ValueError("orc_nn_dist: invalid arguments")
     return out
@@ -202,14 +212,14 @@ def nn_dist(base, queries, threads=None) -> np.ndarray:
 
 def range_search(base, adj, entry, queries, radius, mode=PLAIN, beam=32, es_enable=False,
                  es_visit_limit=20, es_radius=0.0, lam=1.0, max_beam=1 << 20,
-                 threads=None) -> Result:
+                 threads=None, metric="l2") -> Result:
     """Graph range search: mode PLAIN / ES / ADAPTIVE / DOUBLING (Algorithms 1-6)."""
     base, queries = _c(base), _c(queries)
     adj = _c(adj, np.int32)
     nq = queries.shape[0]
     r = _radius_array(radius, nq)
     p = _Params(int(mode), int(beam), int(bool(es_enable) or mode == ES), int(es_visit_limit),
-                float(es_radius), float(lam), int(max_beam))
+                float(es_radius), float(lam), int(max_beam), _metric(metric))
     res = _Result()
     rc = _load().orc_range_search(base.ctypes.data, _dtype_code(base), base.shape[0],
                                   base.shape[1], adj.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -221,7 +231,7 @@ def range_search(base, adj, entry, queries, radius, mode=PLAIN, beam=32, es_enab
     return _take(res, True)
 
 
-def es_profile(base, adj, entry, queries, radius, beam, step, threads=None):
+def es_profile(base, adj, entry, queries, radius, beam, step, threads=None, metric="l2"):
     """Early-stopping metrics of the paper's appendix at visit count `step`
     of Algorithm 1 (beam `beam`, no stopping rule).  Returns (metrics[nq, 4]
     = d_visited, d_top1, d_top10, d_start; flags[nq, 2] = reached, found)."""
@@ -235,7 +245,8 @@ def es_profile(base, adj, entry, queries, radius, beam, step, threads=None):
                                 adj.ctypes.data_as(C.POINTER(C.c_int32)), adj.shape[1],
                                 int(entry), queries.ctypes.data, nq,
                                 r.ctypes.data_as(C.POINTER(C.c_double)), int(beam), int(step),
-                                _threads(threads), metrics.ctypes.data, flags.ctypes.data)
+                                _threads(threads), metrics.ctypes.data, flags.ctypes.data,
+                                _metric(metric))
     if rc != 0:
         raise ValueError("orc_es_profile: invalid arguments")
     return metrics, flags
@@ -298,29 +309,29 @@ def range_recall(truth: Result, found: Result) -> float:
     return float("nan") if tot == 0 else hit / tot
 
 
-def pair_dists(base, queries, threads=None) -> np.ndarray:
-    """All query-base squared distances as an nq x n float64 matrix."""
+def pair_dists(base, queries, threads=None, metric="l2") -> np.ndarray:
+    """All query-base distances as an nq x n float64 matrix."""
     base, queries = _c(base), _c(queries)
     out = np.empty((queries.shape[0], base.shape[0]), dtype=np.float64)
     rc = _load().orc_pair_dists(base.ctypes.data, _dtype_code(base), base.shape[0], base.shape[1],
                                 queries.ctypes.data, queries.shape[0], _threads(threads),
-                                out.ctypes.data_as(C.POINTER(C.c_double)))
+                                out.ctypes.data_as(C.POINTER(C.c_double)), _metric(metric))
     if rc != 0:
         raise ValueError("orc_pair_dists: invalid arguments")
     return out
 
 
-def percentile_radius(base, queries, p, threads=None) -> float:
-    """Inverted-CDF radius: the k-th smallest of all nq*n squared distances,
+def percentile_radius(base, queries, p, threads=None, metric="l2") -> float:
+    """Inverted-CDF radius: the k-th smallest of all nq*n distances,
     k = ceil(p * nq * n).  Enumerates every pair (moderate inputs only)."""
-    ds = pair_dists(base, queries, threads).ravel()
+    ds = pair_dists(base, queries, threads, metric).ravel()
     k = max(1, math.ceil(p * ds.size))
     return float(np.partition(ds, k - 1)[k - 1])
 
 
-def empty_fraction_radius(base, queries, nonempty_frac, threads=None) -> float:
+def empty_fraction_radius(base, queries, nonempty_frac, threads=None, metric="l2") -> float:
     """Radius that leaves at least `nonempty_frac` of queries non-empty: the
     ceil(f * nq)-th smallest per-query nearest-neighbour distance."""
-    nn = np.sort(nn_dist(base, queries, threads))
+    nn = np.sort(nn_dist(base, queries, threads, metric))
     k = max(1, math.ceil(nonempty_frac * len(nn)))
     return float(nn[k - 1])

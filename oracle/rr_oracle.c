@@ -54,6 +54,7 @@ typedef struct {
     int dtype;
     int64_t n;
     int32_t d;
+    int metric; /* ORC_L2 (squared Euclidean) or ORC_IP (negative inner product) */
 } points_t;
 
 static double dist_rows(int dtype, const void *a, const void *b, int32_t d) {
@@ -90,8 +91,34 @@ static const void *row_ptr(const points_t *P, int64_t i) {
     return (const char *)P->base + (size_t)i * (size_t)P->d * elem_size(P->dtype);
 }
 
-double orc_dist(int dtype, const void *a, const void *b, int32_t d) {
-    return dist_rows(dtype, a, b, d);
+/* inner-product "distance" (Section 2: the inner-product datasets): the
+ * negated dot product, so that smaller is closer and membership is still
+ * d <= r; exact int64 for uint8/int8, FP64 for float32 */
+static double dist_ip(int dtype, const void *a, const void *b, int32_t d) {
+    if (dtype == ORC_U8) {
+        const uint8_t *x = (const uint8_t *)a, *y = (const uint8_t *)b;
+        int64_t s = 0;
+        for (int32_t i = 0; i < d; i++) s += (int64_t)x[i] * (int64_t)y[i];
+        return (double)-s;
+    } else if (dtype == ORC_I8) {
+        const int8_t *x = (const int8_t *)a, *y = (const int8_t *)b;
+        int64_t s = 0;
+        for (int32_t i = 0; i < d; i++) s += (int64_t)x[i] * (int64_t)y[i];
+        return (double)-s;
+    } else {
+        const float *x = (const float *)a, *y = (const float *)b;
+        double s = 0.0;
+        for (int32_t i = 0; i < d; i++) s += (double)x[i] * (double)y[i];
+        return -s;
+    }
+}
+
+static double dist_pts(const points_t *P, const void *a, const void *b) {
+    return P->metric == ORC_IP ? dist_ip(P->dtype, a, b, P->d) : dist_rows(P->dtype, a, b, P->d);
+}
+
+double orc_dist(int dtype, const void *a, const void *b, int32_t d, int metric) {
+    return metric == ORC_IP ? dist_ip(dtype, a, b, d) : dist_rows(dtype, a, b, d);
 }
 
 /* total order on (distance, id): the tie-break used everywhere */
@@ -291,7 +318,7 @@ static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64
     for (int64_t i = 0; i < nS; i++) {
         int32_t s = S[i];
         if (sc->inB[s]) continue;
-        double ds = dist_rows(P->dtype, row_ptr(P, s), q, P->d);
+        double ds = dist_pts(P, row_ptr(P, s), q);
         if (!sc->seen[s]) {
             sc->seen[s] = 1;
             st->evals++;
@@ -343,7 +370,7 @@ static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64
             if (u < 0) continue;
             if (sc->inV[u]) continue;
             if (sc->inB[u]) continue;
-            double du = dist_rows(P->dtype, row_ptr(P, u), q, P->d);
+            double du = dist_pts(P, row_ptr(P, u), q);
             if (!sc->seen[u]) {
                 sc->seen[u] = 1;
                 st->evals++;
@@ -427,7 +454,7 @@ static void greedy_search(const graph_t *G, const void *q, const cand_t *S, int6
             int32_t f = nb[j];
             if (f < 0) continue;
             if (sc->inV2[f]) continue; /* f in N_out(p*) \ V */
-            double df = dist_rows(P->dtype, row_ptr(P, f), q, P->d);
+            double df = dist_pts(P, row_ptr(P, f), q);
             if (!sc->seen2[f]) {
                 sc->seen2[f] = 1;
                 st->evals++;
@@ -517,7 +544,7 @@ static void bf_body(void *arg, int64_t qi, int tid) {
     const void *q = (const char *)c->queries + (size_t)qi * (size_t)c->P.d * elem_size(c->P.dtype);
     clist_t l = {0};
     for (int64_t i = 0; i < c->P.n; i++) {
-        double di = dist_rows(c->P.dtype, row_ptr(&c->P, i), q, c->P.d);
+        double di = dist_pts(&c->P, row_ptr(&c->P, i), q);
         if (di <= c->radius[qi]) cl_push(&l, di, (int32_t)i);
     }
     qsort(l.a, (size_t)l.n, sizeof(cand_t), cand_cmp);
@@ -526,11 +553,11 @@ static void bf_body(void *arg, int64_t qi, int tid) {
 }
 
 int orc_brute_force(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
-                    int64_t nq, const double *radius, int threads, orc_result *res) {
+                    int64_t nq, const double *radius, int threads, orc_result *res, int metric) {
     if (n < 0 || d < 1 || nq < 0 || (dtype != ORC_U8 && dtype != ORC_I8 && dtype != ORC_F32))
         return -1;
     res_alloc(res, nq);
-    bf_ctx_t c = {{base, dtype, n, d}, queries, radius, NULL};
+    bf_ctx_t c = {{base, dtype, n, d, metric}, queries, radius, NULL};
     c.qr = (qres_t *)calloc((size_t)(nq > 0 ? nq : 1), sizeof(qres_t));
     parallel_for(nq, threads, bf_body, &c);
     res_flatten(res, c.qr);
@@ -550,13 +577,13 @@ static void pd_body(void *arg, int64_t qi, int tid) {
     pd_ctx_t *c = (pd_ctx_t *)arg;
     const void *q = (const char *)c->queries + (size_t)qi * (size_t)c->P.d * elem_size(c->P.dtype);
     for (int64_t i = 0; i < c->P.n; i++)
-        c->out[qi * c->P.n + i] = dist_rows(c->P.dtype, row_ptr(&c->P, i), q, c->P.d);
+        c->out[qi * c->P.n + i] = dist_pts(&c->P, row_ptr(&c->P, i), q);
 }
 
 int orc_pair_dists(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
-                   int64_t nq, int threads, double *out) {
+                   int64_t nq, int threads, double *out, int metric) {
     if (n < 1 || d < 1 || nq < 0) return -1;
-    pd_ctx_t c = {{base, dtype, n, d}, queries, out};
+    pd_ctx_t c = {{base, dtype, n, d, metric}, queries, out};
     parallel_for(nq, threads, pd_body, &c);
     return 0;
 }
@@ -574,16 +601,16 @@ static void nn_body(void *arg, int64_t qi, int tid) {
     const void *q = (const char *)c->queries + (size_t)qi * (size_t)c->P.d * elem_size(c->P.dtype);
     double best = INFINITY;
     for (int64_t i = 0; i < c->P.n; i++) {
-        double di = dist_rows(c->P.dtype, row_ptr(&c->P, i), q, c->P.d);
+        double di = dist_pts(&c->P, row_ptr(&c->P, i), q);
         if (di < best) best = di;
     }
     c->out[qi] = best;
 }
 
 int orc_nn_dist(const void *base, int dtype, int64_t n, int32_t d, const void *queries, int64_t nq,
-                int threads, double *out) {
+                int threads, double *out, int metric) {
     if (n < 1 || d < 1 || nq < 0) return -1;
-    nn_ctx_t c = {{base, dtype, n, d}, queries, out};
+    nn_ctx_t c = {{base, dtype, n, d, metric}, queries, out};
     parallel_for(nq, threads, nn_body, &c);
     return 0;
 }
@@ -695,7 +722,7 @@ int orc_range_search(const void *base, int dtype, int64_t n, int32_t d, const in
     if (n < 1 || d < 1 || R < 0 || nq < 0 || entry < 0 || entry >= n || sp->beam < 1) return -1;
     if (sp->mode < ORC_PLAIN || sp->mode > ORC_DOUBLING) return -1;
     if (threads < 1) threads = 1;
-    points_t P = {base, dtype, n, d};
+    points_t P = {base, dtype, n, d, sp->metric};
     rs_ctx_t c;
     memset(&c, 0, sizeof(c));
     c.G.P = &P;
@@ -759,10 +786,11 @@ static void ep_body(void *arg, int64_t qi, int tid) {
 
 int orc_es_profile(const void *base, int dtype, int64_t n, int32_t d, const int32_t *adj, int32_t R,
                    int32_t entry, const void *queries, int64_t nq, const double *radius,
-                   int64_t beam, int64_t step, int threads, double *metrics, int8_t *flags) {
+                   int64_t beam, int64_t step, int threads, double *metrics, int8_t *flags,
+                   int metric) {
     if (n < 1 || d < 1 || R < 0 || entry < 0 || entry >= n || nq < 0 || beam < 1 || step < 0)
         return -1;
-    points_t P = {base, dtype, n, d};
+    points_t P = {base, dtype, n, d, metric};
     ep_ctx_t c;
     c.G.P = &P;
     c.G.adj = adj;

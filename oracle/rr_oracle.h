@@ -25,6 +25,11 @@ enum { ORC_U8 = 0, ORC_I8 = 1, ORC_F32 = 2 };
  * ORC_DOUBLING: Algorithm 3 (optionally with Algorithm 5). */
 enum { ORC_PLAIN = 0, ORC_ES = 1, ORC_ADAPTIVE = 2, ORC_DOUBLING = 3 };
 
+/* Distances: ORC_L2 = squared Euclidean (Section 2); ORC_IP = the negated
+ * inner product (the paper's inner-product datasets), so that smaller is
+ * closer and a range query is still d <= r (r is then usually negative). */
+enum { ORC_L2 = 0, ORC_IP = 1 };
+
 typedef struct {
     int32_t mode;
     int32_t beam;           /* b */
@@ -33,6 +38,7 @@ typedef struct {
     double es_radius;       /* esr, same units as the radius */
     double lambda;          /* expansion threshold fraction */
     int64_t max_beam;       /* doubling cap (sets truncated when reached) */
+    int32_t metric;         /* ORC_L2 or ORC_IP */
 } orc_search_params;
 
 typedef struct {
@@ -57,16 +63,16 @@ typedef struct {
     orc_query_stats *stats; /* nq (zeroed for brute force) */
 } orc_result;
 
-double orc_dist(int dtype, const void *a, const void *b, int32_t d);
+double orc_dist(int dtype, const void *a, const void *b, int32_t d, int metric);
 
 int orc_brute_force(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
-                    int64_t nq, const double *radius, int threads, orc_result *res);
+                    int64_t nq, const double *radius, int threads, orc_result *res, int metric);
 
 int orc_pair_dists(const void *base, int dtype, int64_t n, int32_t d, const void *queries,
-                   int64_t nq, int threads, double *out);
+                   int64_t nq, int threads, double *out, int metric);
 
 int orc_nn_dist(const void *base, int dtype, int64_t n, int32_t d, const void *queries, int64_t nq,
-                int threads, double *out);
+                int threads, double *out, int metric);
 
 int orc_range_search(const void *base, int dtype, int64_t n, int32_t d, const int32_t *adj,
                      int32_t R, int32_t entry, const void *queries, int64_t nq,
@@ -78,13 +84,17 @@ int orc_range_search(const void *base, int dtype, int64_t n, int32_t d, const in
  * first three if the search ended earlier); flags nq x 2 = reached, found */
 int orc_es_profile(const void *base, int dtype, int64_t n, int32_t d, const int32_t *adj, int32_t R,
                    int32_t entry, const void *queries, int64_t nq, const double *radius,
-                   int64_t beam, int64_t step, int threads, double *metrics, int8_t *flags);
+                   int64_t beam, int64_t step, int threads, double *metrics, int8_t *flags,
+                   int metric);
 
 int32_t orc_medoid(const void *base, int dtype, int64_t n, int32_t d);
 
 int orc_build_vamana(const void *base, int dtype, int64_t n, int32_t d, int32_t R, int32_t L,
                      double alpha, int32_t passes, const int64_t *order, int threads,
                      int32_t *adj_out, int32_t *entry_out);
+
+/* The graph builder uses ORC_L2 (RobustPrune's alpha rule needs a metric);
+ * inner-product searches run on graphs built with it or given. */
 
 /* RobustPrune(p, cand, alpha, R): returns the kept count (<= R) or -1 */
 int32_t orc_robust_prune(const void *base, int dtype, int64_t n, int32_t d, int32_t p,

@@ -122,7 +122,7 @@ def test_nn_dist_matches_cdist():
 # ---------------------------------------------------------------------------
 
 def _golden_cases():
-    for gname in ("line10", "even10_es"):
+    for gname in ("line10", "even10_es", "line10_ip"):
         g = GOLD[gname]
         for c in g["cases"]:
             yield pytest.param(gname, c, id=f"{gname}-{c['name']}")
@@ -134,14 +134,15 @@ def test_golden_line_graphs(gname, case):
     base = np.array(g["points"], np.uint8)
     adj = np.array(g["adj"], np.int32)
     q = np.array([g["query"]], np.uint8)
+    metric = g.get("metric", "l2")
     if case["mode"] == "brute":
-        res = oracle.brute_force(base, q, case["radius"])
+        res = oracle.brute_force(base, q, case["radius"], metric=metric)
     else:
         res = oracle.range_search(base, adj, g["entry"], q, case["radius"],
                                   mode=MODES[case["mode"]], beam=case["beam"],
                                   es_enable=case["mode"] == "es",
                                   es_visit_limit=case.get("vl", 0), es_radius=case.get("esr", 0.0),
-                                  lam=case.get("lambda", 1.0))
+                                  lam=case.get("lambda", 1.0), metric=metric)
     ids, dists = res.query(0)
     assert ids.tolist() == case["ids"]
     assert dists.tolist() == case["dists"]
@@ -470,3 +471,72 @@ def test_es_profile_predicts_the_stop_at_vl():
         stopped_at_vl = (es.stats["es_fired"] == 1) & (es.stats["visits"] == vl)
         np.testing.assert_array_equal(predicted, stopped_at_vl)
         assert predicted.any() and (open_q & ~predicted).any()
+
+
+
+@pytest.mark.parametrize("dt", [np.uint8, np.int8, np.float32])
+def test_ip_dist_and_brute_force_closed_forms(dt):
+    """Negated inner product: exact int64 dot products for integer data,
+    FP64 for float32; Definition 2.1 under it by numpy enumeration."""
+    rng = np.random.default_rng(11)
+    if dt == np.float32:
+        base = rng.standard_normal((300, 20)).astype(dt)
+        qs = rng.standard_normal((25, 20)).astype(dt)
+        D = -(qs.astype(np.float64) @ base.astype(np.float64).T)
+    else:
+        lo, hi = (0, 256) if dt == np.uint8 else (-128, 128)
+        base = rng.integers(lo, hi, (300, 20)).astype(dt)
+        qs = rng.integers(lo, hi, (25, 20)).astype(dt)
+        D = -(qs.astype(np.int64) @ base.astype(np.int64).T).astype(np.float64)
+    for i in range(5):
+        assert oracle.dist(qs[i], base[i], metric="ip") == pytest.approx(D[i, i], rel=1e-12, abs=1e-12)
+    r = float(np.quantile(D, 0.05))
+    bf = oracle.brute_force(base, qs, r, metric="ip")
+    for qi in range(len(qs)):
+        hit = np.flatnonzero(D[qi] <= r)
+        order = np.lexsort((hit, D[qi, hit]))
+        np.testing.assert_array_equal(bf.query(qi)[0], hit[order])
+        np.testing.assert_allclose(bf.query(qi)[1], D[qi, hit[order]], rtol=1e-12, atol=1e-12)
+    # float32 data: numpy's blocked dot products sum in another order (1e-15)
+    tol = dict(rtol=1e-12, atol=1e-12) if dt == np.float32 else dict(rtol=0, atol=0)
+    np.testing.assert_allclose(oracle.pair_dists(base, qs, metric="ip"), D, **tol)
+    np.testing.assert_allclose(oracle.nn_dist(base, qs, metric="ip"), D.min(1), **tol)
+
+
+def test_ip_complete_graph_and_closure():
+    """Under the inner product: on a complete graph every mode equals brute
+    force, and on random graphs the adaptive result is the closure of N in
+    the ball (the properties the L2 tests check)."""
+    rng = np.random.default_rng(12)
+    for _ in range(40):
+        n = int(rng.integers(2, 40))
+        base = rng.integers(0, 6, (n, 3)).astype(np.uint8)
+        qs = rng.integers(0, 6, (5, 3)).astype(np.uint8)
+        D = -(qs.astype(np.int64) @ base.astype(np.int64).T)
+        r = float(np.quantile(D, 0.3))
+        adj = _complete(n)
+        entry = int(rng.integers(0, n))
+        bf = oracle.brute_force(base, qs, r, metric="ip")
+        for b in (1, 3):
+            for mode in (oracle.ADAPTIVE, oracle.DOUBLING):
+                res = oracle.range_search(base, adj, entry, qs, r, mode=mode, beam=b, metric="ip")
+                np.testing.assert_array_equal(res.ids, bf.ids)
+                np.testing.assert_array_equal(res.offsets, bf.offsets)
+        res = oracle.range_search(base, adj, entry, qs, r, mode=oracle.PLAIN, beam=n, metric="ip")
+        np.testing.assert_array_equal(res.ids, bf.ids)
+        # random sparse graph: adaptive = closure of N inside the ball
+        R = 3
+        g = np.full((n, R), -1, np.int32)
+        for i in range(n):
+            others = np.setdiff1d(np.arange(n), [i])
+            k = min(R, len(others))
+            g[i, :k] = rng.choice(others, k, replace=False)
+        plain = oracle.range_search(base, g, entry, qs, r, mode=oracle.PLAIN, beam=2, metric="ip")
+        ada = oracle.range_search(base, g, entry, qs, r, mode=oracle.ADAPTIVE, beam=2, metric="ip")
+        for qi in range(len(qs)):
+            N = plain.query(qi)[0]
+            if len(N) >= 2:
+                want = _closure(g, D[qi].astype(np.float64), N, r)
+                assert set(ada.query(qi)[0].tolist()) == want
+            else:
+                np.testing.assert_array_equal(ada.query(qi)[0], N)
