@@ -12,7 +12,9 @@
  * Conventions shared by every entry point:
  *  - every function is extern "C", never throws, and returns rr_status;
  *    on failure rr_last_error() returns a thread-local message;
- *  - distances are squared L2.  uint8/int8 data: exact integers (int32).
+ *  - distances are squared L2, or the negated inner product -<p, q> for an
+ *    index set to RR_IP (Section 2 lists both; inner-product distances and
+ *    radii may be negative).  uint8/int8 data: exact integers (int32).
  *    float32 data: accumulated in FP64, reported as float32;
  *  - membership is inclusive: d <= r;
  *  - every result list is ordered by (distance, id) ascending;
@@ -43,6 +45,12 @@ typedef enum {
 } rr_status;
 
 typedef enum { RR_U8 = 0, RR_I8 = 1, RR_F32 = 2 } rr_dtype;
+
+/* Distance function of an index (Section 2).
+ *  RR_L2  squared Euclidean distance |p - q|^2.
+ *  RR_IP  negated inner product -<p, q> (maximum inner product search as
+ *         range search: d <= r  <=>  <p, q> >= -r). */
+typedef enum { RR_L2 = 0, RR_IP = 1 } rr_metric;
 
 /* Search modes.
  *  RR_PLAIN    Algorithm 1 without a stopping rule; returns the in-range
@@ -99,10 +107,12 @@ typedef struct {
     int32_t beam;           /* b >= 1                                      */
     int32_t es_enable;      /* Algorithm 5 in RR_ADAPTIVE / RR_DOUBLING    */
     int32_t es_visit_limit; /* vl >= 1                                     */
-    double es_radius;       /* esr, squared-distance units                 */
+    double es_radius;       /* esr, in distance units (squared for L2)     */
     double lambda;          /* expansion threshold fraction (paper: 1)     */
     int32_t precision;      /* rr_precision                                */
-    double recheck_margin;  /* band half-width, relative to the unsquared radius */
+    double recheck_margin;  /* least band half-width, relative to the unsquared
+                               radius (RR_IP: to |r|); the band is never narrower
+                               than the bfloat16 error bound */
     int64_t max_results_per_query; /* greedy/doubling cap; sets `truncated` */
     int64_t max_beam;       /* doubling cap on b (default 4096); sets `truncated` */
     int64_t result_capacity;/* results the greedy/doubling phases may hold for the
@@ -174,7 +184,16 @@ rr_status rr_index_graph(const rr_index *idx, int32_t *adj_host, int32_t *R_out,
 rr_status rr_index_info(const rr_index *idx, int64_t *n, int32_t *d, int32_t *dtype,
                         int32_t *R, int32_t *entry);
 
-/* Save / load vectors, graph and metadata (little-endian binary file). */
+/* Distance function used by every search, scan and profile of the index
+ * (rr_metric; RR_L2 on creation).  The graph itself is whatever was built
+ * or adopted: rr_index_build constructs it with L2 in either case.  Set
+ * before rr_index_to_device.  Errors: RR_EINVAL (unknown metric), RR_ESTATE
+ * (the index is on the device). */
+rr_status rr_index_set_metric(rr_index *idx, int32_t metric);
+rr_status rr_index_metric(const rr_index *idx, int32_t *metric);
+
+/* Save / load vectors, graph and metadata incl. the metric (little-endian
+ * binary file; files written without a metric load as RR_L2). */
 rr_status rr_index_save(const rr_index *idx, const char *path);
 rr_status rr_index_load(const char *path, rr_index **out);
 
@@ -208,8 +227,8 @@ rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t n
                          double radius, const double *radius_dev, const rr_allocator *alloc,
                          void *stream, rr_results **out);
 
-/* Squared distance from every query to its nearest base point (nq doubles on
- * the device).  Used to choose radii. */
+/* Distance from every query to its nearest base point under the index
+ * metric (nq doubles on the device).  Used to choose radii. */
 rr_status rr_nn_dist(const rr_index *idx, const void *queries_dev, int64_t nq,
                      double *nn_dev, void *stream);
 

@@ -21,7 +21,6 @@
 namespace rr {
 hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
                               hipStream_t s);
-hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s);
 rr_status vamana_build(const void *base, int dtype, int64_t n, int32_t d, const rr_build_params *bp,
                        std::vector<int32_t> &adj, int32_t *entry);
 } // namespace rr
@@ -299,13 +298,29 @@ extern "C" rr_status rr_index_info(const rr_index *ix, int64_t *n, int32_t *d, i
     return RR_OK;
 }
 
-static const char kMagic[8] = {'R', 'R', 'I', 'D', 'X', '0', '0', '1'};
+extern "C" rr_status rr_index_set_metric(rr_index *ix, int32_t metric) {
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (metric != RR_L2 && metric != RR_IP) return fail(RR_EINVAL, "unknown metric %d", metric);
+    if (ix->on_device) return fail(RR_ESTATE, "the metric is fixed once the index is on the device");
+    ix->metric = metric;
+    return RR_OK;
+}
+
+extern "C" rr_status rr_index_metric(const rr_index *ix, int32_t *metric) {
+    if (!ix || !metric) return fail(RR_EINVAL, "index or metric is NULL");
+    *metric = ix->metric;
+    return RR_OK;
+}
+
+// version 1 files hold no metric (L2); version 2 adds it to the header
+static const char kMagic1[8] = {'R', 'R', 'I', 'D', 'X', '0', '0', '1'};
+static const char kMagic[8] = {'R', 'R', 'I', 'D', 'X', '0', '0', '2'};
 
 extern "C" rr_status rr_index_save(const rr_index *ix, const char *path) {
     if (!ix || !path) return fail(RR_EINVAL, "index or path is NULL");
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(RR_EIO, "cannot open %s for writing", path);
-    int64_t hdr[5] = {ix->n, ix->d, ix->dtype, ix->R, ix->entry};
+    int64_t hdr[6] = {ix->n, ix->d, ix->dtype, ix->R, ix->entry, ix->metric};
     bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
               std::fwrite(ix->base.data(), 1, ix->base.size(), f) == ix->base.size() &&
               std::fwrite(ix->adj.data(), sizeof(int32_t), ix->adj.size(), f) == ix->adj.size();
@@ -320,16 +335,21 @@ extern "C" rr_status rr_index_load(const char *path, rr_index **out) {
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(RR_EIO, "cannot open %s", path);
     char magic[8];
-    int64_t hdr[5];
-    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, kMagic, 8) != 0 ||
-        std::fread(hdr, sizeof hdr, 1, f) != 1) {
+    int64_t hdr[6] = {0, 0, 0, 0, 0, RR_L2};
+    bool head = std::fread(magic, 1, 8, f) == 8;
+    const bool v1 = head && std::memcmp(magic, kMagic1, 8) == 0;
+    head = head && (v1 || std::memcmp(magic, kMagic, 8) == 0) &&
+           std::fread(hdr, sizeof(int64_t), v1 ? 5 : 6, f) == (v1 ? 5u : 6u);
+    if (!head) {
         std::fclose(f);
         return fail(RR_EIO, "%s is not an index file", path);
     }
     const int64_t n = hdr[0];
     const int32_t d = (int32_t)hdr[1], dtype = (int32_t)hdr[2], R = (int32_t)hdr[3],
                   entry = (int32_t)hdr[4];
-    if (check_dtype(dtype) != RR_OK || n < 1 || d < 1 || R < 0 || R > 64 || entry < 0 || entry >= n) {
+    const int64_t metric = hdr[5];
+    if (check_dtype(dtype) != RR_OK || n < 1 || d < 1 || R < 0 || R > 64 || entry < 0 || entry >= n ||
+        (metric != RR_L2 && metric != RR_IP)) {
         std::fclose(f);
         return fail(RR_EIO, "%s: corrupt header", path);
     }
@@ -346,7 +366,9 @@ extern "C" rr_status rr_index_load(const char *path, rr_index **out) {
               std::fread(adj.data(), sizeof(int32_t), adj.size(), f) == adj.size();
     std::fclose(f);
     if (!ok) return fail(RR_EIO, "%s: truncated", path);
-    return rr_index_from_graph(base.data(), (rr_dtype)dtype, n, d, adj.data(), R, entry, out);
+    const rr_status st = rr_index_from_graph(base.data(), (rr_dtype)dtype, n, d, adj.data(), R, entry, out);
+    if (st == RR_OK) (*out)->metric = (int32_t)metric;
+    return st;
 }
 
 static void free_device(rr_index *ix) {
@@ -435,6 +457,12 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
     dv.base_bf16 = (const uint8_t *)ix->d_bf16;
     dv.adj = (const int32_t *)ix->d_adj;
     dv.max_norm = maxn;
+    dv.metric = ix->metric;
+    // integer inner product: keys key_off - <p, q> are >= 0 for every pair
+    // (uint8: <p, q> <= 255^2 d; int8: |<p, q>| <= 128^2 d)
+    dv.key_off = 0;
+    if (ix->metric == RR_IP && ix->dtype == RR_U8) dv.key_off = 65025ll * ix->d;
+    if (ix->metric == RR_IP && ix->dtype == RR_I8) dv.key_off = 16384ll * ix->d;
     return RR_OK;
 }
 

@@ -46,6 +46,8 @@ struct DevIndex {
     const uint8_t *base_bf16 = nullptr;
     const int32_t *adj = nullptr;
     float max_norm = 0.f; // largest |x| (float data)
+    int32_t metric = 0;   // rr_metric
+    int64_t key_off = 0;  // integer data, inner product: keys are key_off - <p, q>
 };
 
 // Per-query thresholds derived from the radius (written by a prep kernel).
@@ -186,7 +188,6 @@ hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, d
 hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s);
 hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
                               hipStream_t s);
-hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s);
 
 // error message of the calling thread (rr_last_error)
 rr_status set_error(rr_status st, const char *fmt, ...);
@@ -200,6 +201,7 @@ struct rr_index {
     int32_t dtype = 0;
     int32_t R = 0;
     int32_t entry = 0;
+    int32_t metric = 0;        // rr_metric
     std::vector<uint8_t> base; // n x d x esize, unpadded
     std::vector<int32_t> adj;  // n x R
     // device

@@ -217,14 +217,24 @@ __device__ __forceinline__ int lower_bound_key(const D *ad, const uint32_t *ai, 
 // Internal data type of the approximate pass on float data: rows are the
 // bfloat16 copy, the query stays float32, squares accumulate in float32.
 constexpr int RR_BF16X = 3;
+// Kernel data type = element type (low bits) | RR_IPBIT for the negated
+// inner product (Section 2), so both metrics share every kernel template.
+constexpr int RR_IPBIT = 8;
+__host__ __device__ constexpr int dbase(int dt) { return dt & 7; }
+__host__ __device__ constexpr bool dip(int dt) { return (dt & RR_IPBIT) != 0; }
+__host__ __device__ constexpr bool dfloat(int dt) { return dbase(dt) == RR_F32 || dbase(dt) == RR_BF16X; }
+constexpr int RR_U8IP = RR_U8 | RR_IPBIT, RR_I8IP = RR_I8 | RR_IPBIT, RR_F32IP = RR_F32 | RR_IPBIT,
+              RR_BF16XIP = RR_BF16X | RR_IPBIT;
 
 // T: the search key; Acc: the accumulator; O: the distance that decides
-// membership and is reported (exact for every type).
-template <int DTYPE> struct DistOf;
-template <> struct DistOf<RR_U8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
-template <> struct DistOf<RR_I8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
-template <> struct DistOf<RR_F32> { using T = double; using Acc = double; using O = double; };
-template <> struct DistOf<RR_BF16X> { using T = float; using Acc = float; using O = double; };
+// membership and is reported (exact for every type).  Integer keys are
+// unsigned: the inner product is searched as key_off - <p, q> >= 0.
+template <int BASE> struct DistBase;
+template <> struct DistBase<RR_U8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
+template <> struct DistBase<RR_I8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
+template <> struct DistBase<RR_F32> { using T = double; using Acc = double; using O = double; };
+template <> struct DistBase<RR_BF16X> { using T = float; using Acc = float; using O = double; };
+template <int DTYPE> struct DistOf : DistBase<dbase(DTYPE)> {};
 
 template <int DTYPE>
 __device__ __forceinline__ typename DistOf<DTYPE>::Acc chunk_part(uint4 p, uint4 q);
@@ -266,6 +276,31 @@ template <> __device__ __forceinline__ double chunk_part<RR_F32>(uint4 p, uint4 
     return a;
 }
 
+// inner-product parts: <p, q> over the chunk (uint8/int8: exact int32)
+template <int BASE>
+__device__ __forceinline__ typename DistBase<BASE>::Acc chunk_ip(uint4 p, uint4 q);
+template <> __device__ __forceinline__ int chunk_ip<RR_U8>(uint4 p, uint4 q) {
+    unsigned pq = __builtin_amdgcn_udot4(p.x, q.x, 0u, false);
+    pq = __builtin_amdgcn_udot4(p.y, q.y, pq, false);
+    pq = __builtin_amdgcn_udot4(p.z, q.z, pq, false);
+    pq = __builtin_amdgcn_udot4(p.w, q.w, pq, false);
+    return (int)pq;
+}
+template <> __device__ __forceinline__ int chunk_ip<RR_I8>(uint4 p, uint4 q) {
+    int pq = __builtin_amdgcn_sdot4((int)p.x, (int)q.x, 0, false);
+    pq = __builtin_amdgcn_sdot4((int)p.y, (int)q.y, pq, false);
+    pq = __builtin_amdgcn_sdot4((int)p.z, (int)q.z, pq, false);
+    pq = __builtin_amdgcn_sdot4((int)p.w, (int)q.w, pq, false);
+    return pq;
+}
+template <> __device__ __forceinline__ double chunk_ip<RR_F32>(uint4 p, uint4 q) {
+    double a = (double)__uint_as_float(p.x) * (double)__uint_as_float(q.x);
+    a = fma((double)__uint_as_float(p.y), (double)__uint_as_float(q.y), a);
+    a = fma((double)__uint_as_float(p.z), (double)__uint_as_float(q.z), a);
+    a = fma((double)__uint_as_float(p.w), (double)__uint_as_float(q.w), a);
+    return a;
+}
+
 // bfloat16 row chunk (8 values) against 8 float32 query values: sum of
 // squared differences, float32 accumulation
 __device__ __forceinline__ float chunk_part_bf16(uint4 p, uint4 q0, uint4 q1) {
@@ -284,14 +319,38 @@ __device__ __forceinline__ float chunk_part_bf16(uint4 p, uint4 q0, uint4 q1) {
     return a;
 }
 
-// exact distance of a float32 row for the recheck: FP64 sum of squared
-// differences over the zero-padded rows
+// the same for the inner product: sum of products, float32 accumulation
+__device__ __forceinline__ float chunk_ip_bf16(uint4 p, uint4 q0, uint4 q1) {
+    const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+    const uint32_t qa[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a = fmaf(__uint_as_float(w[j] << 16), __uint_as_float(qa[2 * j]), a);
+        a = fmaf(__uint_as_float(w[j] & 0xffff0000u), __uint_as_float(qa[2 * j + 1]), a);
+    }
+    return a;
+}
+
+// exact distance of a float32 row for the recheck, in FP64 over the
+// zero-padded rows: the sum of squared differences, or -<x, q>
+template <bool IP>
 __device__ __forceinline__ double exact_dist_f32(const DevIndex &ix, uint32_t id,
                                                  const uint8_t *qrow) {
     const float4 *x = reinterpret_cast<const float4 *>(ix.base_exact + (size_t)id * ix.row_bytes_exact);
     const float4 *q = reinterpret_cast<const float4 *>(qrow);
     const int n4 = (ix.d + 3) / 4;
     double a = 0.0;
+    if constexpr (IP) {
+        for (int i = 0; i < n4; ++i) {
+            const float4 u = x[i], v = q[i];
+            a = fma((double)u.x, (double)v.x, a);
+            a = fma((double)u.y, (double)v.y, a);
+            a = fma((double)u.z, (double)v.z, a);
+            a = fma((double)u.w, (double)v.w, a);
+        }
+        return -a;
+    }
     for (int i = 0; i < n4; ++i) {
         const float4 u = x[i], v = q[i];
         double t = (double)u.x - (double)v.x;
@@ -327,22 +386,23 @@ template <> __device__ __forceinline__ int chunk_qq<RR_I8>(uint4 q) {
 // For the bfloat16 pass each 16-byte row chunk (8 values) pairs with 32
 // bytes of the float32 query, so a lane holds 2*CPL query chunks.
 template <int DTYPE, int CPL, int G> struct QueryRegs {
-    static constexpr int QC = DTYPE == RR_BF16X ? 2 * CPL : CPL;
+    static constexpr int QC = dbase(DTYPE) == RR_BF16X ? 2 * CPL : CPL;
+    static constexpr bool L2INT = !dfloat(DTYPE) && !dip(DTYPE);
     uint4 c[QC];
-    int qq; // integer data: |q|^2
+    int qq; // integer data: |q|^2 (L2) or the key offset (inner product)
     const uint8_t *row; // the padded query row (the recheck reads it)
 
-    __device__ __forceinline__ void load(const uint8_t *qrow) {
+    __device__ __forceinline__ void load(const uint8_t *qrow, const DevIndex &ix) {
         const int gl = lane_id() & (G - 1);
         row = qrow;
         int s = 0;
 #pragma unroll
         for (int k = 0; k < QC; ++k) {
             c[k] = *reinterpret_cast<const uint4 *>(qrow + (size_t)(gl * QC + k) * 16);
-            if constexpr (DTYPE == RR_U8 || DTYPE == RR_I8) s += chunk_qq<DTYPE>(c[k]);
+            if constexpr (L2INT) s += chunk_qq<dbase(DTYPE)>(c[k]);
         }
-        if constexpr (DTYPE == RR_U8 || DTYPE == RR_I8) qq = group_sum<G>(s);
-        else qq = 0;
+        if constexpr (L2INT) qq = group_sum<G>(s);
+        else qq = (int)(uint32_t)ix.key_off;
     }
 };
 
@@ -384,13 +444,18 @@ __device__ __forceinline__ void eval_rows(const DevIndex &ix, const QueryRegs<DT
             for (int kk = 0; kk < CPL; ++kk) {
                 if constexpr (DTYPE == RR_BF16X)
                     a += chunk_part_bf16(buf[rb][kk], qr.c[2 * kk], qr.c[2 * kk + 1]);
+                else if constexpr (DTYPE == RR_BF16XIP)
+                    a += chunk_ip_bf16(buf[rb][kk], qr.c[2 * kk], qr.c[2 * kk + 1]);
+                else if constexpr (dip(DTYPE))
+                    a += chunk_ip<dbase(DTYPE)>(buf[rb][kk], qr.c[kk]);
                 else
                     a += chunk_part<DTYPE>(buf[rb][kk], qr.c[kk]);
             }
             a = group_sum<G>(a);
             const int c = (r0 + rb) * RPR + grp;
             if (gl == 0 && c < k) {
-                if constexpr (DTYPE == RR_F32 || DTYPE == RR_BF16X) cd[c] = a;
+                if constexpr (dfloat(DTYPE)) cd[c] = dip(DTYPE) ? -a : a;
+                else if constexpr (dip(DTYPE)) cd[c] = (uint32_t)qr.qq - (uint32_t)a;
                 else cd[c] = (uint32_t)(a + qr.qq);
             }
         }
@@ -422,25 +487,30 @@ template <> __device__ __forceinline__ bool beyond_esr<float>(float d, const QTh
     return d > t.esr_f;
 }
 
-// the kernels' data type: the index dtype, or the bfloat16 pass
+// the kernels' data type: the index dtype, or the bfloat16 pass, with the
+// metric bit
 static int kernel_dtype(const DevIndex &ix, const SearchCfg &cfg) {
-    return (ix.dtype == RR_F32 && cfg.precision == RR_BF16_RECHECK) ? RR_BF16X : ix.dtype;
+    const int b = (ix.dtype == RR_F32 && cfg.precision == RR_BF16_RECHECK) ? RR_BF16X : ix.dtype;
+    return b | (ix.metric == RR_IP ? RR_IPBIT : 0);
 }
 
 // stride of the padded query rows: the bfloat16 pass keeps float32 queries
 // next to bf16 rows, so its query rows are twice the row stride
 template <int DTYPE> __device__ __forceinline__ size_t qrow_stride(const DevIndex &ix) {
-    return DTYPE == RR_BF16X ? 2 * (size_t)ix.row_bytes : (size_t)ix.row_bytes;
+    return dbase(DTYPE) == RR_BF16X ? 2 * (size_t)ix.row_bytes : (size_t)ix.row_bytes;
 }
 
 // --------------------------------------------------------------------------
 // query preparation: pad rows, derive per-query thresholds
 // --------------------------------------------------------------------------
 
-__device__ int64_t floor_clamp(double r) {
-    if (!(r >= 0.0)) return -1; // negative or NaN: nothing is within
+// integer keys are key_off + d (key_off = 0 for L2): d <= r <=> key <= the
+// returned threshold; -1 when no key can be within (r below -key_off, NaN)
+__device__ int64_t floor_key(double r, int64_t key_off) {
+    if (!(r >= -4.0e18)) return -1;
     if (r >= 4.0e18) return (int64_t)4000000000000000000ll;
-    return (int64_t)floor(r);
+    const int64_t k = (int64_t)floor(r) + key_off;
+    return k < 0 ? -1 : k;
 }
 
 // Band of the approximate pass (squared units).  With x^ the bfloat16 row
@@ -464,12 +534,26 @@ __device__ void band(double r2, double maxnorm, int d, double margin, float *lo,
     *lo = __double2float_rd(l);
 }
 
+// Band of the approximate pass for the negated inner product: the bfloat16
+// row moves <x, q> by at most 2^-8 sum |x_i q_i| <= 2^-8 max|x| |q|, float32
+// accumulation by at most gamma (1 + 2^-8) max|x| |q|, so s > r + delta
+// proves -<x, q> > r and s < r - delta proves the opposite.
+__device__ void band_ip(double r, double maxnorm, double qnorm, int d, double margin, float *lo,
+                        float *hi) {
+    const double gamma = (double)(d + 2) * 0x1p-24;
+    const double delta = fmax(margin * fabs(r),
+                              (0x1p-8 + gamma * (1.0 + 0x1p-8)) * maxnorm * qnorm * (1.0 + 1e-6));
+    *hi = __double2float_ru(r + delta);
+    *lo = __double2float_rd(r - delta);
+}
+
 // pads query qi into row dst[qi] (qi when dst is null) and derives its
 // thresholds; a non-null `state` marks the destination slots as fresh
 __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int32_t row_out,
                                double radius, const double *radius_dev, double esr,
                                QThresh *qth, uint8_t *qpad, double maxnorm, int d,
-                               double margin, int approx, const int32_t *dst, BeamState *state) {
+                               double margin, int approx, int ip, int64_t key_off,
+                               const int32_t *dst, BeamState *state) {
     const int64_t chunks = row_out / 16;
     const int64_t tot = nq * chunks;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
@@ -494,13 +578,20 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
             const double r = radius_dev ? radius_dev[qi] : radius;
             th.r = r;
             th.esr = esr;
-            th.r_int = floor_clamp(r);
-            th.esr_int = floor_clamp(esr);
+            th.r_int = floor_key(r, key_off);
+            th.esr_int = floor_key(esr, key_off);
             th.r_f = (float)r;
             th.esr_f = (float)esr;
             th.lo = -1.f;
             th.hi = -1.f;
-            if (approx) band(r, maxnorm, d, margin, &th.lo, &th.hi);
+            if (approx && !ip) band(r, maxnorm, d, margin, &th.lo, &th.hi);
+            if (approx && ip) {
+                // |q| of the float32 query row
+                const float *qf = reinterpret_cast<const float *>(q + qi * row_in);
+                double qn = 0.0;
+                for (int i = 0; i < d; ++i) qn = fma((double)qf[i], (double)qf[i], qn);
+                band_ip(r, maxnorm, sqrt(qn), d, margin, &th.lo, &th.hi);
+            }
             qth[qo] = th;
             if (state) {
                 BeamState bs{};
@@ -515,7 +606,7 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
                                hipStream_t s) {
     if (nq == 0) return hipSuccess;
     const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
-    const int approx = kernel_dtype(ix, cfg) == RR_BF16X;
+    const int approx = dbase(kernel_dtype(ix, cfg)) == RR_BF16X;
     // the approximate pass pairs each bf16 row chunk with twice its bytes of
     // float32 query
     const int32_t row_out = approx ? 2 * ix.row_bytes : ix.row_bytes;
@@ -525,7 +616,8 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
     hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s,
                        (const uint8_t *)queries, nq, ix.d * esz, row_out, radius, radius_dev,
                        cfg.esr, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, approx,
-                       (const int32_t *)nullptr, (BeamState *)nullptr);
+                       (int)(ix.metric == RR_IP), ix.key_off, (const int32_t *)nullptr,
+                       (BeamState *)nullptr);
     return hipGetLastError();
 }
 
@@ -534,24 +626,15 @@ hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
                              SearchBufs &sb, BeamState *state, hipStream_t s) {
     if (k == 0) return hipSuccess;
     const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
-    const int approx = kernel_dtype(ix, cfg) == RR_BF16X;
+    const int approx = dbase(kernel_dtype(ix, cfg)) == RR_BF16X;
     const int32_t row_out = approx ? 2 * ix.row_bytes : ix.row_bytes;
     const int64_t tot = k * (row_out / 16);
     int blocks = (int)std::min<int64_t>((tot + 255) / 256, 65536);
     hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s, (const uint8_t *)queries, k,
                        ix.d * esz, row_out, 0.0, radius_dev, cfg.esr, sb.qth, sb.qpad,
-                       (double)ix.max_norm, ix.d, cfg.margin, approx, dst, state);
+                       (double)ix.max_norm, ix.d, cfg.margin, approx, (int)(ix.metric == RR_IP),
+                       ix.key_off, dst, state);
     return hipGetLastError();
-}
-
-// esr is a search parameter: written separately so prep stays param-free
-__global__ void k_set_esr(QThresh *qth, int64_t nq, double esr) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        qth[i].esr = esr;
-        qth[i].esr_int = floor_clamp(esr);
-        qth[i].esr_f = (float)esr;
-    }
 }
 
 // --------------------------------------------------------------------------
@@ -621,7 +704,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
 
         const QThresh th = a.sb.qth[q];
         QueryRegs<DTYPE, CPL, G> qr;
-        qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
+        qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix), ix);
 
         for (int i = lane; i < cs; i += 64) htab[i] = RR_EMPTY32;
         wave_sync();
@@ -665,7 +748,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                     a.probe_m[4 * q] = nan;
                     a.probe_m[4 * q + 1] = nan;
                     a.probe_m[4 * q + 2] = nan;
-                    a.probe_m[4 * q + 3] = (double)cd[0];
+                    a.probe_m[4 * q + 3] = (double)cd[0] - (double)ix.key_off;
                     a.probe_f[2 * q] = 0;
                     a.probe_f[2 * q + 1] = 0;
                 }
@@ -690,9 +773,10 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             if (ip < 0) break;
             const D dp = bd[ip];
             if (a.probe_m && visits == a.probe_step && lane == 0) {
-                a.probe_m[4 * q] = (double)dp;
-                a.probe_m[4 * q + 1] = (double)bd[0];
-                a.probe_m[4 * q + 2] = nB >= 10 ? (double)bd[9] : __builtin_inf();
+                const double ko = (double)ix.key_off;
+                a.probe_m[4 * q] = (double)dp - ko;
+                a.probe_m[4 * q + 1] = (double)bd[0] - ko;
+                a.probe_m[4 * q + 2] = nB >= 10 ? (double)bd[9] - ko : __builtin_inf();
                 a.probe_f[2 * q] = 1;
                 a.probe_f[2 * q + 1] = in_range<D>(bd[0], th) ? 1 : 0;
             }
@@ -810,7 +894,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         // the sorted beam.  Approximate pass: the prefix with s <= hi holds
         // every possible member; each is re-decided on its exact distance.
         int cN = 0, cH = 0, nband = 0;
-        if constexpr (DTYPE == RR_BF16X) {
+        if constexpr (dbase(DTYPE) == RR_BF16X) {
             for (int base = 0; base < nB; base += 64) {
                 const int i = base + lane;
                 const int c = __popcll(__ballot(i < nB && bd[i] <= th.hi));
@@ -820,7 +904,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             for (int base = 0; base < cH; base += 64) {
                 const int i = base + lane;
                 bool inr = false;
-                if (i < cH) inr = exact_dist_f32(ix, bi[i] & RR_IDMASK, qr.row) <= th.r;
+                if (i < cH) inr = exact_dist_f32<dip(DTYPE)>(ix, bi[i] & RR_IDMASK, qr.row) <= th.r;
                 cN += __popcll(__ballot(inr));
                 nband += __popcll(__ballot(i < cH && bd[i] > th.lo));
             }
@@ -838,7 +922,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         const bool expand = expand_flag && cN > 0;
         // results of the approximate pass are sorted by exact distance in the
         // finalisation, so every non-empty query becomes a task there
-        const bool as_task = expand || (DTYPE == RR_BF16X && cN > 0);
+        const bool as_task = expand || (dbase(DTYPE) == RR_BF16X && cN > 0);
         rr_query_stats st;
         st.visits = visits;
         st.evals = evals;
@@ -881,13 +965,13 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             int written = 0;
             O *idist = (O *)a.sb.item_dist;
             const int64_t hmask = a.sb.hash_cap - 1;
-            if constexpr (DTYPE == RR_BF16X) {
+            if constexpr (dbase(DTYPE) == RR_BF16X) {
                 for (int base = 0; base < cH; base += 64) {
                     const int i = base + lane;
                     double dx = 0.0;
                     bool inr = false;
                     if (i < cH) {
-                        dx = exact_dist_f32(ix, bi[i] & RR_IDMASK, qr.row);
+                        dx = exact_dist_f32<dip(DTYPE)>(ix, bi[i] & RR_IDMASK, qr.row);
                         inr = dx <= th.r;
                     }
                     const unsigned long long im = __ballot(inr);
@@ -1018,7 +1102,7 @@ __global__ __launch_bounds__(512) void k_doubling(DoublingArgs a) {
 
         const QThresh th = a.sb.qth[q];
         QueryRegs<DTYPE, CPL, G> qr;
-        qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
+        qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix), ix);
 
         D *bd = bdA, *bdo = bdB;
         uint32_t *bi = biA, *bio = biB;
@@ -1261,7 +1345,7 @@ constexpr int GREEDY_QUEUE = 192;   // per-wave queue of candidates awaiting dis
 // waves per workgroup (one workgroup per CU): 16, or 8 where the distance
 // code needs more than the 128 registers a 1024-lane workgroup leaves
 template <int DTYPE, int CPL> constexpr int greedy_waves() {
-    return (DTYPE == RR_F32 || DTYPE == RR_BF16X || CPL >= 6) ? 8 : 16;
+    return (dfloat(DTYPE) || CPL >= 6) ? 8 : 16;
 }
 
 template <typename D, typename O, int GW> struct GreedyLds {
@@ -1493,11 +1577,11 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
                 uint32_t myi = 0;
                 if (i < k) {
                     myi = qi[i];
-                    if constexpr (DTYPE == RR_BF16X) {
+                    if constexpr (dbase(DTYPE) == RR_BF16X) {
                         // approximate distance above hi: provably outside the
                         // ball; otherwise the exact distance decides
                         if (qd[i] <= th.hi) {
-                            myd = exact_dist_f32(ix, myi, qr.row);
+                            myd = exact_dist_f32<dip(DTYPE)>(ix, myi, qr.row);
                             inr = myd <= th.r;
                         }
                     } else {
@@ -1505,7 +1589,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
                         inr = in_range<D>(qd[i], th);
                     }
                 }
-                if constexpr (DTYPE == RR_BF16X) {
+                if constexpr (dbase(DTYPE) == RR_BF16X) {
                     const int nb = __popcll(__ballot(i < k && qd[i] > th.lo && qd[i] <= th.hi));
                     run_rechk += (unsigned long long)nb;
                 }
@@ -1550,7 +1634,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
                 qtask = t;
                 const int32_t q = a.sb.task_q[t];
                 th = a.sb.qth[q];
-                qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix));
+                qr.load(a.sb.qpad + (size_t)q * qrow_stride<DTYPE>(ix), ix);
             }
             if (mine) qi[qn + mbcnt(mask)] = (uint32_t)f;
             wave_sync();
@@ -2081,6 +2165,10 @@ static hipError_t dispatch_beam(const DevIndex &ix, int64_t nq, const SearchCfg 
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
     RR_SPLITS(X, RR_BF16X)
+    RR_SPLITS(X, RR_U8IP)
+    RR_SPLITS(X, RR_I8IP)
+    RR_SPLITS(X, RR_F32IP)
+    RR_SPLITS(X, RR_BF16XIP)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -2142,6 +2230,9 @@ hipError_t launch_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
     RR_SPLITS(X, RR_U8)
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
+    RR_SPLITS(X, RR_U8IP)
+    RR_SPLITS(X, RR_I8IP)
+    RR_SPLITS(X, RR_F32IP)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -2189,6 +2280,10 @@ hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, S
     RR_SPLITS(X, RR_I8)
     RR_SPLITS(X, RR_F32)
     RR_SPLITS(X, RR_BF16X)
+    RR_SPLITS(X, RR_U8IP)
+    RR_SPLITS(X, RR_I8IP)
+    RR_SPLITS(X, RR_F32IP)
+    RR_SPLITS(X, RR_BF16XIP)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -2267,9 +2362,12 @@ __device__ int64_t last_le(const int64_t *offsets, int64_t lo, int64_t hi, int64
     return lo;
 }
 
+// integer keys are key_off + d: subtracting key_off modulo 2^32 gives d
+// (which fits int32) for both metrics
 template <typename DIN, typename DOUT>
 __global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, int64_t nq,
-                                const int32_t *aid, const DIN *ad, int32_t *ids, DOUT *dists) {
+                                const int32_t *aid, const DIN *ad, int32_t *ids, DOUT *dists,
+                                DIN key_off) {
     __shared__ int64_t s_q[2];
     const int64_t total = offsets[nq];
     for (int64_t b0 = (int64_t)blockIdx.x * COPY_SPAN; b0 < total;
@@ -2283,7 +2381,7 @@ __global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, 
             const int64_t q = qlo == qhi ? qlo : last_le(offsets, qlo, qhi, i);
             const int64_t src = res_off[q] + (i - offsets[q]);
             ids[i] = aid[src];
-            dists[i] = (DOUT)ad[src];
+            dists[i] = (DOUT)(ad[src] - key_off);
         }
         __syncthreads();
     }
@@ -2319,19 +2417,13 @@ hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, con
     if (dtype == RR_F32)
         hipLaunchKernelGGL((k_copy_segments<double, float>), dim3(blocks), dim3(256), 0, s,
                            res_off, offsets, nq, arena_ids, (const double *)arena_dists, ids,
-                           (float *)dists);
+                           (float *)dists, 0.0);
     else
         hipLaunchKernelGGL((k_copy_segments<uint32_t, int32_t>), dim3(blocks), dim3(256), 0, s,
                            res_off, offsets, nq, arena_ids, (const uint32_t *)arena_dists, ids,
-                           (int32_t *)dists);
+                           (int32_t *)dists, (uint32_t)ix.key_off);
     return hipGetLastError();
 }
 
-hipError_t launch_set_esr(QThresh *qth, int64_t nq, double esr, hipStream_t s) {
-    if (nq == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_set_esr, dim3((unsigned)std::min<int64_t>((nq + 255) / 256, 4096)), dim3(256),
-                       0, s, qth, nq, esr);
-    return hipGetLastError();
-}
 
 } // namespace rr

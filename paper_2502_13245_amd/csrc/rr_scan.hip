@@ -8,6 +8,10 @@
 //    d = |q'|^2 + |x'|^2 - 2 q'.x' is exact in int32.
 //  * float32: v_mfma_f64_16x16x4f64 on the float32 values widened to FP64,
 //    d = |q|^2 + |x|^2 - 2 q.x in FP64.
+// The negated inner product (Section 2) uses the same products: float32
+// d = -q.x; integer data keeps the search's unsigned key key_off - q.x,
+// where for uint8 q.x = q'.x' + 128 (sum q + sum x) - 128^2 P over the P
+// padded coordinates (padding is 0 before the shift).
 // Each wave keeps QT tiles of 16 queries in registers (A operand) and
 // streams 16-point base tiles (B operand); the four waves of a workgroup
 // share the base tiles through the L1 cache.  Output tile layout of the int8
@@ -49,7 +53,26 @@ constexpr int QT = 4; // 16-query tiles per wave
 
 __device__ __forceinline__ uint32_t shift_u8(uint32_t w) { return w ^ 0x80808080u; }
 
-template <int DTYPE, int KS>
+// running sum of the 16 unsigned bytes of v
+__device__ __forceinline__ int row_sum_u8(uint4 v, int s) {
+    unsigned t = __builtin_amdgcn_udot4(v.x, 0x01010101u, (unsigned)s, false);
+    t = __builtin_amdgcn_udot4(v.y, 0x01010101u, t, false);
+    t = __builtin_amdgcn_udot4(v.z, 0x01010101u, t, false);
+    t = __builtin_amdgcn_udot4(v.w, 0x01010101u, t, false);
+    return (int)t;
+}
+
+// order-preserving map of a double to an unsigned key (atomicMin over
+// signed distances) and back
+__device__ __forceinline__ unsigned long long dbl_order(double d) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dbl_unorder(unsigned long long k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+
+template <int DTYPE, int KS, bool IP>
 __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -71,6 +94,7 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
         for (int ks = 0; ks < KSMAX; ++ks) {
             if (ks < ks_n) {
                 uint4 v = *reinterpret_cast<const uint4 *>(a.qpad + q * a.ix.row_bytes + ks * 64 + grp * 16);
+                if (IP && DTYPE == RR_U8) s = row_sum_u8(v, s);
                 if (DTYPE == RR_U8) {
                     v.x = shift_u8(v.x);
                     v.y = shift_u8(v.y);
@@ -78,17 +102,24 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
                     v.w = shift_u8(v.w);
                 }
                 A[t][ks] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
-                s = __builtin_amdgcn_sdot4((int)v.x, (int)v.x, s, false);
-                s = __builtin_amdgcn_sdot4((int)v.y, (int)v.y, s, false);
-                s = __builtin_amdgcn_sdot4((int)v.z, (int)v.z, s, false);
-                s = __builtin_amdgcn_sdot4((int)v.w, (int)v.w, s, false);
+                if (!IP) {
+                    s = __builtin_amdgcn_sdot4((int)v.x, (int)v.x, s, false);
+                    s = __builtin_amdgcn_sdot4((int)v.y, (int)v.y, s, false);
+                    s = __builtin_amdgcn_sdot4((int)v.z, (int)v.z, s, false);
+                    s = __builtin_amdgcn_sdot4((int)v.w, (int)v.w, s, false);
+                }
             }
         }
         // zero padding becomes -128 after the uint8 shift in queries and base
         // rows alike, so padded coordinates add (q'-x')^2 = 0 to the distance
         s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
-        qn_own[t] = s; // lanes with row == i hold |q_i'|^2
+        // lanes with row == i hold |q_i'|^2, or for the inner product the
+        // query part of the key: key_off (+ 128^2 P - 128 sum q for uint8)
+        if (IP)
+            s = (int)((uint32_t)a.ix.key_off +
+                      (DTYPE == RR_U8 ? (uint32_t)(16384 * KS * 64) - 128u * (uint32_t)s : 0u));
+        qn_own[t] = s;
     }
     int qn[QT][4];
     int64_t rthr[QT][4];
@@ -115,6 +146,7 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
         for (int ks = 0; ks < KSMAX; ++ks) {
             if (ks < ks_n) {
                 uint4 v = *reinterpret_cast<const uint4 *>(xr + ks * 64);
+                if (IP && DTYPE == RR_U8) xs = row_sum_u8(v, xs);
                 if (DTYPE == RR_U8) {
                     v.x = shift_u8(v.x);
                     v.y = shift_u8(v.y);
@@ -122,14 +154,17 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
                     v.w = shift_u8(v.w);
                 }
                 B[ks] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
-                xs = __builtin_amdgcn_sdot4((int)v.x, (int)v.x, xs, false);
-                xs = __builtin_amdgcn_sdot4((int)v.y, (int)v.y, xs, false);
-                xs = __builtin_amdgcn_sdot4((int)v.z, (int)v.z, xs, false);
-                xs = __builtin_amdgcn_sdot4((int)v.w, (int)v.w, xs, false);
+                if (!IP) {
+                    xs = __builtin_amdgcn_sdot4((int)v.x, (int)v.x, xs, false);
+                    xs = __builtin_amdgcn_sdot4((int)v.y, (int)v.y, xs, false);
+                    xs = __builtin_amdgcn_sdot4((int)v.z, (int)v.z, xs, false);
+                    xs = __builtin_amdgcn_sdot4((int)v.w, (int)v.w, xs, false);
+                }
             }
         }
         xs += __shfl_xor(xs, 16);
         xs += __shfl_xor(xs, 32);
+        if (IP) xs = -128 * xs; // the base row's part of the uint8 key (0 for int8)
         const bool pvalid = p0 + row < p_end;
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
@@ -139,12 +174,15 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
                 if (ks < ks_n) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t][ks], B[ks], acc, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int dd = qn[t][v] + xs - 2 * acc[v];
+                // L2: |q'|^2 + |x'|^2 - 2 q'.x'; inner product: the key
+                const int dd = IP ? (int)((uint32_t)qn[t][v] + (uint32_t)xs - (uint32_t)acc[v])
+                                  : qn[t][v] + xs - 2 * acc[v];
                 const uint32_t du = (uint32_t)dd;
                 if (mode == SCAN_NN) {
                     if (pvalid && du < best[t][v]) best[t][v] = du;
                 } else {
-                    const bool hit = pvalid && (int64_t)dd <= rthr[t][v];
+                    const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq &&
+                                     (int64_t)du <= rthr[t][v];
                     const unsigned long long hm = __ballot(hit);
                     if (hm) {
                         unsigned long long base = 0;
@@ -187,6 +225,7 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
 // B: lane l holds x[j=l%16][k=4s+l/16].  The FP64 output tile differs from
 // the integer one: lane l, register v holds row (l/16) + 4v, column l%16.
 #define F64_ROW(grp, v) ((grp) + 4 * (v))
+template <bool IP>
 __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -203,7 +242,8 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
         const int64_t q = min(q0 + t * 16 + row, a.nq - 1);
         const float *qr = (const float *)(a.qpad + q * a.ix.row_bytes);
         double s = 0;
-        for (int k = grp; k < d; k += 4) s = fma((double)qr[k], (double)qr[k], s);
+        if (!IP)
+            for (int k = grp; k < d; k += 4) s = fma((double)qr[k], (double)qr[k], s);
         s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
         qn_own[t] = s;
@@ -214,7 +254,9 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
         for (int v = 0; v < 4; ++v) {
             qn[t][v] = __shfl(qn_own[t], F64_ROW(grp, v));
             const int64_t q = q0 + t * 16 + F64_ROW(grp, v);
-            rr_[t][v] = (mode == SCAN_RANGE && q < a.nq) ? a.qth[q].r : -1.0;
+            // rows past nq never hit (the inner product has negative distances,
+            // so no finite sentinel radius would exclude them)
+            rr_[t][v] = (mode == SCAN_RANGE && q < a.nq) ? a.qth[q].r : -__builtin_huge_val();
             best[t][v] = __builtin_huge_val();
         }
     for (int64_t p0 = p_begin; p0 < p_end; p0 += 16) {
@@ -226,7 +268,7 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
         for (int s = 0; s < ksteps; ++s) {
             const int k = 4 * s + grp;
             const double xv = k < d ? (double)xr[k] : 0.0;
-            xs = fma(xv, xv, xs);
+            if (!IP) xs = fma(xv, xv, xs);
             for (int t = 0; t < QTF; ++t) {
                 const int64_t q = min(q0 + t * 16 + row, a.nq - 1);
                 const float *qr = (const float *)(a.qpad + q * a.ix.row_bytes);
@@ -239,12 +281,18 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
         const bool pvalid = p0 + row < p_end;
         for (int t = 0; t < QTF; ++t)
             for (int v = 0; v < 4; ++v) {
-                double dd = qn[t][v] + xs - 2.0 * acc[t][v];
-                if (dd < 0) dd = 0;
+                double dd;
+                if (IP) {
+                    dd = -acc[t][v];
+                } else {
+                    dd = qn[t][v] + xs - 2.0 * acc[t][v];
+                    if (dd < 0) dd = 0;
+                }
                 if (mode == SCAN_NN) {
                     if (pvalid && dd < best[t][v]) best[t][v] = dd;
                 } else {
-                    const bool hit = pvalid && dd <= rr_[t][v];
+                    const int64_t qrow = q0 + t * 16 + F64_ROW(grp, v);
+                    const bool hit = pvalid && qrow < a.nq && dd <= rr_[t][v];
                     const unsigned long long hm = __ballot(hit);
                     if (hm) {
                         unsigned long long base = 0;
@@ -274,15 +322,17 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
                 double b = best[t][v];
                 for (int m = 1; m < 16; m <<= 1) b = fmin(b, __shfl_xor(b, m));
                 const int64_t q = q0 + t * 16 + F64_ROW(grp, v);
-                if (row == 0 && q < a.nq) atomicMin(&a.nn_bits[q], (unsigned long long)__double_as_longlong(b));
+                if (row == 0 && q < a.nq) atomicMin(&a.nn_bits[q], dbl_order(b));
             }
     }
 }
 
-__global__ void k_nn_finish(const unsigned long long *bits, int64_t nq, int dtype, double *out) {
+__global__ void k_nn_finish(const unsigned long long *bits, int64_t nq, int dtype, int64_t key_off,
+                            double *out) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
          i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = dtype == RR_F32 ? __longlong_as_double((long long)bits[i]) : (double)(uint32_t)bits[i];
+        out[i] = dtype == RR_F32 ? dbl_unorder(bits[i])
+                                 : (double)(uint32_t)bits[i] - (double)key_off;
 }
 
 __global__ void k_identity_tasks(int32_t *task_q, int64_t nq, unsigned long long *counters) {
@@ -307,15 +357,19 @@ static hipError_t launch_scan(const ScanArgs &a0, int mode, hipStream_t s) {
         pblocks = (a.ix.n + a.chunk - 1) / a.chunk;
     }
     dim3 grid((unsigned)qblocks, (unsigned)pblocks), block(256);
+    const bool ip = a.ix.metric == RR_IP;
     if (a.ix.dtype == RR_F32) {
-        hipLaunchKernelGGL(k_scan_f32, grid, block, 0, s, a, mode);
+        if (ip) hipLaunchKernelGGL(k_scan_f32<true>, grid, block, 0, s, a, mode);
+        else hipLaunchKernelGGL(k_scan_f32<false>, grid, block, 0, s, a, mode);
         return hipGetLastError();
     }
     const int ks = a.ix.row_bytes / 64;
 #define RR_SCAN_KS(K)                                                                         \
     if (ks == K) {                                                                            \
-        if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K>), grid, block, 0, s, a, mode); \
-        else hipLaunchKernelGGL((k_scan_int<RR_I8, K>), grid, block, 0, s, a, mode);         \
+        if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true>), grid, block, 0, s, a, mode); \
+        else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false>), grid, block, 0, s, a, mode); \
+        else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true>), grid, block, 0, s, a, mode); \
+        else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false>), grid, block, 0, s, a, mode);  \
         return hipGetLastError();                                                             \
     }
     RR_SCAN_KS(1) RR_SCAN_KS(2) RR_SCAN_KS(3) RR_SCAN_KS(4) RR_SCAN_KS(6) RR_SCAN_KS(8)
@@ -336,7 +390,7 @@ hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, d
     e = launch_scan(a, SCAN_NN, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_nn_finish, dim3((unsigned)std::min<int64_t>((nq + 255) / 256, 4096)),
-                       dim3(256), 0, s, bits, nq, ix.dtype, nn);
+                       dim3(256), 0, s, bits, nq, ix.dtype, ix.key_off, nn);
     return hipGetLastError();
 }
 

@@ -272,8 +272,12 @@ void worker_main(rr_server *s) {
                 float *dst = (float *)f.dists.data();
                 for (int32_t j = 0; j < cnt; ++j) dst[j] = (float)src[j];
             } else {
-                const uint8_t *src = s->h_ad + (size_t)off * 4;
-                f.dists.assign(src, src + (size_t)cnt * 4);
+                // integer keys are key_off + d (mod 2^32)
+                const uint32_t *src = (const uint32_t *)s->h_ad + off;
+                const uint32_t ko = (uint32_t)s->view.key_off;
+                f.dists.resize((size_t)cnt * 4);
+                int32_t *dst = (int32_t *)f.dists.data();
+                for (int32_t j = 0; j < cnt; ++j) dst[j] = (int32_t)(src[j] - ko);
             }
             rr_completion c{};
             c.tag = sl.tag;

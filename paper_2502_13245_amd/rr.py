@@ -20,6 +20,7 @@ RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_EIO, RR_ESTATE, RR_EBUSY = range(7)
 U8, I8, F32 = 0, 1, 2
 PLAIN, ES, ADAPTIVE, DOUBLING = 0, 1, 2, 3
 EXACT, BF16_RECHECK = 0, 1
+L2, IP = 0, 1
 
 _MODES = {"plain": PLAIN, "es": ES, "adaptive": ADAPTIVE, "doubling": DOUBLING}
 
@@ -137,6 +138,8 @@ SIGNATURES = {
     "rr_index_info": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32)]),
+    "rr_index_set_metric": (C.c_int, [_VP, _I32]),
+    "rr_index_metric": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
     "rr_index_save": (C.c_int, [_VP, C.c_char_p]),
     "rr_index_load": (C.c_int, [C.c_char_p, C.POINTER(_VP)]),
     "rr_index_to_device": (C.c_int, [_VP, C.POINTER(Allocator), _VP]),
@@ -207,6 +210,14 @@ def _dtype_code(dt) -> int:
     raise TypeError(f"unsupported vector dtype {dt}")
 
 
+def _metric_code(metric) -> int:
+    if metric in (L2, "l2", "L2"):
+        return L2
+    if metric in (IP, "ip", "IP"):
+        return IP
+    raise ValueError(f"unknown metric {metric!r}")
+
+
 # ---------------------------------------------------------------------------
 # torch-backed device memory
 # ---------------------------------------------------------------------------
@@ -268,8 +279,9 @@ class Index:
 
     @staticmethod
     def build(base: np.ndarray, R=64, L=128, alpha=1.2, passes=2, threads=0, seed=0,
-              order=None, verbose=False) -> "Index":
-        """build_graph: DiskANN/Vamana construction on the host."""
+              order=None, verbose=False, metric="l2") -> "Index":
+        """build_graph: DiskANN/Vamana construction on the host (L2 graph;
+        `metric` is the distance the searches use)."""
         base = np.ascontiguousarray(base)
         bp = BuildParams()
         lib().rr_default_build_params(C.byref(bp))
@@ -281,10 +293,10 @@ class Index:
         out = C.c_void_p()
         _check(lib().rr_index_build(base.ctypes.data, _dtype_code(base.dtype), base.shape[0],
                                     base.shape[1], C.byref(bp), C.byref(out)))
-        return Index(out.value)
+        return Index(out.value).set_metric(metric)
 
     @staticmethod
-    def from_graph(base: np.ndarray, adj: np.ndarray, entry: int) -> "Index":
+    def from_graph(base: np.ndarray, adj: np.ndarray, entry: int, metric="l2") -> "Index":
         base = np.ascontiguousarray(base)
         adj = np.ascontiguousarray(adj, dtype=np.int32)
         out = C.c_void_p()
@@ -292,7 +304,19 @@ class Index:
                                          base.shape[0], base.shape[1],
                                          adj.ctypes.data_as(C.POINTER(C.c_int32)),
                                          adj.shape[1], int(entry), C.byref(out)))
-        return Index(out.value)
+        return Index(out.value).set_metric(metric)
+
+    def set_metric(self, metric):
+        """rr_index_set_metric: "l2" (squared Euclidean) or "ip" (negated
+        inner product); before to_device()."""
+        _check(lib().rr_index_set_metric(self._h, _metric_code(metric)))
+        return self
+
+    @property
+    def metric(self) -> str:
+        m = C.c_int32()
+        _check(lib().rr_index_metric(self._h, C.byref(m)))
+        return ("l2", "ip")[m.value]
 
     @staticmethod
     def load(path: str) -> "Index":

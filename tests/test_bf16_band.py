@@ -54,3 +54,37 @@ def test_bf16_rounding_matches_definition():
     assert bf16_round(np.array([1 + 3 * 2 ** -8], np.float32))[0] == 1 + 2 ** -6
     x = np.random.default_rng(1).standard_normal(1000).astype(np.float32)
     assert np.all(np.abs(bf16_round(x) - x) <= 2 ** -8 * np.abs(x))
+
+
+def approx_ip(xb, q, rng):
+    """float32 sum of products in a random order (one rounding per FMA)."""
+    acc = np.float32(0)
+    for i in rng.permutation(len(q)):
+        acc = np.float32(np.float64(xb[i]) * np.float64(q[i]) + np.float64(acc))
+    return acc
+
+
+def band_ip(r, maxnorm, qnorm, d, margin):
+    gamma = (d + 2) * 2.0 ** -24
+    delta = max(margin * abs(r), (2.0 ** -8 + gamma * (1 + 2.0 ** -8)) * maxnorm * qnorm * (1 + 1e-6))
+    return r - delta, r + delta
+
+
+def test_inner_product_band_brackets_the_exact_distance():
+    """d = -<x, q>: with r = d exactly, the approximate value lies inside
+    [lo, hi] for rows of any norm and for cancelling sums."""
+    rng = np.random.default_rng(2)
+    worst = 0.0
+    for d in (8, 96, 768):
+        for k in range(300):
+            q = (rng.standard_normal(d) * rng.uniform(0.1, 3.0)).astype(np.float32)
+            x = (rng.standard_normal(d) * rng.uniform(0.1, 3.0)).astype(np.float32)
+            if k % 3 == 0:  # nearly orthogonal: the sum cancels
+                x = (x - q * np.float32(np.dot(x, q) / np.dot(q, q))).astype(np.float32)
+            d64 = -float(np.dot(x.astype(np.float64), q.astype(np.float64)))
+            s = -float(approx_ip(bf16_round(x), q, rng))
+            maxnorm = float(np.linalg.norm(x.astype(np.float64)))
+            lo, hi = band_ip(d64, maxnorm, float(np.linalg.norm(q.astype(np.float64))), d, 0.0)
+            assert lo <= s <= hi, (d, s, lo, hi, d64)
+            worst = max(worst, abs(s - d64) / (hi - d64))
+    assert worst < 1.0
