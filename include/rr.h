@@ -74,8 +74,15 @@ typedef enum { RR_PLAIN = 0, RR_ES = 1, RR_ADAPTIVE = 2, RR_DOUBLING = 3 } rr_mo
  *  RR_BF16_RECHECK  traversal on a bfloat16 copy with FP32 accumulation;
  *                   a point whose approximate distance lies within a band of
  *                   the radius is re-decided from its float32 row in FP64, so
- *                   every membership decision of a returned point is exact. */
-typedef enum { RR_EXACT = 0, RR_BF16_RECHECK = 1 } rr_precision;
+ *                   every membership decision of a returned point is exact.
+ *  RR_SQ8_RERANK    the paper's setting for float data (Section 5): traversal
+ *                   on an 8-bit scalar-quantized copy (one affine map for all
+ *                   coordinates, x ~ lo + scale * code, codes 0..255) against
+ *                   the float32 query with FP32 accumulation, and the same
+ *                   exact FP64 re-decision of every point the quantized
+ *                   distance does not prove outside the ball.  Reads a
+ *                   quarter of the float32 bytes while traversing. */
+typedef enum { RR_EXACT = 0, RR_BF16_RECHECK = 1, RR_SQ8_RERANK = 2 } rr_precision;
 
 typedef struct rr_index rr_index;
 typedef struct rr_results rr_results;
@@ -197,8 +204,8 @@ rr_status rr_index_metric(const rr_index *idx, int32_t *metric);
 rr_status rr_index_save(const rr_index *idx, const char *path);
 rr_status rr_index_load(const char *path, rr_index **out);
 
-/* Upload padded vectors (and a bfloat16 copy for float32 data), the graph
- * and the entry to the current device.  Memory comes from `alloc`.  The
+/* Upload padded vectors (and, for float32 data, a bfloat16 copy and an 8-bit
+ * scalar-quantized copy), the graph and the entry to the current device.  Memory comes from `alloc`.  The
  * index is immutable afterwards; concurrent searches on several streams are
  * allowed.  Errors: RR_ENOMEM, RR_EHIP. */
 rr_status rr_index_to_device(rr_index *idx, const rr_allocator *alloc, void *stream);

@@ -379,7 +379,8 @@ static void free_device(rr_index *ix) {
     ix->alloc.release(ix->d_base);
     ix->alloc.release(ix->d_bf16);
     ix->alloc.release(ix->d_adj);
-    ix->d_base = ix->d_bf16 = ix->d_adj = nullptr;
+    ix->alloc.release(ix->d_sq8);
+    ix->d_base = ix->d_bf16 = ix->d_adj = ix->d_sq8 = nullptr;
     ix->on_device = false;
     if (cur >= 0) (void)hipSetDevice(cur);
 }
@@ -415,8 +416,8 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
     ix->on_device = true;
     HIP_TRY(hipMemcpyAsync(ix->d_base, pad.data(), pad.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int32_t rb16 = 0;
-    float maxn = 0.f;
+    int32_t rb16 = 0, rb8 = 0;
+    float maxn = 0.f, sq_lo = 0.f, sq_scale = 1.f;
     if (ix->dtype == RR_F32) {
         rb16 = padded_row_bytes((int64_t)ix->d * 2);
         std::vector<uint16_t> h((size_t)ix->n * (rb16 / 2), 0);
@@ -434,6 +435,32 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
         if (!ix->d_bf16) return fail(RR_ENOMEM, "device allocation failed");
         HIP_TRY(hipMemcpyAsync(ix->d_bf16, h.data(), h.size() * 2, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
+        // 8-bit scalar quantization: one affine map for every coordinate.  lo
+        // is rounded down and scale up to float so that [lo, lo + 255 scale]
+        // covers every value and each code is within scale/2 of its value.
+        double mn = INFINITY, mx = -INFINITY;
+        for (size_t i = 0; i < (size_t)ix->n * ix->d; ++i) {
+            mn = std::min(mn, (double)x[i]);
+            mx = std::max(mx, (double)x[i]);
+        }
+        float lo = (float)mn;
+        if ((double)lo > mn) lo = std::nextafter(lo, -INFINITY);
+        const double span = mx > mn ? (mx - (double)lo) / 255.0 : 1.0;
+        float sc = (float)span;
+        if ((double)sc < span) sc = std::nextafter(sc, INFINITY);
+        rb8 = padded_row_bytes((int64_t)ix->d);
+        std::vector<uint8_t> c8((size_t)ix->n * rb8, 0);
+        for (int64_t i = 0; i < ix->n; ++i)
+            for (int32_t j = 0; j < ix->d; ++j) {
+                const double v = std::rint(((double)x[(size_t)i * ix->d + j] - (double)lo) / (double)sc);
+                c8[(size_t)i * rb8 + j] = (uint8_t)std::min(255.0, std::max(0.0, v));
+            }
+        ix->d_sq8 = ix->alloc.alloc(c8.size());
+        if (!ix->d_sq8) return fail(RR_ENOMEM, "device allocation failed");
+        HIP_TRY(hipMemcpyAsync(ix->d_sq8, c8.data(), c8.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        sq_lo = lo;
+        sq_scale = sc;
     }
     const size_t adj_bytes = std::max<size_t>(ix->adj.size() * sizeof(int32_t), 4);
     ix->d_adj = ix->alloc.alloc(adj_bytes);
@@ -457,6 +484,10 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
     dv.base_bf16 = (const uint8_t *)ix->d_bf16;
     dv.adj = (const int32_t *)ix->d_adj;
     dv.max_norm = maxn;
+    dv.base_sq8 = (const uint8_t *)ix->d_sq8;
+    dv.row_bytes_sq8 = rb8;
+    dv.sq_lo = sq_lo;
+    dv.sq_scale = sq_scale;
     dv.metric = ix->metric;
     // integer inner product: keys key_off - <p, q> are >= 0 for every pair
     // (uint8: <p, q> <= 255^2 d; int8: |<p, q>| <= 128^2 d)
@@ -623,11 +654,13 @@ rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, Sea
     if (es && sp->es_visit_limit < 1) return fail(RR_EINVAL, "es_visit_limit must be >= 1");
     if (es && std::isnan(sp->es_radius)) return fail(RR_EINVAL, "es_radius is NaN");
     if (!(sp->lambda >= 0.0)) return fail(RR_EINVAL, "lambda must be >= 0");
-    if (sp->precision != RR_EXACT && sp->precision != RR_BF16_RECHECK)
+    if (sp->precision != RR_EXACT && sp->precision != RR_BF16_RECHECK &&
+        sp->precision != RR_SQ8_RERANK)
         return fail(RR_EINVAL, "unknown precision %d", sp->precision);
-    if (sp->precision == RR_BF16_RECHECK && ix->dtype != RR_F32)
-        return fail(RR_EINVAL, "bf16 precision needs float32 data");
-    if (sp->precision == RR_BF16_RECHECK && !(sp->recheck_margin >= 0.0))
+    const bool approx = sp->precision != RR_EXACT;
+    if (approx && ix->dtype != RR_F32)
+        return fail(RR_EINVAL, "bf16/sq8 precision needs float32 data");
+    if (approx && !(sp->recheck_margin >= 0.0))
         return fail(RR_EINVAL, "recheck_margin must be >= 0");
     if (ix->dev.dtype != ix->dtype) return fail(RR_ESTATE, "index state is inconsistent");
 
@@ -668,15 +701,22 @@ rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, Sea
     cfg.lambda = sp->lambda;
     cfg.bcap = (int32_t)bcap;
 
-    // the bf16 pass sends every result list through the sort/emit stage
-    const bool approx = sp->precision == RR_BF16_RECHECK;
+    // the approximate passes send every result list through the sort/emit stage
     const bool greedy = sp->mode == RR_ADAPTIVE || approx;
     DevIndex view = ix->dev;
-    if (approx) {
+    int32_t qrow = view.row_bytes;
+    if (sp->precision == RR_BF16_RECHECK) {
+        // float32 query beside bf16 rows: twice the row bytes
         view.base = ix->dev.base_bf16;
         view.row_bytes = ix->dev.row_bytes_bf16;
+        qrow = 2 * view.row_bytes;
+    } else if (sp->precision == RR_SQ8_RERANK) {
+        // the query prepared for the codes (float32, 4 bytes per code), then
+        // the float32 query itself for the re-decision
+        view.base = ix->dev.base_sq8;
+        view.row_bytes = ix->dev.row_bytes_sq8;
+        qrow = 8 * view.row_bytes;
     }
-    const int32_t qrow = approx ? 2 * view.row_bytes : view.row_bytes;
     *cfg_out = cfg;
     *view_out = view;
     *qrow_out = qrow;
@@ -1001,10 +1041,11 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
     if (agg) {
         std::memset(agg, 0, sizeof *agg);
         agg->nq = res->nq;
-        // the bf16 pass reads 2 bytes per coordinate while searching and the
-        // float32 row of every rechecked or returned point
-        const bool approx = res->precision == RR_BF16_RECHECK;
-        const int64_t row = (int64_t)res->d * (approx ? 2 : res->es);
+        // the bf16 (sq8) pass reads 2 (1) bytes per coordinate while searching
+        // and the float32 row of every rechecked or returned point
+        const bool approx = res->precision != RR_EXACT;
+        const int64_t row = (int64_t)res->d *
+                            (res->precision == RR_BF16_RECHECK ? 2 : res->precision == RR_SQ8_RERANK ? 1 : res->es);
         const int64_t exact_row = approx ? (int64_t)res->d * 4 : 0;
         for (int64_t i = 0; i < res->nq; ++i) {
             const rr_query_stats &q = st[i];

@@ -48,6 +48,9 @@ struct DevIndex {
     float max_norm = 0.f; // largest |x| (float data)
     int32_t metric = 0;   // rr_metric
     int64_t key_off = 0;  // integer data, inner product: keys are key_off - <p, q>
+    const uint8_t *base_sq8 = nullptr; // float data: 8-bit codes, x ~ sq_lo + sq_scale * code
+    int32_t row_bytes_sq8 = 0;
+    float sq_lo = 0.f, sq_scale = 1.f;
 };
 
 // Per-query thresholds derived from the radius (written by a prep kernel).
@@ -208,7 +211,7 @@ struct rr_index {
     bool on_device = false;
     int device = -1;
     rr::Allocator alloc;
-    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr;
+    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr, *d_sq8 = nullptr;
     rr::DevIndex dev;
 };
 

@@ -217,14 +217,19 @@ __device__ __forceinline__ int lower_bound_key(const D *ad, const uint32_t *ai, 
 // Internal data type of the approximate pass on float data: rows are the
 // bfloat16 copy, the query stays float32, squares accumulate in float32.
 constexpr int RR_BF16X = 3;
+// Internal data type of the 8-bit scalar-quantized pass: rows are codes,
+// the query is float32 (prepared for the codes), sums accumulate in float32.
+constexpr int RR_SQ8X = 4;
 // Kernel data type = element type (low bits) | RR_IPBIT for the negated
 // inner product (Section 2), so both metrics share every kernel template.
 constexpr int RR_IPBIT = 8;
 __host__ __device__ constexpr int dbase(int dt) { return dt & 7; }
 __host__ __device__ constexpr bool dip(int dt) { return (dt & RR_IPBIT) != 0; }
-__host__ __device__ constexpr bool dfloat(int dt) { return dbase(dt) == RR_F32 || dbase(dt) == RR_BF16X; }
+// an approximate pass whose candidates are re-decided on the float32 rows
+__host__ __device__ constexpr bool dapprox(int dt) { return dbase(dt) == RR_BF16X || dbase(dt) == RR_SQ8X; }
+__host__ __device__ constexpr bool dfloat(int dt) { return dbase(dt) == RR_F32 || dapprox(dt); }
 constexpr int RR_U8IP = RR_U8 | RR_IPBIT, RR_I8IP = RR_I8 | RR_IPBIT, RR_F32IP = RR_F32 | RR_IPBIT,
-              RR_BF16XIP = RR_BF16X | RR_IPBIT;
+              RR_BF16XIP = RR_BF16X | RR_IPBIT, RR_SQ8XIP = RR_SQ8X | RR_IPBIT;
 
 // T: the search key; Acc: the accumulator; O: the distance that decides
 // membership and is reported (exact for every type).  Integer keys are
@@ -234,6 +239,7 @@ template <> struct DistBase<RR_U8> { using T = uint32_t; using Acc = int; using 
 template <> struct DistBase<RR_I8> { using T = uint32_t; using Acc = int; using O = uint32_t; };
 template <> struct DistBase<RR_F32> { using T = double; using Acc = double; using O = double; };
 template <> struct DistBase<RR_BF16X> { using T = float; using Acc = float; using O = double; };
+template <> struct DistBase<RR_SQ8X> { using T = float; using Acc = float; using O = double; };
 template <int DTYPE> struct DistOf : DistBase<dbase(DTYPE)> {};
 
 template <int DTYPE>
@@ -332,6 +338,42 @@ __device__ __forceinline__ float chunk_ip_bf16(uint4 p, uint4 q0, uint4 q1) {
     return a;
 }
 
+// 8-bit code chunk (16 codes) against 16 float32 query values prepared for
+// the codes (q' = (q - lo) / scale): sum of squared differences in code
+// units, float32 accumulation; the caller scales by scale^2
+__device__ __forceinline__ float chunk_part_sq8(uint4 p, const uint4 *qc) {
+    const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint4 q = qc[j];
+        const float qa[4] = {__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
+                             __uint_as_float(q.w)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float t = (float)((w[j] >> (8 * k)) & 0xffu) - qa[k];
+            a = fmaf(t, t, a);
+        }
+    }
+    return a;
+}
+
+// the same for the inner product: sum of code * q (the caller scales by
+// -scale; the lo <q, 1> part is a per-query constant kept in the thresholds)
+__device__ __forceinline__ float chunk_ip_sq8(uint4 p, const uint4 *qc) {
+    const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint4 q = qc[j];
+        const float qa[4] = {__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
+                             __uint_as_float(q.w)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a = fmaf((float)((w[j] >> (8 * k)) & 0xffu), qa[k], a);
+    }
+    return a;
+}
+
 // exact distance of a float32 row for the recheck, in FP64 over the
 // zero-padded rows: the sum of squared differences, or -<x, q>
 template <bool IP>
@@ -385,16 +427,21 @@ template <> __device__ __forceinline__ int chunk_qq<RR_I8>(uint4 q) {
 // Query state held by each lane: its CPL chunks of the padded query row.
 // For the bfloat16 pass each 16-byte row chunk (8 values) pairs with 32
 // bytes of the float32 query, so a lane holds 2*CPL query chunks.
+// For the 8-bit pass each 16-byte chunk (16 codes) pairs with 64 bytes of
+// float32 query, so a lane holds 4*CPL query chunks; the float32 query for
+// the re-decision follows the prepared one in the query row.
 template <int DTYPE, int CPL, int G> struct QueryRegs {
-    static constexpr int QC = dbase(DTYPE) == RR_BF16X ? 2 * CPL : CPL;
+    static constexpr int QC = dbase(DTYPE) == RR_BF16X ? 2 * CPL : dbase(DTYPE) == RR_SQ8X ? 4 * CPL : CPL;
     static constexpr bool L2INT = !dfloat(DTYPE) && !dip(DTYPE);
     uint4 c[QC];
     int qq; // integer data: |q|^2 (L2) or the key offset (inner product)
-    const uint8_t *row; // the padded query row (the recheck reads it)
+    float sc; // 8-bit pass: scale^2 (L2) or -scale (inner product)
+    const uint8_t *row; // the padded float32 query row (the recheck reads it)
 
     __device__ __forceinline__ void load(const uint8_t *qrow, const DevIndex &ix) {
         const int gl = lane_id() & (G - 1);
-        row = qrow;
+        row = dbase(DTYPE) == RR_SQ8X ? qrow + 4 * (size_t)ix.row_bytes : qrow;
+        sc = dip(DTYPE) ? -ix.sq_scale : ix.sq_scale * ix.sq_scale;
         int s = 0;
 #pragma unroll
         for (int k = 0; k < QC; ++k) {
@@ -446,6 +493,10 @@ __device__ __forceinline__ void eval_rows(const DevIndex &ix, const QueryRegs<DT
                     a += chunk_part_bf16(buf[rb][kk], qr.c[2 * kk], qr.c[2 * kk + 1]);
                 else if constexpr (DTYPE == RR_BF16XIP)
                     a += chunk_ip_bf16(buf[rb][kk], qr.c[2 * kk], qr.c[2 * kk + 1]);
+                else if constexpr (DTYPE == RR_SQ8X)
+                    a += chunk_part_sq8(buf[rb][kk], &qr.c[4 * kk]);
+                else if constexpr (DTYPE == RR_SQ8XIP)
+                    a += chunk_ip_sq8(buf[rb][kk], &qr.c[4 * kk]);
                 else if constexpr (dip(DTYPE))
                     a += chunk_ip<dbase(DTYPE)>(buf[rb][kk], qr.c[kk]);
                 else
@@ -454,7 +505,8 @@ __device__ __forceinline__ void eval_rows(const DevIndex &ix, const QueryRegs<DT
             a = group_sum<G>(a);
             const int c = (r0 + rb) * RPR + grp;
             if (gl == 0 && c < k) {
-                if constexpr (dfloat(DTYPE)) cd[c] = dip(DTYPE) ? -a : a;
+                if constexpr (dbase(DTYPE) == RR_SQ8X) cd[c] = a * qr.sc;
+                else if constexpr (dfloat(DTYPE)) cd[c] = dip(DTYPE) ? -a : a;
                 else if constexpr (dip(DTYPE)) cd[c] = (uint32_t)qr.qq - (uint32_t)a;
                 else cd[c] = (uint32_t)(a + qr.qq);
             }
@@ -490,14 +542,19 @@ template <> __device__ __forceinline__ bool beyond_esr<float>(float d, const QTh
 // the kernels' data type: the index dtype, or the bfloat16 pass, with the
 // metric bit
 static int kernel_dtype(const DevIndex &ix, const SearchCfg &cfg) {
-    const int b = (ix.dtype == RR_F32 && cfg.precision == RR_BF16_RECHECK) ? RR_BF16X : ix.dtype;
+    int b = ix.dtype;
+    if (ix.dtype == RR_F32 && cfg.precision == RR_BF16_RECHECK) b = RR_BF16X;
+    if (ix.dtype == RR_F32 && cfg.precision == RR_SQ8_RERANK) b = RR_SQ8X;
     return b | (ix.metric == RR_IP ? RR_IPBIT : 0);
 }
 
 // stride of the padded query rows: the bfloat16 pass keeps float32 queries
-// next to bf16 rows, so its query rows are twice the row stride
+// next to bf16 rows (twice the row stride); the 8-bit pass keeps the query
+// prepared for the codes and the float32 query (4 + 4 times the stride)
 template <int DTYPE> __device__ __forceinline__ size_t qrow_stride(const DevIndex &ix) {
-    return dbase(DTYPE) == RR_BF16X ? 2 * (size_t)ix.row_bytes : (size_t)ix.row_bytes;
+    return dbase(DTYPE) == RR_BF16X ? 2 * (size_t)ix.row_bytes
+           : dbase(DTYPE) == RR_SQ8X ? 8 * (size_t)ix.row_bytes
+                                     : (size_t)ix.row_bytes;
 }
 
 // --------------------------------------------------------------------------
@@ -513,58 +570,62 @@ __device__ int64_t floor_key(double r, int64_t key_off) {
     return k < 0 ? -1 : k;
 }
 
-// Band of the approximate pass (squared units).  With x^ the bfloat16 row
-// (per-coordinate relative rounding <= 2^-8, so |x^ - x| <= 2^-8 |x|) and
-// float32 accumulation of d squared differences (relative error <= gamma =
-// (d + 2) 2^-24), s > (1 + gamma)(r + delta)^2 with delta >= 2^-8 max|x|
-// proves |x - q| > r.  lo is the matching lower edge: below it the point is
-// certainly inside (reported as "rechecked" only in between).
-__device__ void band(double r2, double maxnorm, int d, double margin, float *lo, float *hi) {
+// Band of an approximate pass on squared L2 units.  If the approximate pass
+// sees the point at most delta0 away from its true position (unsquared)
+// and accumulates with relative error <= gamma, then s > (1 + gamma)
+// (r + delta)^2, delta >= delta0, proves |x - q| > r.  lo is the matching
+// lower edge: below it the point is certainly inside (reported as
+// "rechecked" only in between).
+__device__ void band_l2(double r2, double delta0, double gamma, double margin, float *lo, float *hi) {
     if (!(r2 >= 0.0)) {
         *lo = -1.f;
         *hi = -1.f;
         return;
     }
     const double r = sqrt(r2);
-    const double gamma = (double)(d + 2) * 0x1p-24;
-    const double delta = fmax(margin * r, 0x1p-8 * maxnorm * (1.0 + 1e-6));
+    const double delta = fmax(margin * r, delta0);
     const double h = (1.0 + gamma) * (r + delta) * (r + delta);
     *hi = __double2float_ru(h);
     const double l = r > delta ? (1.0 - gamma) * (r - delta) * (r - delta) : -1.0;
     *lo = __double2float_rd(l);
 }
 
-// Band of the approximate pass for the negated inner product: the bfloat16
-// row moves <x, q> by at most 2^-8 sum |x_i q_i| <= 2^-8 max|x| |q|, float32
-// accumulation by at most gamma (1 + 2^-8) max|x| |q|, so s > r + delta
-// proves -<x, q> > r and s < r - delta proves the opposite.
-__device__ void band_ip(double r, double maxnorm, double qnorm, int d, double margin, float *lo,
-                        float *hi) {
-    const double gamma = (double)(d + 2) * 0x1p-24;
-    const double delta = fmax(margin * fabs(r),
-                              (0x1p-8 + gamma * (1.0 + 0x1p-8)) * maxnorm * qnorm * (1.0 + 1e-6));
-    *hi = __double2float_ru(r + delta);
-    *lo = __double2float_rd(r - delta);
+// Band of an approximate pass on the negated inner product: the approximate
+// key is within delta0 of the true distance plus `shift` (a per-query
+// constant the pass leaves out).
+__device__ void band_ip(double r, double shift, double delta0, double margin, float *lo, float *hi) {
+    const double c = r + shift;
+    const double delta = fmax(margin * fabs(r), delta0) + 0x1p-50 * (fabs(r) + fabs(shift));
+    *hi = __double2float_ru(c + delta);
+    *lo = __double2float_rd(c - delta);
 }
 
-// pads query qi into row dst[qi] (qi when dst is null) and derives its
-// thresholds; a non-null `state` marks the destination slots as fresh
+enum { PASS_EXACT = 0, PASS_BF16 = 1, PASS_SQ8 = 2 };
+
+// Pads query qi into row dst[qi] (qi when dst is null) and derives its
+// thresholds; a non-null `state` marks the destination slots as fresh.
+// Exact and bfloat16 passes copy the row (zero padded to row_out bytes).
+// The 8-bit pass writes two halves of row_out/2 bytes: the float32 query
+// prepared for the codes (L2: (q - lo) / scale; inner product: q itself),
+// then the float32 query for the re-decision.
 __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int32_t row_out,
                                double radius, const double *radius_dev, double esr,
                                QThresh *qth, uint8_t *qpad, double maxnorm, int d,
-                               double margin, int approx, int ip, int64_t key_off,
-                               const int32_t *dst, BeamState *state) {
+                               double margin, int pass, int ip, int64_t key_off, float sq_lo,
+                               float sq_scale, const int32_t *dst, BeamState *state) {
     const int64_t chunks = row_out / 16;
     const int64_t tot = nq * chunks;
+    const int64_t half = row_out / 2;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t qi = t / chunks;
         const int64_t c = t % chunks;
         const int64_t qo = dst ? (int64_t)dst[qi] : qi;
+        const int64_t src = pass == PASS_SQ8 ? (c * 16) % half : c * 16;
         uint8_t b[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int64_t o = c * 16 + i;
+            const int64_t o = src + i;
             b[i] = o < row_in ? q[qi * row_in + o] : 0;
         }
         uint4 v;
@@ -572,6 +633,15 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
         v.y = b[4] | (b[5] << 8) | (b[6] << 16) | ((uint32_t)b[7] << 24);
         v.z = b[8] | (b[9] << 8) | (b[10] << 16) | ((uint32_t)b[11] << 24);
         v.w = b[12] | (b[13] << 8) | (b[14] << 16) | ((uint32_t)b[15] << 24);
+        if (pass == PASS_SQ8 && !ip && c * 16 < half) {
+            // codes are compared with (q - lo) / scale; padding stays 0
+            uint32_t *w = &v.x;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (src + 4 * k < row_in)
+                    w[k] = __float_as_uint(
+                        (float)(((double)__uint_as_float(w[k]) - (double)sq_lo) / (double)sq_scale));
+        }
         *reinterpret_cast<uint4 *>(qpad + qo * row_out + c * 16) = v;
         if (c == 0) {
             QThresh th;
@@ -584,13 +654,42 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
             th.esr_f = (float)esr;
             th.lo = -1.f;
             th.hi = -1.f;
-            if (approx && !ip) band(r, maxnorm, d, margin, &th.lo, &th.hi);
-            if (approx && ip) {
-                // |q| of the float32 query row
+            if (pass != PASS_EXACT) {
+                // norms of the float32 query row
                 const float *qf = reinterpret_cast<const float *>(q + qi * row_in);
-                double qn = 0.0;
-                for (int i = 0; i < d; ++i) qn = fma((double)qf[i], (double)qf[i], qn);
-                band_ip(r, maxnorm, sqrt(qn), d, margin, &th.lo, &th.hi);
+                double n2 = 0.0, n1 = 0.0, sum = 0.0, dl2 = 0.0;
+                for (int i = 0; i < d; ++i) {
+                    const double x = (double)qf[i];
+                    n2 = fma(x, x, n2);
+                    n1 += fabs(x);
+                    sum += x;
+                    dl2 = fma(x - (double)sq_lo, x - (double)sq_lo, dl2);
+                }
+                const double u = 0x1p-24, slack = 1.0 + 1e-6;
+                if (pass == PASS_BF16 && !ip) {
+                    // bf16 rows: |x^ - x| <= 2^-8 |x| per coordinate
+                    band_l2(r, 0x1p-8 * maxnorm * slack, (double)(d + 2) * u, margin, &th.lo, &th.hi);
+                } else if (pass == PASS_BF16) {
+                    // |<x^ - x, q>| <= 2^-8 max|x| |q|, float32 sum error
+                    // <= gamma (1 + 2^-8) max|x| |q|
+                    const double g = (double)(d + 2) * u;
+                    band_ip(r, 0.0, (0x1p-8 + g * (1.0 + 0x1p-8)) * maxnorm * sqrt(n2) * slack, margin,
+                            &th.lo, &th.hi);
+                } else if (!ip) {
+                    // codes: within scale/2 per coordinate; the prepared query
+                    // within 2^-24 |q_i - lo| (in value units) per coordinate
+                    band_l2(r, (0.5 * (double)sq_scale * sqrt((double)d) + u * sqrt(dl2)) * slack,
+                            (double)(d + 4) * u, margin, &th.lo, &th.hi);
+                } else {
+                    // key = -scale sum(code q) = d + lo sum(q) + error, with
+                    // |error| <= scale |q|_1 (1/2 + 255 (d + 2) 2^-24)
+                    const double shift = (double)sq_lo * sum;
+                    const double delta0 =
+                        (double)sq_scale * n1 * (0.5 + 255.0 * (double)(d + 2) * u) * slack;
+                    band_ip(r, shift, delta0, margin, &th.lo, &th.hi);
+                    th.r_f = (float)(r + shift);
+                    th.esr_f = (float)(esr + shift);
+                }
             }
             qth[qo] = th;
             if (state) {
@@ -601,23 +700,29 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
     }
 }
 
+// the prep kernel's pass and output row width for a search configuration
+static void prep_shape(const DevIndex &ix, const SearchCfg &cfg, int *pass, int32_t *row_out) {
+    const int kd = dbase(kernel_dtype(ix, cfg));
+    *pass = kd == RR_BF16X ? PASS_BF16 : kd == RR_SQ8X ? PASS_SQ8 : PASS_EXACT;
+    *row_out = kd == RR_BF16X ? 2 * ix.row_bytes : kd == RR_SQ8X ? 8 * ix.row_bytes : ix.row_bytes;
+}
+
 hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t nq, double radius,
                                const double *radius_dev, const SearchCfg &cfg, SearchBufs &sb,
                                hipStream_t s) {
     if (nq == 0) return hipSuccess;
     const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
-    const int approx = dbase(kernel_dtype(ix, cfg)) == RR_BF16X;
-    // the approximate pass pairs each bf16 row chunk with twice its bytes of
-    // float32 query
-    const int32_t row_out = approx ? 2 * ix.row_bytes : ix.row_bytes;
+    int pass = 0;
+    int32_t row_out = 0;
+    prep_shape(ix, cfg, &pass, &row_out);
     const int64_t tot = nq * (row_out / 16);
     int blocks = (int)((tot + 255) / 256);
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s,
                        (const uint8_t *)queries, nq, ix.d * esz, row_out, radius, radius_dev,
-                       cfg.esr, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, approx,
-                       (int)(ix.metric == RR_IP), ix.key_off, (const int32_t *)nullptr,
-                       (BeamState *)nullptr);
+                       cfg.esr, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, pass,
+                       (int)(ix.metric == RR_IP), ix.key_off, ix.sq_lo, ix.sq_scale,
+                       (const int32_t *)nullptr, (BeamState *)nullptr);
     return hipGetLastError();
 }
 
@@ -626,14 +731,15 @@ hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
                              SearchBufs &sb, BeamState *state, hipStream_t s) {
     if (k == 0) return hipSuccess;
     const int32_t esz = ix.dtype == RR_F32 ? 4 : 1;
-    const int approx = dbase(kernel_dtype(ix, cfg)) == RR_BF16X;
-    const int32_t row_out = approx ? 2 * ix.row_bytes : ix.row_bytes;
+    int pass = 0;
+    int32_t row_out = 0;
+    prep_shape(ix, cfg, &pass, &row_out);
     const int64_t tot = k * (row_out / 16);
     int blocks = (int)std::min<int64_t>((tot + 255) / 256, 65536);
     hipLaunchKernelGGL(k_prep_queries, dim3(blocks), dim3(256), 0, s, (const uint8_t *)queries, k,
                        ix.d * esz, row_out, 0.0, radius_dev, cfg.esr, sb.qth, sb.qpad,
-                       (double)ix.max_norm, ix.d, cfg.margin, approx, (int)(ix.metric == RR_IP),
-                       ix.key_off, dst, state);
+                       (double)ix.max_norm, ix.d, cfg.margin, pass, (int)(ix.metric == RR_IP),
+                       ix.key_off, ix.sq_lo, ix.sq_scale, dst, state);
     return hipGetLastError();
 }
 
@@ -894,7 +1000,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         // the sorted beam.  Approximate pass: the prefix with s <= hi holds
         // every possible member; each is re-decided on its exact distance.
         int cN = 0, cH = 0, nband = 0;
-        if constexpr (dbase(DTYPE) == RR_BF16X) {
+        if constexpr (dapprox(DTYPE)) {
             for (int base = 0; base < nB; base += 64) {
                 const int i = base + lane;
                 const int c = __popcll(__ballot(i < nB && bd[i] <= th.hi));
@@ -922,7 +1028,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         const bool expand = expand_flag && cN > 0;
         // results of the approximate pass are sorted by exact distance in the
         // finalisation, so every non-empty query becomes a task there
-        const bool as_task = expand || (dbase(DTYPE) == RR_BF16X && cN > 0);
+        const bool as_task = expand || (dapprox(DTYPE) && cN > 0);
         rr_query_stats st;
         st.visits = visits;
         st.evals = evals;
@@ -965,7 +1071,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             int written = 0;
             O *idist = (O *)a.sb.item_dist;
             const int64_t hmask = a.sb.hash_cap - 1;
-            if constexpr (dbase(DTYPE) == RR_BF16X) {
+            if constexpr (dapprox(DTYPE)) {
                 for (int base = 0; base < cH; base += 64) {
                     const int i = base + lane;
                     double dx = 0.0;
@@ -1577,7 +1683,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
                 uint32_t myi = 0;
                 if (i < k) {
                     myi = qi[i];
-                    if constexpr (dbase(DTYPE) == RR_BF16X) {
+                    if constexpr (dapprox(DTYPE)) {
                         // approximate distance above hi: provably outside the
                         // ball; otherwise the exact distance decides
                         if (qd[i] <= th.hi) {
@@ -1589,7 +1695,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
                         inr = in_range<D>(qd[i], th);
                     }
                 }
-                if constexpr (dbase(DTYPE) == RR_BF16X) {
+                if constexpr (dapprox(DTYPE)) {
                     const int nb = __popcll(__ballot(i < k && qd[i] > th.lo && qd[i] <= th.hi));
                     run_rechk += (unsigned long long)nb;
                 }
@@ -2169,6 +2275,8 @@ static hipError_t dispatch_beam(const DevIndex &ix, int64_t nq, const SearchCfg 
     RR_SPLITS(X, RR_I8IP)
     RR_SPLITS(X, RR_F32IP)
     RR_SPLITS(X, RR_BF16XIP)
+    RR_SPLITS(X, RR_SQ8X)
+    RR_SPLITS(X, RR_SQ8XIP)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -2284,6 +2392,8 @@ hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, S
     RR_SPLITS(X, RR_I8IP)
     RR_SPLITS(X, RR_F32IP)
     RR_SPLITS(X, RR_BF16XIP)
+    RR_SPLITS(X, RR_SQ8X)
+    RR_SPLITS(X, RR_SQ8XIP)
 #undef X
     return hipErrorInvalidValue;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_EIO, RR_ESTATE, RR_EBUSY = range(7)
 U8, I8, F32 = 0, 1, 2
 PLAIN, ES, ADAPTIVE, DOUBLING = 0, 1, 2, 3
-EXACT, BF16_RECHECK = 0, 1
+EXACT, BF16_RECHECK, SQ8_RERANK = 0, 1, 2
 L2, IP = 0, 1
 
 _MODES = {"plain": PLAIN, "es": ES, "adaptive": ADAPTIVE, "doubling": DOUBLING}

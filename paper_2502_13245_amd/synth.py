@@ -105,6 +105,52 @@ def gaussian_mixture_unit(n: int, nq: int, d: int, k: int, sigma: float, seed: i
     return Workload(name, base, queries, meta)
 
 
+def latent_mixture_f32(n: int, nq: int, d: int, k: int, sigma: float, seed: int, *,
+                       latent: int = 16, within: int = 10, noise: float = 0.05,
+                       spread: float = 0.35, zipf: float = 1.0, unit: bool = True,
+                       chunk: int = 0, name: str = "latent-f32") -> Workload:
+    """float32 mixture with low intrinsic dimension, like text or image
+    embeddings.  Centres lie on a `latent`-dimensional Gaussian sheet
+    (c = A u, per-coordinate std 1); each cluster varies along its own
+    `within`-dimensional random basis with per-coordinate std sigma_k =
+    sigma exp(U[-spread, spread]), plus isotropic noise of std `noise`.
+    Zipf(`zipf`) cluster sizes.  With `unit` every row is scaled to norm 1
+    (in float64).  Unlike centres drawn independently on the sphere, nearby
+    centres exist at every scale, so a proximity graph can be navigated."""
+    ss = np.random.SeedSequence(seed).spawn(7)
+    r_c, r_s, r_l, r_x, r_ql, r_qx, r_b = [np.random.default_rng(x) for x in ss]
+    A = r_c.standard_normal((d, latent)) / np.sqrt(latent)
+    centers = r_c.standard_normal((k, latent)) @ A.T
+    scale = sigma * np.exp(r_s.uniform(-spread, spread, size=k))
+    basis = r_b.standard_normal((k, d, within)) / np.sqrt(within)
+    if chunk <= 0:
+        chunk = max(1024, (1 << 25) // d)  # bounds the float64 work array
+
+    def draw(m, rl, rx):
+        lab = _labels(rl, k, m, zipf)
+        out = np.empty((m, d), dtype=np.float32)
+        for a in range(0, m, chunk):
+            b = min(m, a + chunk)
+            L = lab[a:b]
+            z = rx.standard_normal(size=(b - a, within)) * scale[L, None]
+            v = centers[L] + noise * rx.standard_normal(size=(b - a, d))
+            # the within-cluster part, one product per cluster present
+            order = np.argsort(L, kind="stable")
+            for grp in np.split(order, np.flatnonzero(np.diff(L[order])) + 1):
+                v[grp] += z[grp] @ basis[L[grp[0]]].T
+            if unit:
+                v /= np.linalg.norm(v, axis=1, keepdims=True)
+            out[a:b] = v.astype(np.float32)
+        return out
+
+    base = draw(n, r_l, r_x)
+    queries = draw(nq, r_ql, r_qx)
+    meta = dict(generator="latent_mixture_f32", n=n, nq=nq, d=d, k=k, sigma=sigma, seed=seed,
+                latent=latent, within=within, noise=noise, spread=spread, zipf=zipf, unit=unit,
+                dtype="float32")
+    return Workload(name, base, queries, meta)
+
+
 def latent_mixture_u8(n: int, nq: int, d: int, k: int, sigma: float, seed: int, *,
                       latent: int = 16, center_std: float = 40.0, within: int = 10,
                       noise: float = 4.0, spread: float = 0.35, zipf: float = 1.0,
@@ -223,9 +269,9 @@ def config_1m_u8(seed: int = 1, n: int = 1_000_000, nq: int = 10_000) -> Workloa
 
 
 def config_1m_f32(seed: int = 2, n: int = 1_000_000, nq: int = 10_000) -> Workload:
-    """1M base + 10,000 queries, d=96 float32 unit-norm, 2,000 directions."""
-    return gaussian_mixture_unit(n, nq, 96, 2_000, 0.3 / np.sqrt(96), seed, spread=0.3,
-                                 name=f"f32-{n // 1000}k-d96")
+    """1M base + 10,000 queries, d=96 float32 unit-norm embeddings: 2,000
+    clusters on a 16-dimensional sheet, Zipf cluster sizes."""
+    return latent_mixture_f32(n, nq, 96, 2_000, 0.35, seed, name=f"f32-{n // 1000}k-d96")
 
 
 def config_i8(seed: int = 3, n: int = 10_000_000, nq: int = 100_000) -> Workload:

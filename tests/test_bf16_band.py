@@ -1,6 +1,7 @@
-"""The approximate pass's band (bf16 rows, float32 accumulation) against an
-emulation of that arithmetic on the CPU: a point inside the radius must
-never compute above the band's upper edge, whatever the summation order."""
+"""The approximate passes' bands (bf16 rows or 8-bit codes, float32
+accumulation) against an emulation of that arithmetic on the CPU: a point
+inside the radius must never compute above the band's upper edge, whatever
+the summation order, for squared L2 and for the negated inner product."""
 import numpy as np
 
 
@@ -88,3 +89,64 @@ def test_inner_product_band_brackets_the_exact_distance():
             assert lo <= s <= hi, (d, s, lo, hi, d64)
             worst = max(worst, abs(s - d64) / (hi - d64))
     assert worst < 1.0
+
+
+def sq8_params(base):
+    """One affine map for all coordinates: lo rounded down and scale rounded
+    up to float32 so that [lo, lo + 255 scale] covers every value."""
+    mn, mx = float(base.min()), float(base.max())
+    lo = np.float32(mn)
+    if float(lo) > mn:
+        lo = np.nextafter(lo, np.float32(-np.inf))
+    span = (mx - float(lo)) / 255.0 if mx > mn else 1.0
+    sc = np.float32(span)
+    if float(sc) < span:
+        sc = np.nextafter(sc, np.float32(np.inf))
+    codes = np.clip(np.rint((base.astype(np.float64) - float(lo)) / float(sc)), 0, 255)
+    return lo, sc, codes.astype(np.uint8)
+
+
+def sq8_approx_l2(code, q, lo, sc, rng):
+    qp = ((q.astype(np.float64) - float(lo)) / float(sc)).astype(np.float32)
+    acc = np.float32(0)
+    for i in rng.permutation(len(q)):
+        t = np.float32(np.float32(code[i]) - qp[i])
+        acc = np.float32(np.float64(t) * np.float64(t) + np.float64(acc))
+    return np.float32(acc * np.float32(sc * sc))
+
+
+def sq8_approx_ip(code, q, sc, rng):
+    acc = np.float32(0)
+    for i in rng.permutation(len(q)):
+        acc = np.float32(np.float64(np.float32(code[i])) * np.float64(q[i]) + np.float64(acc))
+    return np.float32(acc * np.float32(-sc))
+
+
+def test_sq8_bands_bracket_the_exact_distance():
+    rng = np.random.default_rng(3)
+    u = 2.0 ** -24
+    for d in (8, 96, 768):
+        base = (rng.standard_normal((200, d)) * rng.uniform(0.05, 2.0, (200, 1))).astype(np.float32)
+        lo, sc, codes = sq8_params(base)
+        xh = float(lo) + float(sc) * codes.astype(np.float64)
+        assert np.all(np.abs(xh - base) <= float(sc) / 2 * (1 + 1e-12))
+        for k in range(100):
+            q = (rng.standard_normal(d) * rng.uniform(0.05, 2.0)).astype(np.float32)
+            i = k % len(base)
+            x = base[i].astype(np.float64)
+            # squared L2 at r = the exact distance
+            e2 = float(((x - q) ** 2).sum())
+            s = float(sq8_approx_l2(codes[i], q, lo, sc, rng))
+            dl2 = float(((q.astype(np.float64) - float(lo)) ** 2).sum())
+            delta = (0.5 * float(sc) * np.sqrt(d) + u * np.sqrt(dl2)) * (1 + 1e-6)
+            g = (d + 4) * u
+            r = np.sqrt(e2)
+            hi = (1 + g) * (r + delta) ** 2
+            lo_e = (1 - g) * (r - delta) ** 2 if r > delta else -1.0
+            assert lo_e <= s <= hi, (d, s, lo_e, hi, e2)
+            # negated inner product, in keys shifted by lo * sum(q)
+            dip = -float(np.dot(x, q.astype(np.float64)))
+            shift = float(lo) * float(q.astype(np.float64).sum())
+            s = float(sq8_approx_ip(codes[i], q, sc, rng))
+            delta = float(sc) * float(np.abs(q.astype(np.float64)).sum()) * (0.5 + 255 * (d + 2) * u) * (1 + 1e-6)
+            assert dip + shift - delta <= s <= dip + shift + delta, (d, s, dip + shift, delta)

@@ -119,10 +119,10 @@ def test_plain_es_and_brute_force_full_size(rr, c2):
 
 
 # ---------------------------------------------------------------------------
-# float workloads: 1M x 96 at full size (bf16 first pass) and the serving
-# workload's 768-wide rows.  Their graphs are seeded shifted random graphs (building
-# Vamana graphs of these sizes takes the host many minutes); parity does not
-# depend on graph quality.
+# float workloads: 1M x 96 at full size (exact, bf16 and 8-bit first passes)
+# and the serving workload's 768-wide rows.  Their graphs are one-pass Vamana
+# graphs (R=32, L=64) from the library's host builder, so searches find the
+# in-ball points and the checks below see real result lists.
 # ---------------------------------------------------------------------------
 
 def _fp64_dists(base, q, ids):
@@ -130,27 +130,28 @@ def _fp64_dists(base, q, ids):
     return (x * x).sum(1)
 
 
-def test_float32_1m_exact_and_bf16_sampled(rr):
-    """1M x 96 float32 unit vectors, 10,000 queries, radius at the 0.05th
+def test_float32_1m_exact_bf16_sq8_sampled(rr):
+    """1M x 96 float32 unit embeddings, 10,000 queries, radius at the 0.01th
     percentile (of a 50,000 x 200 sample of pairs).  Exact float path:
     sampled queries within 1e-5 of the FP64 oracle (sets equal outside the
-    +-1e-5 band).  bf16 pass with recheck: every returned point is in the
-    FP64 ball with its exact distance; the membership difference against
-    the FP64 oracle's exact traversal on the sample is reported (the bf16
-    traversal may differ, so in-ball points can be missed or added)."""
+    +-1e-5 band).  bf16 and 8-bit passes with recheck: every returned point
+    is in the FP64 ball with its exact distance; the membership difference
+    against the FP64 oracle's exact traversal on the sample is reported (an
+    approximate traversal may differ, so in-ball points can be missed or
+    added)."""
     w = synth.config_1m_f32(2)
-    adj = synth.shifted_graph(len(w.base), 64, 11)
-    r = oracle.percentile_radius(w.base[:50_000], w.queries[:200], 0.0005)
-    ix = rr.Index.from_graph(w.base, adj, 0).to_device("cuda:0")
+    flush_print("building the 1M float graph on the host")
+    ix = rr.Index.build(w.base, R=32, L=64, alpha=1.2, passes=1, threads=16, seed=2)
+    adj, entry = ix.graph()
+    ix.to_device("cuda:0")
+    r = oracle.percentile_radius(w.base[:50_000], w.queries[:200], 0.0001)
     q = torch.from_numpy(w.queries).cuda()
     flush_print(f"1M f32 radius {r}")
     ex = rr.range_search(ix, q, r, mode="adaptive", beam=32)
-    bf = rr.range_search(ix, q, r, mode="adaptive", beam=32, precision=rr.BF16_RECHECK)
     idx = np.random.default_rng(5).choice(len(w.queries), 200, replace=False)
-    o = oracle.range_search(w.base, adj, 0, w.queries[idx], r, mode=oracle.ADAPTIVE, beam=32)
+    o = oracle.range_search(w.base, adj, entry, w.queries[idx], r, mode=oracle.ADAPTIVE, beam=32)
     eo, ei, ed = ex.numpy()
-    bo, bi, bd = bf.numpy()
-    missing = extra = total = 0
+    assert len(o.ids) > 0
     for k, qi in enumerate(idx):
         oi, od = o.query(k)
         gi, gd = ei[eo[qi]:eo[qi + 1]], ed[eo[qi]:eo[qi + 1]].astype(np.float64)
@@ -159,41 +160,54 @@ def test_float32_1m_exact_and_bf16_sampled(rr):
         for x in np.setxor1d(gi, oi):
             dx = _fp64_dists(w.base, w.queries[qi], np.array([x]))[0]
             assert abs(dx - r) <= 1e-5 * r, f"q{qi}: id {x} at {dx} outside the band"
+    for prec, name in ((rr.BF16_RECHECK, "bf16"), (rr.SQ8_RERANK, "sq8")):
+        _approx_sampled(rr, w, ix, q, r, idx, o, prec, name)
+
+
+def _approx_sampled(rr, w, ix, q, r, idx, o, prec, name):
+    bf = rr.range_search(ix, q, r, mode="adaptive", beam=32, precision=prec)
+    bo, bi, bd = bf.numpy()
+    missing = extra = total = 0
+    for k, qi in enumerate(idx):
+        oi, od = o.query(k)
         hi, hd = bi[bo[qi]:bo[qi + 1]], bd[bo[qi]:bo[qi + 1]].astype(np.float64)
         dd = _fp64_dists(w.base, w.queries[qi], hi)
-        assert (dd <= r).all(), f"q{qi}: bf16 result outside the ball"
+        assert (dd <= r).all(), f"q{qi}: {name} result outside the ball"
         np.testing.assert_allclose(hd, dd, rtol=1e-6)
         missing += len(np.setdiff1d(oi, hi))
         extra += len(np.setdiff1d(hi, oi))
         total += len(oi)
-    # the bf16 pass traverses differently from the exact one, so it may miss
-    # or add in-ball points (each one it returns was checked above)
-    flush_print(f"  bf16 vs FP64 oracle on {len(idx)} queries: {total} results, "
-                f"{missing} missing, {extra} extra (in the ball)")
-    assert missing <= 0.05 * total + 5
+    # an approximate pass traverses differently from the exact one, so it may
+    # miss or add in-ball points (each one it returns was checked above)
+    flush_print(f"  {name} vs FP64 oracle on {len(idx)} queries: {total} results, "
+                f"{missing} missing, {extra} extra (in the ball), "
+                f"band {int(bf.stats['rechecked'].sum())}")
+    assert total > 0 and missing <= 0.05 * total + 5
 
 
 def test_serving_d768_bf16(rr):
-    """The serving workload's rows at their real width: 500,000 x 768
-    float32 unit vectors (the 2M-point workload's kernels and row layout on a
-    quarter of its points; generating 2M such vectors takes the host a
-    minute), bf16 first pass with exact recheck, 2,000 requests each with one of three
-    radii (0.02, 0.05, 0.1th percentiles of a 20,000 x 100 sample of pairs),
-    a step budget that suspends searches between ticks: every served result
-    equals the batched result for its query and radius, and sampled results
-    are inside the FP64 ball with their exact distances."""
-    w = synth.gaussian_mixture_unit(500_000, 2_000, 768, 5_000, 0.3 / np.sqrt(768), 17,
-                                    spread=0.3)
-    adj = synth.shifted_graph(len(w.base), 64, 13)
+    """The serving workload's rows at their real width: 200,000 x 768
+    float32 unit embeddings (the 2M-point workload's kernels and row layout
+    on a tenth of its points; its graph takes the host about a minute), bf16
+    first pass with exact recheck, 2,000 requests each with one of three
+    radii (0.005, 0.01, 0.02th percentiles of a 20,000 x 100 sample of
+    pairs), a step budget that suspends searches between ticks: every served
+    result equals the batched result for its query and radius, and sampled
+    results are inside the FP64 ball with their exact distances."""
+    w = synth.latent_mixture_f32(200_000, 2_000, 768, 5_000, 0.35, 17)
+    flush_print("building the d768 graph on the host")
+    ix = rr.Index.build(w.base, R=32, L=64, alpha=1.2, passes=1, threads=16, seed=13)
     levels = [oracle.percentile_radius(w.base[:20_000], w.queries[:100], p)
-              for p in (0.0002, 0.0005, 0.001)]
+              for p in (0.00005, 0.0001, 0.0002)]
     radii = np.asarray(levels)[np.arange(len(w.queries)) % 3]
-    ix = rr.Index.from_graph(w.base, adj, 0).to_device("cuda:0")
+    ix.to_device("cuda:0")
     flush_print(f"d768 radii {levels}")
     sp = rr.search_params(mode="adaptive", beam=16, precision=rr.BF16_RECHECK)
     batch = rr.range_search(ix, torch.from_numpy(w.queries).cuda(), torch.from_numpy(radii),
                             params=sp)
     off, ids, d = batch.numpy()
+    flush_print(f"  batched results {len(ids)}")
+    assert len(ids) > 0
     got = {}
     with rr.Server(ix, sp, slots=512, step_budget=8) as srv:
         for qi in range(len(w.queries)):

@@ -46,9 +46,9 @@ def ip_u8(rr):
 
 @pytest.fixture(scope="module")
 def ip_f32(rr):
-    """4,000 x 96 float32 mixture with row norms spread over [0.5, 2] (the
-    inner product is not a function of L2 there), 300 queries."""
-    w = synth.gaussian_mixture_unit(4000, 300, 96, 40, 0.3 / np.sqrt(96), 61, spread=0.3)
+    """4,000 x 96 float32 embeddings with row norms spread over [0.5, 2]
+    (the inner product is not a function of L2 there), 300 queries."""
+    w = synth.latent_mixture_f32(4000, 300, 96, 40, 0.35, 61)
     rng = np.random.default_rng(61)
     w.base[:] = w.base * rng.uniform(0.5, 2.0, (len(w.base), 1)).astype(np.float32)
     w.queries[:] = w.queries * rng.uniform(0.5, 2.0, (len(w.queries), 1)).astype(np.float32)
@@ -189,7 +189,7 @@ def test_ip_bf16_recheck_sound(rr, ip_f32, mode, om):
     eo, ei, ed = e.numpy()
     rec_e = oracle.range_recall(bf, oracle.Result(eo, ei, ed, None))
     flush_print(f"  recall bf16 {rec_b:.4f} exact {rec_e:.4f}, rechecked {g.stats['rechecked'].sum()}")
-    assert rec_b >= rec_e - 0.02
+    assert rec_e >= 0.25 and rec_b >= rec_e - 0.02
     assert g.stats["truncated"].sum() == 0
 
 

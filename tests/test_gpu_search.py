@@ -115,7 +115,7 @@ def test_doubling_heavy_and_float(rr):
                             max_beam=8192)
     _compare_doubling(g, o, "doubling heavy")
     assert o.stats["rounds"].max() >= 8
-    wf = synth.gaussian_mixture_unit(4000, 300, 96, 40, 0.3 / np.sqrt(96), 14, spread=0.3)
+    wf = synth.latent_mixture_f32(4000, 300, 96, 40, 0.35, 14)
     adjf, ef = oracle.build_vamana(wf.base, 32, 64, 1.2, synth.permutation(4000, 2))
     rf = oracle.percentile_radius(wf.base, wf.queries, 0.002)
     ixf = rr.Index.from_graph(wf.base, adjf, ef).to_device("cuda:0")
@@ -124,6 +124,7 @@ def test_doubling_heavy_and_float(rr):
                          max_beam=4096)
     of = oracle.range_search(wf.base, adjf, ef, wf.queries, rf, mode=oracle.DOUBLING, beam=4,
                              max_beam=4096)
+    assert len(of.ids) > 0
     compare_float(gf, of, rf, label="doubling f32")
     np.testing.assert_array_equal(gf.stats["visits"], of.stats["visits"])
     np.testing.assert_array_equal(gf.stats["rounds"], of.stats["rounds"])
@@ -202,7 +203,7 @@ def test_int8_and_ragged_dims(rr):
 def test_float32_within_tolerance(rr):
     """float32 unit vectors (d=96): distances within 1e-5 relative of the
     FP64 oracle, sets equal outside a 1e-5 band around the radius."""
-    w = synth.gaussian_mixture_unit(4000, 300, 96, 40, 0.3 / np.sqrt(96), 4, spread=0.3)
+    w = synth.latent_mixture_f32(4000, 300, 96, 40, 0.35, 4)
     adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, synth.permutation(4000, 2))
     r = oracle.percentile_radius(w.base, w.queries, 0.002)
     ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
@@ -212,6 +213,7 @@ def test_float32_within_tolerance(rr):
         g = rr.range_search(ix, q, r, mode=mode, beam=24, es_visit_limit=10, es_radius=r)
         o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=om, beam=24,
                                 es_visit_limit=10, es_radius=r)
+        assert len(o.ids) > 0
         compare_float(g, o, r, label=mode)
         np.testing.assert_array_equal(g.stats["visits"], o.stats["visits"])
 
@@ -273,7 +275,7 @@ def test_bf16_recheck_sound_exact_and_close(rr, mode, om):
     ball by the FP64 oracle's distance, reported distances are that exact
     distance, lists are ordered by that distance, and recall stays close to
     the exact float path."""
-    w = synth.gaussian_mixture_unit(8000, 400, 96, 40, 0.3 / np.sqrt(96), 14, spread=0.3)
+    w = synth.latent_mixture_f32(8000, 400, 96, 40, 0.35, 14)
     adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, synth.permutation(8000, 4))
     r = oracle.percentile_radius(w.base, w.queries, 0.002)
     ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
@@ -295,7 +297,7 @@ def test_bf16_recheck_sound_exact_and_close(rr, mode, om):
     eo, ei, ed = e.numpy()
     rec_e = oracle.range_recall(bf, oracle.Result(eo, ei, ed, None))
     flush_print(f"  recall bf16 {rec_b:.4f} exact {rec_e:.4f}, rechecked {g.stats['rechecked'].sum()}")
-    assert rec_b >= rec_e - 0.02
+    assert rec_e >= 0.25 and rec_b >= rec_e - 0.02
 
 
 @pytest.fixture(scope="module")

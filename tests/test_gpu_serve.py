@@ -122,7 +122,7 @@ def test_served_plain_and_es_staggered(rr, nav):
 def test_served_bf16_equals_batched(rr):
     """float32 data, bf16 first pass with exact recheck: the served result
     of every query is the batched result, byte for byte."""
-    w = synth.gaussian_mixture_unit(4000, 300, 96, 40, 0.3 / np.sqrt(96), 41, spread=0.3)
+    w = synth.latent_mixture_f32(4000, 300, 96, 40, 0.35, 41)
     adj, entry = oracle.build_vamana(w.base, 32, 64, 1.2, synth.permutation(4000, 41))
     r = oracle.percentile_radius(w.base, w.queries, 0.002)
     ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
@@ -132,6 +132,7 @@ def test_served_bf16_equals_batched(rr):
         sp = rr.search_params(mode="adaptive", beam=16, precision=prec)
         g = rr.range_search(ix, q, r, params=sp)
         off, ids, d = g.numpy()
+        assert len(ids) > 0
         ctx = dict(w=w, ix=ix)
         out, _ = _serve(rr, ctx, sp, 50, 2, np.full(len(w.queries), r))
         for qi in range(len(w.queries)):
