@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -516,6 +517,13 @@ extern "C" void rr_results_free(rr_results *res) {
     delete res;
 }
 
+int64_t rr::bitmap_tasks(int64_t n, int64_t nq) {
+    int64_t budget = 512ll << 20;
+    if (const char *e = std::getenv("RR_BITMAP_BYTES")) budget = std::max<int64_t>(0, std::atoll(e));
+    const int64_t cap = budget / (bitmap_words(n) * 4);
+    return std::min(nq, cap);
+}
+
 struct Carver {
     size_t off = 0;
     template <typename T> size_t take(int64_t count) {
@@ -566,7 +574,8 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
     size_t o_scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
     size_t o_tq = 0, o_tc = 0, o_te = 0, o_it = 0, o_ii = 0, o_idist = 0, o_lvl = 0, o_hash = 0,
            o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0, o_tr = 0, o_tx = 0, o_tp = 0, o_ut = 0,
-           o_ui = 0, o_ud = 0, o_lc = 0;
+           o_ui = 0, o_ud = 0, o_lc = 0, o_bm = 0;
+    const int64_t bm_words = bitmap_words(ix->n), bm_tasks = with_greedy ? bitmap_tasks(ix->n, nq) : 0;
     const int32_t max_levels = 4096;
     if (with_greedy) {
         o_tq = c.take<int32_t>(nq);
@@ -585,6 +594,7 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         o_sd = c.take<uint8_t>(item_cap * (int64_t)dsz);
         o_tp = c.take<unsigned long long>(nq);
         o_lc = c.take<unsigned long long>(1 + 3 * LEVEL_CLOCKS);
+        o_bm = c.take<uint32_t>(bm_tasks * bm_words);
         o_ut = c.take<int32_t>(item_cap);
         o_ui = c.take<int32_t>(item_cap);
         o_ud = c.take<uint8_t>(item_cap * (int64_t)dsz);
@@ -628,6 +638,9 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         sb.seg_dists = b + o_sd;
         sb.task_prev = (unsigned long long *)(b + o_tp);
         sb.level_clock = (unsigned long long *)(b + o_lc);
+        sb.bm = (uint32_t *)(b + o_bm);
+        sb.bm_words = bm_words;
+        sb.bm_tasks = bm_tasks;
         sb.u_task = (int32_t *)(b + o_ut);
         sb.u_id = (int32_t *)(b + o_ui);
         sb.u_dist = b + o_ud;
@@ -748,7 +761,9 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
                                        : std::min<int64_t>(std::max<int64_t>(nq, 1) * 4096, 1 << 21);
     if (greedy) {
         item_cap = nq * (int64_t)sp->beam + gcap;
-        hash_cap = next_pow2(std::max<int64_t>(4 * item_cap, 1024)); // >= 8 and a power of two
+        // the hash table serves the tasks the bitmaps do not cover
+        hash_cap = bitmap_tasks(ix->n, nq) >= nq ? 1024
+                                                 : next_pow2(std::max<int64_t>(4 * item_cap, 1024));
     }
     const int64_t arena_cap = nq * (int64_t)sp->beam + gcap;
     rr_results *res = nullptr;

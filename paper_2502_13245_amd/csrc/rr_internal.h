@@ -124,6 +124,12 @@ struct SearchBufs {
     int32_t max_levels = 0;
     unsigned long long *hash = nullptr; // [hash_cap] (task << 32 | id), ~0 = empty
     int64_t hash_cap = 0;
+    // per-task membership bitmaps for tasks below bm_tasks (each task's words
+    // are cleared by the beam kernel when it creates the task); tasks at or
+    // above bm_tasks use the hash table
+    uint32_t *bm = nullptr;     // [bm_tasks][bm_words]
+    int64_t bm_words = 0;       // 32-bit words per task: n bits rounded up to 128
+    int64_t bm_tasks = 0;
     int64_t *seg_off = nullptr;   // [nq + 1] per-task segment offsets
     unsigned long long *seg_cur = nullptr;   // [nq]
     int32_t *seg_ids = nullptr;   // [item_cap]
@@ -250,4 +256,10 @@ rr_status make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
                        const rr_allocator *alloc, void *stream, rr_results **out);
 int device_cus();
 int64_t next_pow2(int64_t x);
+// membership bitmaps: words per task, and how many tasks get one for a
+// batch of nq queries (the rest use the hash table).  The bitmaps of one
+// search take at most 512 MiB (RR_BITMAP_BYTES in the environment
+// overrides this; 0 sends every task to the hash table).
+inline int64_t bitmap_words(int64_t n) { return (n + 127) / 128 * 4; }
+int64_t bitmap_tasks(int64_t n, int64_t nq);
 } // namespace rr

@@ -168,6 +168,57 @@ __device__ __forceinline__ void gset_insert2(unsigned long long *tab, int64_t ca
     }
 }
 
+// The (task, id) set of the greedy phase.  Tasks below bm_tasks own a
+// bitmap of n bits: membership is one atomic OR on a word of a contiguous
+// per-task region (a task's probes stay within n/8 bytes, which caches
+// well); later tasks fall back to the hash table.
+
+// wave-wide: clear task t's bitmap (all lanes call this; a no-op for tasks
+// that use the hash table).  The fence orders the clearing stores before
+// the wave's atomic updates of the same words.
+__device__ __forceinline__ void tset_clear(const SearchBufs &sb, int64_t t) {
+    if (t >= sb.bm_tasks) return;
+    uint4 *p = reinterpret_cast<uint4 *>(sb.bm + t * sb.bm_words);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = lane_id(); i < sb.bm_words / 4; i += 64) p[i] = z;
+    __threadfence();
+}
+
+// add (t, id) to the set (seeds: known not to be present)
+__device__ __forceinline__ void tset_add(const SearchBufs &sb, int64_t hmask, int64_t t, uint32_t id,
+                                         bool &full) {
+    if (t < sb.bm_tasks)
+        atomicOr(&sb.bm[t * sb.bm_words + (id >> 5)], 1u << (id & 31));
+    else
+        gset_insert(sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
+}
+
+// insert two keys per lane; nA / nB tell whether each was new
+__device__ __forceinline__ void tset_insert2(const SearchBufs &sb, int64_t hmask, int32_t tA,
+                                             uint32_t fA, bool okA, int32_t tB, uint32_t fB, bool okB,
+                                             bool &nA, bool &nB, bool &full) {
+    const bool bA = okA && tA < sb.bm_tasks, bB = okB && tB < sb.bm_tasks;
+    uint32_t oA = 0, oB = 0;
+    if (bA) oA = atomicOr(&sb.bm[(int64_t)tA * sb.bm_words + (fA >> 5)], 1u << (fA & 31));
+    if (bB) oB = atomicOr(&sb.bm[(int64_t)tB * sb.bm_words + (fB >> 5)], 1u << (fB & 31));
+    const bool hA = okA && !bA, hB = okB && !bB;
+    bool xA = false, xB = false;
+    if (__ballot(hA || hB))
+        gset_insert2(sb.hash, hmask, ((unsigned long long)(uint32_t)tA << 32) | fA, hA,
+                     ((unsigned long long)(uint32_t)tB << 32) | fB, hB, xA, xB, full);
+    nA = bA ? !(oA & (1u << (fA & 31))) : xA;
+    nB = bB ? !(oB & (1u << (fB & 31))) : xB;
+}
+
+// Logical block index that gives each XCD a contiguous share of the grid:
+// the dispatcher deals workgroups to the 8 XCDs in turn, so consecutive
+// logical blocks land on one XCD (and its L2) when the grid is a multiple
+// of 8.
+__device__ __forceinline__ int64_t xcd_block() {
+    if (gridDim.x % 8 != 0) return blockIdx.x;
+    return (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+}
+
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m);
@@ -1067,6 +1118,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             int64_t t = 0;
             if (lane == 0) t = (int64_t)atomicAdd(&a.sb.counters[CTR_TASKS], 1ull);
             t = __shfl(t, 0);
+            if (expand) tset_clear(a.sb, t);
             bool full = false;
             int written = 0;
             O *idist = (O *)a.sb.item_dist;
@@ -1093,7 +1145,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                         a.sb.item_task[o] = (int32_t)t;
                         a.sb.item_id[o] = (int32_t)id;
                         idist[o] = dx;
-                        if (expand) gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
+                        if (expand) tset_add(a.sb, hmask, t, id, full);
                     }
                     const int mw = __popcll(__ballot(wr));
                     written += mw;
@@ -1113,7 +1165,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                     a.sb.item_task[o] = (int32_t)t;
                     a.sb.item_id[o] = (int32_t)id;
                     idist[o] = (O)bd[i];
-                    gset_insert(a.sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
+                    tset_add(a.sb, hmask, t, id, full);
                 }
                 written = (int)max((int64_t)0, min((int64_t)cN, a.sb.item_cap - off));
             }
@@ -1661,7 +1713,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         // this workgroup's block of the level (items beyond item_cap were dropped)
         const int64_t avail = max((int64_t)0, min(cnt, a.sb.item_cap - base));
         const int64_t per = (avail + gridDim.x - 1) / gridDim.x;
-        const int64_t i0 = min(avail, (int64_t)blockIdx.x * per), i1 = min(avail, i0 + per);
+        const int64_t i0 = min(avail, xcd_block() * per), i1 = min(avail, i0 + per);
 
         // the queue holds candidates of one task, `qtask`, whose query is in qr
         int qn = 0;
@@ -1799,7 +1851,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             const bool cA = okA && !wg_cache_seen(L.cache, keyA);
             const bool cB = okB && !wg_cache_seen(L.cache, keyB);
             bool nA = false, nB = false, full = false;
-            gset_insert2(a.sb.hash, hmask, keyA, cA, keyB, cB, nA, nB, full);
+            tset_insert2(a.sb, hmask, tA, (uint32_t)fA, cA, tB, (uint32_t)fB, cB, nA, nB, full);
             if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
             const unsigned long long mA = __ballot(nA), mB = __ballot(nB);
             if (mA) enqueue(tA, mA, nA, fA);

@@ -331,12 +331,12 @@ struct Caps {
     int64_t gcap, item_cap, hash_cap, arena_cap;
 };
 
-Caps server_caps(int64_t S, int64_t b, bool greedy, int64_t result_capacity) {
+Caps server_caps(int64_t n, int64_t S, int64_t b, bool greedy, int64_t result_capacity) {
     Caps c{0, 0, 0, 0};
     if (greedy) {
         c.gcap = result_capacity > 0 ? result_capacity : std::min<int64_t>(S * 4096, 1 << 21);
         c.item_cap = S * b + c.gcap;
-        c.hash_cap = next_pow2(std::max<int64_t>(4 * c.item_cap, 1024));
+        c.hash_cap = bitmap_tasks(n, S) >= S ? 1024 : next_pow2(std::max<int64_t>(4 * c.item_cap, 1024));
     }
     c.arena_cap = S * b + c.gcap;
     return c;
@@ -344,9 +344,9 @@ Caps server_caps(int64_t S, int64_t b, bool greedy, int64_t result_capacity) {
 
 // device bytes of a server with S slots (the buffers rr_server_create and
 // the per-search buffers allocate, 256-byte aligned pieces rounded up)
-int64_t server_bytes(int64_t S, int64_t b, bool greedy, int64_t result_capacity, int32_t qrow,
-                     int64_t qbytes, int dsz) {
-    const Caps c = server_caps(S, b, greedy, result_capacity);
+int64_t server_bytes(int64_t n, int64_t S, int64_t b, bool greedy, int64_t result_capacity,
+                     int32_t qrow, int64_t qbytes, int dsz) {
+    const Caps c = server_caps(n, S, b, greedy, result_capacity);
     int64_t t = 0;
     auto add = [&](int64_t bytes) { t += (int64_t)up256((size_t)std::max<int64_t>(bytes, 1)); };
     add(S * qrow);
@@ -369,6 +369,7 @@ int64_t server_bytes(int64_t S, int64_t b, bool greedy, int64_t result_capacity,
         add((S + 1) * 8 + S * 8 * 2);
         add(c.item_cap * (4 + dsz));
         add((1 + 3 * LEVEL_CLOCKS) * 8);
+        add(bitmap_tasks(n, S) * bitmap_words(n) * 4);
     }
     // server buffers: state, stored beams, qlist, staging
     add(S * (int64_t)sizeof(BeamState));
@@ -411,7 +412,7 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
         int64_t lo = 0, hi = 1 << 20;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) / 2;
-            if (server_bytes(mid, sp->beam, s->greedy, scfg->result_capacity, s->qrow, qb, ds) <=
+            if (server_bytes(ix->n, mid, sp->beam, s->greedy, scfg->result_capacity, s->qrow, qb, ds) <=
                 scfg->hbm_budget)
                 lo = mid;
             else
@@ -442,10 +443,10 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     if (e != hipSuccess) return bail(RR_EHIP, "hipStreamCreateWithFlags", e);
 
     const int64_t S = s->S, b = sp->beam;
-    const Caps caps = server_caps(S, b, s->greedy, scfg->result_capacity);
+    const Caps caps = server_caps(ix->n, S, b, s->greedy, scfg->result_capacity);
     const int64_t item_cap = caps.item_cap, hash_cap = caps.hash_cap, arena_cap = caps.arena_cap;
     s->info.slots = S;
-    s->info.device_bytes = server_bytes(S, b, s->greedy, scfg->result_capacity, s->qrow, s->qbytes, s->dsz);
+    s->info.device_bytes = server_bytes(ix->n, S, b, s->greedy, scfg->result_capacity, s->qrow, s->qbytes, s->dsz);
     st = make_results(ix, s->view, S, sp, s->greedy, arena_cap, item_cap, hash_cap, s->qrow, alloc,
                       s->stream, &s->bufs);
     if (st != RR_OK) {

@@ -141,6 +141,19 @@ def test_doubling_argument_checks(rr, small_u8):
         rr.Server(small_u8["ix"], rr.search_params(mode="doubling", beam=8))
 
 
+@pytest.mark.parametrize("budget", ["0", "6400"])
+def test_task_set_bitmap_and_hash_paths(rr, small_u8, budget, monkeypatch):
+    """The greedy phase's (task, id) set: with no bitmap budget every task
+    uses the hash table; with room for 5 bitmaps the first tasks use
+    bitmaps and the rest the hash table.  Results stay bit-exact."""
+    monkeypatch.setenv("RR_BITMAP_BYTES", budget)
+    flush_print(f"task set budget={budget}")
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=8)
+    o = _orc(small_u8, mode=oracle.ADAPTIVE, beam=8)
+    compare_exact(g, o, label=f"task set budget={budget}")
+    assert o.stats["expanded"].sum() > 5
+
+
 @pytest.mark.parametrize("waves,cache", [(1, 64), (2, 256), (8, 1024), (4, 4096)])
 def test_kernel_shapes_do_not_change_results(rr, small_u8, waves, cache):
     """A small visited cache forgets ids (more evaluations) but never changes
