@@ -193,23 +193,6 @@ __device__ __forceinline__ void tset_add(const SearchBufs &sb, int64_t hmask, in
         gset_insert(sb.hash, hmask, ((unsigned long long)t << 32) | id, full);
 }
 
-// insert two keys per lane; nA / nB tell whether each was new
-__device__ __forceinline__ void tset_insert2(const SearchBufs &sb, int64_t hmask, int32_t tA,
-                                             uint32_t fA, bool okA, int32_t tB, uint32_t fB, bool okB,
-                                             bool &nA, bool &nB, bool &full) {
-    const bool bA = okA && tA < sb.bm_tasks, bB = okB && tB < sb.bm_tasks;
-    uint32_t oA = 0, oB = 0;
-    if (bA) oA = atomicOr(&sb.bm[(int64_t)tA * sb.bm_words + (fA >> 5)], 1u << (fA & 31));
-    if (bB) oB = atomicOr(&sb.bm[(int64_t)tB * sb.bm_words + (fB >> 5)], 1u << (fB & 31));
-    const bool hA = okA && !bA, hB = okB && !bB;
-    bool xA = false, xB = false;
-    if (__ballot(hA || hB))
-        gset_insert2(sb.hash, hmask, ((unsigned long long)(uint32_t)tA << 32) | fA, hA,
-                     ((unsigned long long)(uint32_t)tB << 32) | fB, hB, xA, xB, full);
-    nA = bA ? !(oA & (1u << (fA & 31))) : xA;
-    nB = bB ? !(oB & (1u << (fB & 31))) : xB;
-}
-
 // Logical block index that gives each XCD a contiguous share of the grid:
 // the dispatcher deals workgroups to the 8 XCDs in turn, so consecutive
 // logical blocks land on one XCD (and its L2) when the grid is a multiple
@@ -1801,66 +1784,113 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             run_evals += (unsigned long long)k;
         };
 
-        // item j of this wave is i0 + wid + GREEDY_WAVES * j; items are taken
-        // in pairs.  Item records are loaded two pairs ahead, adjacency rows and
-        // expansion flags one pair ahead.
-        auto load_item = [&](int64_t it, int32_t &t, int32_t &p) {
-            t = -1;
-            p = -1;
-            if (it < i1) {
-                t = a.sb.item_task[base + it];
-                p = a.sb.item_id[base + it];
-                if (!(t >= 0 && t < ntasks && p >= 0 && (int64_t)p < ix.n)) {
-                    t = -1; // never written
-                    p = -1;
-                }
-            }
+        // Item j of this wave is i0 + wid + GREEDY_WAVES * j; items are taken
+        // in pairs, in a four-stage software pipeline: item records three pairs
+        // ahead, adjacency rows two pairs ahead, the set updates one pair
+        // ahead of the pair whose results are consumed.  Loads are issued
+        // without branches and their values are first used one stage later,
+        // so a wave keeps several round trips to memory in flight.
+        const int64_t nidx = ix.n;
+        auto load_item = [&](int64_t it, int32_t &t, int32_t &p, bool &in) {
+            in = it < i1;
+            const int64_t k = in ? base + it : 0;
+            t = a.sb.item_task[k];
+            p = a.sb.item_id[k];
         };
-        auto load_adj = [&](int32_t t, int32_t p, int32_t &f, int &e) {
-            f = -1;
-            e = 0;
-            if (t >= 0) {
-                e = a.sb.task_expand[t];
-                if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
-            }
+        // sanitises the item (items beyond item_cap are never written) and
+        // loads its expansion flag and adjacency row
+        auto load_adj = [&](bool in, int32_t t, int32_t p, int32_t &tv, int32_t &f, int &e) {
+            const bool v = in && t >= 0 && t < ntasks && p >= 0 && (int64_t)p < nidx;
+            tv = v ? t : -1;
+            const int32_t ts = v ? t : 0, ps = v ? p : 0;
+            e = a.sb.task_expand[ts];
+            f = ix.adj[(size_t)ps * (size_t)R + (size_t)max(0, min(lane, R - 1))];
         };
-        const int64_t S = GREEDY_WAVES;
-        int64_t it = i0 + wid;
-        int32_t tA, pA, tB, pB, fA, fB, tA1, pA1, tB1, pB1;
-        int eA, eB;
-        load_item(it, tA, pA);
-        load_item(it + S, tB, pB);
-        load_adj(tA, pA, fA, eA);
-        load_adj(tB, pB, fB, eB);
-        load_item(it + 2 * S, tA1, pA1);
-        load_item(it + 3 * S, tB1, pB1);
-        for (; it < i1; it += 2 * S) {
-            int32_t fA1, fB1, tA2, pA2, tB2, pB2;
-            int eA1, eB1;
-            load_adj(tA1, pA1, fA1, eA1);
-            load_adj(tB1, pB1, fB1, eB1);
-            load_item(it + 4 * S, tA2, pA2);
-            load_item(it + 5 * S, tB2, pB2);
-
-            // this pair: neighbours not yet known to the workgroup cache go to
-            // the global set; the ones inserted now are new members
-            const bool okA = tA >= 0 && eA && fA >= 0;
-            const bool okB = tB >= 0 && eB && fB >= 0;
+        // the set update of a pair: neighbours not yet known to the workgroup
+        // cache go to the global set (bitmap words are returned for the
+        // consume stage; hash-table tasks are decided here)
+        struct Pend {
+            uint32_t oA, oB;
+            bool bA, bB, xA, xB;
+        };
+        auto issue = [&](int32_t tA, int32_t fA, int eA, int32_t tB, int32_t fB, int eB, Pend &P) {
+            const bool okA = tA >= 0 && eA && lane < R && fA >= 0;
+            const bool okB = tB >= 0 && eB && lane < R && fB >= 0;
             const unsigned long long keyA = ((unsigned long long)(uint32_t)tA << 32) | (uint32_t)fA;
             const unsigned long long keyB = ((unsigned long long)(uint32_t)tB << 32) | (uint32_t)fB;
             const bool cA = okA && !wg_cache_seen(L.cache, keyA);
             const bool cB = okB && !wg_cache_seen(L.cache, keyB);
-            bool nA = false, nB = false, full = false;
-            tset_insert2(a.sb, hmask, tA, (uint32_t)fA, cA, tB, (uint32_t)fB, cB, nA, nB, full);
-            if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
+            P.bA = cA && tA < a.sb.bm_tasks;
+            P.bB = cB && tB < a.sb.bm_tasks;
+            P.oA = ~0u;
+            P.oB = ~0u;
+            if (P.bA) P.oA = atomicOr(&a.sb.bm[(int64_t)tA * a.sb.bm_words + ((uint32_t)fA >> 5)],
+                                      1u << (fA & 31));
+            if (P.bB) P.oB = atomicOr(&a.sb.bm[(int64_t)tB * a.sb.bm_words + ((uint32_t)fB >> 5)],
+                                      1u << (fB & 31));
+            const bool hA = cA && !P.bA, hB = cB && !P.bB;
+            P.xA = false;
+            P.xB = false;
+            bool full = false;
+            if (__ballot(hA || hB)) {
+                gset_insert2(a.sb.hash, hmask, keyA, hA, keyB, hB, P.xA, P.xB, full);
+                if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
+            }
+        };
+        auto consume = [&](int32_t tA, int32_t fA, int32_t tB, int32_t fB, const Pend &P) {
+            const bool nA = P.bA ? !(P.oA & (1u << (fA & 31))) : P.xA;
+            const bool nB = P.bB ? !(P.oB & (1u << (fB & 31))) : P.xB;
             const unsigned long long mA = __ballot(nA), mB = __ballot(nB);
             if (mA) enqueue(tA, mA, nA, fA);
             if (mB) enqueue(tB, mB, nB, fB);
             if (qn >= 64) flush();
+        };
+        const int64_t S = GREEDY_WAVES;
+        int64_t it = i0 + wid;
+        // stage 3 (consume), 2 (issue), 1 (adjacency), 0 (items)
+        int32_t tA3, fA3, tB3, fB3;
+        int32_t tA2, fA2, tB2, fB2;
+        int eA2, eB2;
+        int32_t tA1, pA1, tB1, pB1, tA0, pA0, tB0, pB0;
+        bool iA1, iB1, iA0, iB0;
+        Pend P3;
+        {
+            int32_t t, p;
+            bool in;
+            int e;
+            load_item(it, t, p, in);
+            load_adj(in, t, p, tA3, fA3, e);
+            int32_t tb, pb;
+            bool inb;
+            int eb;
+            load_item(it + S, tb, pb, inb);
+            load_adj(inb, tb, pb, tB3, fB3, eb);
+            issue(tA3, fA3, e, tB3, fB3, eb, P3);
+        }
+        {
+            int32_t t, p, tb, pb;
+            bool in, inb;
+            load_item(it + 2 * S, t, p, in);
+            load_item(it + 3 * S, tb, pb, inb);
+            load_adj(in, t, p, tA2, fA2, eA2);
+            load_adj(inb, tb, pb, tB2, fB2, eB2);
+        }
+        load_item(it + 4 * S, tA1, pA1, iA1);
+        load_item(it + 5 * S, tB1, pB1, iB1);
+        for (; it < i1; it += 2 * S) {
+            load_item(it + 6 * S, tA0, pA0, iA0);
+            load_item(it + 7 * S, tB0, pB0, iB0);
+            int32_t tAn, fAn, tBn, fBn;
+            int eAn, eBn;
+            load_adj(iA1, tA1, pA1, tAn, fAn, eAn);
+            load_adj(iB1, tB1, pB1, tBn, fBn, eBn);
+            Pend P2;
+            issue(tA2, fA2, eA2, tB2, fB2, eB2, P2);
+            consume(tA3, fA3, tB3, fB3, P3);
 
-            tA = tA1; pA = pA1; fA = fA1; eA = eA1;
-            tB = tB1; pB = pB1; fB = fB1; eB = eB1;
-            tA1 = tA2; pA1 = pA2; tB1 = tB2; pB1 = pB2;
+            tA3 = tA2; fA3 = fA2; tB3 = tB2; fB3 = fB2; P3 = P2;
+            tA2 = tAn; fA2 = fAn; eA2 = eAn; tB2 = tBn; fB2 = fBn; eB2 = eBn;
+            tA1 = tA0; pA1 = pA0; iA1 = iA0; tB1 = tB0; pB1 = pB0; iB1 = iB0;
         }
         flush();
         close_task();
