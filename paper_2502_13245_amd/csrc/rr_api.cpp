@@ -518,7 +518,7 @@ extern "C" void rr_results_free(rr_results *res) {
 }
 
 int64_t rr::bitmap_tasks(int64_t n, int64_t nq) {
-    int64_t budget = 512ll << 20;
+    int64_t budget = 2048ll << 20;
     if (const char *e = std::getenv("RR_BITMAP_BYTES")) budget = std::max<int64_t>(0, std::atoll(e));
     const int64_t cap = budget / (bitmap_words(n) * 4);
     return std::min(nq, cap);

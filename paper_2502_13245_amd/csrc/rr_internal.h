@@ -258,7 +258,7 @@ int device_cus();
 int64_t next_pow2(int64_t x);
 // membership bitmaps: words per task, and how many tasks get one for a
 // batch of nq queries (the rest use the hash table).  The bitmaps of one
-// search take at most 512 MiB (RR_BITMAP_BYTES in the environment
+// search take at most 2 GiB (RR_BITMAP_BYTES in the environment
 // overrides this; 0 sends every task to the hash table).
 inline int64_t bitmap_words(int64_t n) { return (n + 127) / 128 * 4; }
 int64_t bitmap_tasks(int64_t n, int64_t nq);

@@ -2120,28 +2120,37 @@ __device__ int lds_sort(D *ad, uint32_t *ai, D *bd, uint32_t *bi, int p) {
     D *sd = ad, *dd = bd;
     uint32_t *si = ai, *di = bi;
     int in_b = 0;
+    // merge passes: runs A = [a0, a0 + w) and B = [a0 + w, a0 + 2w) merge
+    // into the same range.  Each thread writes MERGE_E consecutive outputs:
+    // it finds how many of them come from A by a binary search on the merge
+    // path, then merges sequentially.  p and 2w are multiples of 64, so a
+    // thread's outputs never straddle two pairs.
+    constexpr int MERGE_E = 8;
     for (int w = 64; w < p; w <<= 1) {
-        for (int i = tid; i < p; i += nth) {
-            const int run = i / w;
-            const int a0 = (run & ~1) * w, b0 = a0 + w;
-            const D x = sd[i];
-            const uint32_t xi = si[i];
-            int pos;
-            if (b0 >= p) {
-                pos = i; // no partner run
-            } else {
-                const bool left = (run & 1) == 0;
-                int lo = left ? b0 : a0, hi = left ? min(p, b0 + w) : b0;
-                const int start = lo;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (key_less(sd[mid], si[mid], x, xi)) lo = mid + 1;
-                    else hi = mid;
-                }
-                pos = left ? a0 + (i - a0) + (lo - start) : a0 + (i - b0) + (lo - start);
+        for (int k0 = tid * MERGE_E; k0 < p; k0 += nth * MERGE_E) {
+            const int a0 = k0 / (2 * w) * (2 * w), b0 = a0 + w;
+            const int la = min(w, p - a0), lb = b0 < p ? min(w, p - b0) : 0;
+            const int k = k0 - a0;
+            int lo = max(0, k - lb), hi = min(k, la);
+            while (lo < hi) {
+                const int x = (lo + hi) >> 1;
+                if (key_less(sd[a0 + x], si[a0 + x], sd[b0 + k - x - 1], si[b0 + k - x - 1])) lo = x + 1;
+                else hi = x;
             }
-            dd[pos] = x;
-            di[pos] = xi;
+            int ia = a0 + lo, ib = b0 + (k - lo);
+            const int ea = a0 + la, eb = b0 + lb;
+#pragma unroll
+            for (int j = 0; j < MERGE_E; ++j) {
+                // clamped reads stay inside the two runs (la >= 1, b0 >= 64)
+                const int ca = min(ia, ea - 1), cb = min(ib, eb - 1);
+                const bool takea =
+                    ib >= eb || (ia < ea && key_less(sd[ca], si[ca], sd[cb], si[cb]));
+                const int src = takea ? ia : ib;
+                dd[k0 + j] = sd[src];
+                di[k0 + j] = si[src];
+                ia += takea ? 1 : 0;
+                ib += takea ? 0 : 1;
+            }
         }
         __syncthreads();
         D *td = sd;
