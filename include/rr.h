@@ -269,7 +269,8 @@ typedef struct {
 /* Pick the search parameters of a workload.  `truth` is an exact result of
  * the same queries and radii (rr_brute_force).  Keeps mode, early-stop and
  * precision fields of *inout and writes beam, waves_per_group and
- * cache_slots: first the fastest beam (from a fixed ladder) whose range
+ * cache_slots: first the fastest beam (ladder 2..256 for adaptive and
+ * doubling search, 16..4096 otherwise) whose range
  * recall (sum |K & K'| / sum |K|, Definition 2.2) is >= target (a wider
  * beam replaces a narrower one only if it is at least 3% faster), then the
  * fastest kernel shape for that beam (shapes never change results).  Each
@@ -293,7 +294,7 @@ typedef struct {
 
 /* Choose Algorithm 5's parameters for a search (mode, beam and the other
  * fields of *inout are kept; es_enable, es_visit_limit, es_radius are
- * written).  For vl in {5, 10, 20, 40} the metrics of rr_es_profile at step
+ * written).  For vl in {2, 3, 5, 10, 20, 40} the metrics of rr_es_profile at step
  * vl give, over the queries that have results (in `truth`) but no point
  * within r yet, the distances d(p*) an early stop would cut; esr candidates
  * are their maximum (cuts none of them at vl) and their 99th and 95th

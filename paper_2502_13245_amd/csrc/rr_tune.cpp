@@ -115,7 +115,7 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
     Csr gt;
     rr_status st = fetch_ids(truth, nq, stream, &gt);
     if (st != RR_OK) return st;
-    static const int kAdaptive[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    static const int kAdaptive[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
     static const int kBeam[] = {16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
     const bool adaptive = inout->mode == RR_ADAPTIVE || inout->mode == RR_DOUBLING;
     std::vector<int> ladder = adaptive ? std::vector<int>(std::begin(kAdaptive), std::end(kAdaptive))
@@ -247,7 +247,7 @@ extern "C" rr_status rr_tune_early_stop(const rr_index *ix, const void *queries_
     }
     std::vector<double> m((size_t)nq * 4);
     std::vector<int8_t> f((size_t)nq * 2);
-    for (int vl : {5, 10, 20, 40}) {
+    for (int vl : {2, 3, 5, 10, 20, 40}) {
         st = rr_es_profile(ix, queries_dev, nq, radius, radius_dev, inout->beam, vl, m.data(), f.data(),
                            alloc, stream);
         if (st != RR_OK) return st;
