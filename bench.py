@@ -202,6 +202,28 @@ def main():
     radius = float(nn_sorted[math.ceil(0.25 * nq) - 1])
     scan_tops = 2.0 * nq * n * d / (nn_ms * 1e-3) / 1e12
     log(f"radius {radius:.0f} (nn scan {nn_ms:.2f} ms, {scan_tops:.0f} TOP/s int8 MFMA)")
+    # context for the search kernels' rooflines: the rate of a plain random
+    # row gather (PyTorch index_select of d-byte rows at seeded random ids;
+    # reads random, writes sequential)
+    base_t = torch.from_numpy(w.base).cuda().view(torch.int64)  # rows of d/8 8-byte words
+    g_rows = 4_000_000
+    gidx = torch.from_numpy(np.random.default_rng(7).integers(0, n, size=g_rows)).cuda()
+    torch.index_select(base_t, 0, gidx)
+    g_ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.index_select(base_t, 0, gidx)
+        e1.record()
+        torch.cuda.synchronize()
+        g_ts.append(e0.elapsed_time(e1))
+    g_ms = float(np.median(g_ts))
+    gather = {"op": "torch.index_select of random rows", "rows": g_rows, "row_bytes": d,
+              "ms": round(g_ms, 4), "rows_per_s": round(g_rows / (g_ms * 1e-3), 1),
+              "random_read_GBs": round(g_rows * d / (g_ms * 1e-3) / 1e9, 1)}
+    log(f"random row gather (context): {gather['rows_per_s'] / 1e9:.1f}G rows/s, "
+        f"{gather['random_read_GBs']:.0f} GB/s of random reads")
+    del base_t, gidx
     t0 = time.time()
     truth_h = rr.brute_force_async(ix, q, radius)
     truth = truth_h.fetch(False)
@@ -391,6 +413,7 @@ def main():
                     "tops": round(scan_tops, 1), "peak_tops": INT8_PEAK_TOPS,
                     "frac": round(scan_tops / INT8_PEAK_TOPS, 4)},
         "graph_build_s": round(build_s, 1) if build_s else None,
+        "random_row_gather": gather,
         "greedy": {"phase_ms": round(float(np.mean(greedy_ms)), 4),
                    "kernel_ms": round(float(np.mean(gk_ms)), 4), "levels": st["greedy_levels"],
                    "items": st["greedy_items"], "tasks": st["expanded"],

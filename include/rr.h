@@ -220,9 +220,15 @@ void rr_index_free(rr_index *idx);
  * is enqueued on `stream`; *out owns the per-query results until
  * rr_results_free.  Queries must stay valid until the stream reaches the
  * end of the call's work.  nq = 0 is valid (no results).
+ * Device memory held by *out (from `alloc`): the padded queries, the result
+ * arena, and for modes with a greedy or sort stage the greedy items plus
+ * n/8 bytes of membership bitmap per query that may expand.  The bitmaps are
+ * capped at 2 GiB per call: further queries use a hash table instead.  The
+ * environment variable RR_BITMAP_BYTES sets another cap, and 0 disables the
+ * bitmaps.
  * Errors: RR_EINVAL (beam < 1, vl < 1 with early stopping, NaN radius, mode
- * or precision unknown, BF16 precision on integer data), RR_ESTATE (index
- * not on the device), RR_ENOMEM, RR_EHIP. */
+ * or precision unknown, BF16 or SQ8 precision on integer data), RR_ESTATE
+ * (index not on the device), RR_ENOMEM, RR_EHIP. */
 rr_status rr_range_search(const rr_index *idx, const void *queries_dev, int64_t nq,
                           double radius, const double *radius_dev,
                           const rr_search_params *sp, const rr_allocator *alloc, void *stream,
