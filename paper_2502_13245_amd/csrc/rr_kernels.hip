@@ -1590,6 +1590,16 @@ __device__ void greedy_segments(unsigned long long *part, const SearchBufs &sb, 
     }
 }
 
+// one workgroup, for a level that is not regrouped: task_prev = task_cnt, so
+// the next regrouping sees only the growth of its own level (same task
+// partition over the threads as greedy_segments, so no barrier is needed
+// between the two)
+__device__ void greedy_mark_prev(const SearchBufs &sb, int64_t ntasks) {
+    const int64_t per = (ntasks + blockDim.x - 1) / blockDim.x;
+    const int64_t lo = min(ntasks, (int64_t)threadIdx.x * per), hi = min(ntasks, lo + per);
+    for (int64_t t = lo; t < hi; ++t) sb.task_prev[t] = sb.task_cnt[t];
+}
+
 // regroup the unsorted level [lo, hi) by task into the item arrays; one
 // cursor atomic per run of equal tasks
 template <typename O>
@@ -1685,6 +1695,8 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             a.sb.level_clock[i] = i == 0 ? wall_clock64() : 0ull;
     int64_t base = 0;
     int lvl = 0;
+    bool grouped = true;
+    const int64_t regroup_min = 512 * (int64_t)gridDim.x;
     for (; lvl < a.sb.max_levels - 1; ++lvl) {
         const int64_t cnt = (int64_t)__hip_atomic_load(&a.sb.level_cnt[lvl], __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1693,6 +1705,10 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         for (int i = threadIdx.x; i < GREEDY_CACHE; i += blockDim.x) L.cache[i] = ~0ull;
         if (lane == 0) L.st_n[wid] = 0;
         __syncthreads();
+        // where this level's items are: the item arrays (level 0, or regrouped)
+        // or the unsorted level as emitted
+        const int32_t *src_task = grouped ? a.sb.item_task : a.sb.u_task;
+        const int32_t *src_id = grouped ? a.sb.item_id : a.sb.u_id;
         // this workgroup's block of the level (items beyond item_cap were dropped)
         const int64_t avail = max((int64_t)0, min(cnt, a.sb.item_cap - base));
         const int64_t per = (avail + gridDim.x - 1) / gridDim.x;
@@ -1794,8 +1810,8 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         auto load_item = [&](int64_t it, int32_t &t, int32_t &p, bool &in) {
             in = it < i1;
             const int64_t k = in ? base + it : 0;
-            t = a.sb.item_task[k];
-            p = a.sb.item_id[k];
+            t = src_task[k];
+            p = src_id[k];
         };
         // sanitises the item (items beyond item_cap are never written) and
         // loads its expansion flag and adjacency row
@@ -1917,14 +1933,42 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             ++lvl;
             break;
         }
-        if (blockIdx.x == 0) greedy_segments(L.part, a.sb, ntasks, next_base);
-        grid_sync();
-        stamp(lvl, 1);
-        const int64_t stored = max((int64_t)0, min(ncnt, a.sb.item_cap - next_base));
-        greedy_regroup<O>(a.sb, next_base, next_base + stored);
-        grid_sync();
-        stamp(lvl, 2);
+        // levels below 512 items per workgroup are expanded as emitted (their
+        // items are moved to the item arrays at the end): regrouping them costs
+        // two grid barriers and a pass, more than their locality gains back
+        grouped = ncnt >= regroup_min;
+        if (!grouped && blockIdx.x == 0) greedy_mark_prev(a.sb, ntasks);
+        if (grouped) {
+            if (blockIdx.x == 0) greedy_segments(L.part, a.sb, ntasks, next_base);
+            grid_sync();
+            stamp(lvl, 1);
+            const int64_t stored = max((int64_t)0, min(ncnt, a.sb.item_cap - next_base));
+            greedy_regroup<O>(a.sb, next_base, next_base + stored);
+            grid_sync();
+            stamp(lvl, 2);
+        }
         base = next_base;
+    }
+    // move the levels that were expanded as emitted into the item arrays (the
+    // kernel's end orders these writes before the finalisation)
+    {
+        int64_t b0 = 0;
+        const O *ud = (const O *)a.sb.u_dist;
+        O *idist = (O *)a.sb.item_dist;
+        // (level lvl is empty, except when the level limit stopped the loop)
+        for (int l = 0; l <= lvl && l < a.sb.max_levels; ++l) {
+            const int64_t c = (int64_t)__hip_atomic_load(&a.sb.level_cnt[l], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t lo = b0, hi = min(b0 + c, a.sb.item_cap);
+            b0 += c;
+            if (l == 0 || c >= regroup_min) continue;
+            for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+                 i += (int64_t)gridDim.x * blockDim.x) {
+                a.sb.item_task[i] = a.sb.u_task[i];
+                a.sb.item_id[i] = a.sb.u_id[i];
+                idist[i] = ud[i];
+            }
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.sb.counters[CTR_LEVELS] = (unsigned long long)lvl;
