@@ -2223,12 +2223,20 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
         const int32_t q = sb.task_q[t];
-        if (threadIdx.x == 0) s_off = (int64_t)atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)n);
-        __syncthreads();
-        const int64_t off = s_off;
-        const bool ok = off + n <= sb.arena_cap;
+        // thread 0 issues the arena reservation and the loads of the task's
+        // counters up front; they complete while the segment is loaded
+        unsigned long long aoff = 0, evals = 0, rechk = 0;
+        int32_t prev_rechk = 0;
+        bool exp = true;
+        if (threadIdx.x == 0) {
+            aoff = atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)n);
+            exp = sb.task_expand == nullptr || sb.task_expand[t] != 0;
+            evals = sb.task_evals[t];
+            if (sb.task_rechk) rechk = sb.task_rechk[t];
+            prev_rechk = sb.stats[q].rechecked;
+        }
+        const int p = max(64, (int)((n + 63) & ~63ll));
         if (n <= CAP) {
-            const int p = max(64, (int)((n + 63) & ~63ll));
             for (int i = threadIdx.x; i < p; i += blockDim.x) {
                 if (i < n) {
                     ad[i] = segd[s0 + i];
@@ -2238,7 +2246,12 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
                     ai[i] = RR_EMPTY32 - (uint32_t)(i - n);
                 }
             }
-            __syncthreads();
+        }
+        if (threadIdx.x == 0) s_off = (int64_t)aoff;
+        __syncthreads();
+        const int64_t off = s_off;
+        const bool ok = off + n <= sb.arena_cap;
+        if (n <= CAP) {
             const int in_b = lds_sort<D>(ad, ai, bd, bi, p);
             const D *rd = in_b ? bd : ad;
             const uint32_t *ri = in_b ? bi : ai;
@@ -2260,10 +2273,9 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
             sb.res_cnt[q] = ok ? (int32_t)n : 0;
             rr_query_stats *st = &sb.stats[q];
             st->count = ok ? (int32_t)n : 0;
-            const bool exp = sb.task_expand == nullptr || sb.task_expand[t] != 0;
             st->greedy_visits = exp ? (int32_t)n : 0;
-            st->greedy_evals = (int32_t)sb.task_evals[t];
-            if (sb.task_rechk) st->rechecked += (int32_t)sb.task_rechk[t];
+            st->greedy_evals = (int32_t)evals;
+            st->rechecked = prev_rechk + (int32_t)rechk;
             if (!ok) {
                 st->truncated = 1;
                 atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);
