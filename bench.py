@@ -254,11 +254,11 @@ def main():
     sweeps = {
         "plain": (dict(), [32, 64, 128, 256, 512, 1024, 2048, 4096]),
         "es": (dict(es_visit_limit=10, es_radius=radius), [32, 64, 128, 256, 512, 1024, 2048, 4096]),
-        "adaptive": (es_kw, [8, 16, 24, 32, 48, 64, 96, 128]),
-        "adaptive_noes": (dict(es_enable=False), [8, 16, 24, 32, 48, 64, 96, 128]),
-        "doubling": (dict(max_beam=8192, result_capacity=4_000_000), [4, 8, 16, 32, 64]),
+        "adaptive": (es_kw, [2, 4, 8, 16, 24, 32, 48, 64, 96, 128]),
+        "adaptive_noes": (dict(es_enable=False), [2, 4, 8, 16, 24, 32, 48, 64, 96, 128]),
+        "doubling": (dict(max_beam=8192, result_capacity=4_000_000), [2, 4, 8, 16, 32, 64]),
         "doubling_es": (dict(max_beam=8192, result_capacity=4_000_000, es_enable=True,
-                             es_visit_limit=10, es_radius=radius), [4, 8, 16, 32, 64]),
+                             es_visit_limit=10, es_radius=radius), [2, 4, 8, 16, 32, 64]),
     }
     best = {}
     curves = {}

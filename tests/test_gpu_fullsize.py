@@ -228,3 +228,54 @@ def test_serving_d768_bf16(rr):
         dd = _fp64_dists(w.base, w.queries[qi], gi)
         assert (dd <= radii[qi]).all()
         np.testing.assert_allclose(gd.astype(np.float64), dd, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# int8 at the batching workload's full size: 10M x 100 base, 100,000 queries
+# in uneven batches.  The graph is a seeded shifted random graph (a Vamana
+# build of 10M points takes the host many minutes); parity does not depend
+# on graph quality.  At this size adjacency offsets pass 2^31 bytes, each
+# task's membership bitmap is 1.25 MB, and the heaviest query returns over
+# 100,000 points (the sort's global merge path).
+# ---------------------------------------------------------------------------
+
+def test_int8_10m_uneven_batches(rr):
+    """Every query's result is the same in one 100,000-query launch and in
+    batches of 1k, 4k, 16k, 64k and 15k; sampled queries equal the oracle
+    (ids, distances, visit counts)."""
+    w = synth.config_i8(3)
+    adj = synth.shifted_graph(len(w.base), 64, 17)
+    # radius: 75% of 200 sampled queries empty (the oracle's nearest neighbours)
+    r = oracle.empty_fraction_radius(w.base, w.queries[:200], 0.25)
+    ix = rr.Index.from_graph(w.base, adj, 0).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    flush_print(f"10M int8 radius {r}")
+    kw = dict(mode="adaptive", beam=16, es_enable=True, es_visit_limit=10, es_radius=r,
+              result_capacity=20_000_000)
+    one = rr.range_search(ix, q, r, **kw)
+    off, ids, d = one.numpy()
+    counts = np.diff(off)
+    flush_print(f"  one launch: {int(off[-1])} results, {int((counts > 0).sum())} non-empty, "
+                f"max {counts.max()}, expanded {int(one.stats['expanded'].sum())}")
+    assert counts.max() > 0
+    start = 0
+    for size in (1_000, 4_000, 16_000, 64_000, 15_000):
+        part = rr.range_search(ix, q[start:start + size], r, **kw)
+        po, pi, pd = part.numpy()
+        for k in range(size):
+            qi = start + k
+            np.testing.assert_array_equal(pi[po[k]:po[k + 1]], ids[off[qi]:off[qi + 1]])
+            np.testing.assert_array_equal(pd[po[k]:po[k + 1]], d[off[qi]:off[qi + 1]])
+        np.testing.assert_array_equal(part.stats["visits"], one.stats["visits"][start:start + size])
+        start += size
+    assert start == len(w.queries)
+    rng = np.random.default_rng(9)
+    idx = np.unique(np.concatenate([rng.choice(len(counts), 100, replace=False),
+                                    np.argsort(-counts, kind="stable")[:20]]))
+    o = oracle.range_search(w.base, adj, 0, w.queries[idx], r, mode=oracle.ADAPTIVE, beam=16,
+                            es_enable=True, es_visit_limit=10, es_radius=r)
+    for k, qi in enumerate(idx):
+        oi, od = o.query(k)
+        np.testing.assert_array_equal(ids[off[qi]:off[qi + 1]], oi, err_msg=f"q{qi} ids")
+        np.testing.assert_array_equal(d[off[qi]:off[qi + 1]].astype(np.int64), od.astype(np.int64))
+        assert one.stats["visits"][qi] == o.stats["visits"][k]
