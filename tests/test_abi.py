@@ -130,3 +130,32 @@ def test_shifted_graph_is_a_valid_index_graph():
     assert not (s[:, 1:] == s[:, :-1]).any()
     rr.Index.from_graph(np.zeros((n, 2), np.uint8), adj, 0)
     np.testing.assert_array_equal(adj, synth.shifted_graph(n, R, 7))
+
+
+def test_metric_is_saved_and_old_files_load_as_l2(tmp_path):
+    """The index file records the metric (version 2 header); a version 1
+    file, which has no metric field, loads as squared L2."""
+    w = synth.gaussian_mixture_int(300, 5, 16, 4, 12.0, 2)
+    adj = synth.random_graph(300, 8, 2)
+    ix = rr.Index.from_graph(w.base, adj, 5, metric="ip")
+    assert ix.metric == "ip"
+    p2 = str(tmp_path / "v2.rri")
+    ix.save(p2)
+    back = rr.Index.load(p2)
+    assert back.metric == "ip" and back.info() == ix.info()
+    np.testing.assert_array_equal(back.graph()[0], adj)
+    # the same index in the version 1 layout: magic, 5 int64, rows, graph
+    p1 = str(tmp_path / "v1.rri")
+    with open(p1, "wb") as f:
+        f.write(b"RRIDX001")
+        f.write(np.array([300, 16, rr.U8, 8, 5], np.int64).tobytes())
+        f.write(np.ascontiguousarray(w.base).tobytes())
+        f.write(np.ascontiguousarray(adj, np.int32).tobytes())
+    old = rr.Index.load(p1)
+    assert old.metric == "l2" and old.info()["entry"] == 5
+    np.testing.assert_array_equal(old.graph()[0], adj)
+    with pytest.raises(ValueError):
+        ix.set_metric("cosine")
+    with pytest.raises(rr.RRError):
+        lib = rr.lib()
+        rr._check(lib.rr_index_set_metric(ix._h, 7))
