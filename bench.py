@@ -136,6 +136,9 @@ def main():
                                                  "setting as JSON")
     ap.add_argument("--only", action="store_true",
                     help="profiling mode: skip sweeps, run the setting from --choice --steps times")
+    ap.add_argument("--scan-only", action="store_true",
+                    help="profiling mode: run the MFMA nearest-distance scan and the brute-force "
+                         "range scan --steps times on the workload and exit (no graph is built)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run a device-to-device copy of this size (counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
@@ -157,6 +160,26 @@ def main():
     t0 = time.time()
     w = synth.config_1m_u8(1, n=args.n, nq=args.nq)
     log(f"workload {w.name}: generated in {time.time() - t0:.1f}s")
+    if args.scan_only:
+        # the scans read only the vectors: any valid graph serves
+        ix = rr.Index.from_graph(w.base, synth.shifted_graph(len(w.base), 8, 1), 0).to_device("cuda:0")
+        q = torch.from_numpy(w.queries).cuda()
+        nn = rr.nn_dist(ix, q)
+        radius = float(np.sort(nn.cpu().numpy())[math.ceil(0.25 * len(w.queries)) - 1])
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            rr.nn_dist(ix, q)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        tops = 2.0 * len(w.queries) * len(w.base) * 128 / (ms * 1e-3) / 1e12
+        for _ in range(args.steps):
+            rr.brute_force(ix, q, radius)
+        torch.cuda.synchronize()
+        log(f"scan-only run done: {args.steps} x nn scan ({ms:.3f} ms, {tops:.0f} TOP/s) "
+            f"and {args.steps} x range scan at radius {radius:.0f}")
+        return
     t0 = time.time()
     if args.graph and os.path.exists(args.graph):
         ix = rr.Index.load(args.graph)

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 
 #include "rr_internal.h"
@@ -72,8 +73,11 @@ __device__ __forceinline__ double dbl_unorder(unsigned long long k) {
     return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
 }
 
-template <int DTYPE, int KS, bool IP>
-__global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
+// MODE (SCAN_NN / SCAN_RANGE) is a template parameter so that each
+// instantiation keeps only its own per-query state in registers
+template <int DTYPE, int KS, bool IP, int MODE>
+__global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
+    constexpr int mode = MODE;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int row = lane & 15, grp = lane >> 4;
@@ -121,21 +125,26 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
                       (DTYPE == RR_U8 ? (uint32_t)(16384 * KS * 64) - 128u * (uint32_t)s : 0u));
         qn_own[t] = s;
     }
-    int qn[QT][4];
-    int64_t rthr[QT][4];
+    // Every distance (or key) is qn + part with the query's constant qn and
+    // part = |x'|^2 - 2 q'.x' (inner product: the base row's part - q.x),
+    // exact in int32.  The loop works on part alone: the nearest-neighbour
+    // minimum adds qn at the end, and the range test compares part with
+    // r_int - qn (saturated to int32; rows past nq never hit).  This keeps
+    // one register per (tile, row) instead of three.
+    int lim[QT][4]; // SCAN_NN: the smallest part so far; SCAN_RANGE: r_int - qn
 #pragma unroll
     for (int t = 0; t < QT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            qn[t][v] = __shfl(qn_own[t], 4 * grp + v);
-            const int64_t q = q0 + t * 16 + 4 * grp + v;
-            rthr[t][v] = (mode == SCAN_RANGE && q < a.nq) ? a.qth[q].r_int : -1;
+            if (mode == SCAN_NN) {
+                lim[t][v] = INT_MAX;
+            } else {
+                const int64_t q = q0 + t * 16 + 4 * grp + v;
+                const int64_t qn = __shfl(qn_own[t], 4 * grp + v);
+                const int64_t r = q < a.nq ? a.qth[q].r_int : -1;
+                lim[t][v] = (int)max((int64_t)INT_MIN, min((int64_t)INT_MAX, r - qn));
+            }
         }
-    uint32_t best[QT][4];
-#pragma unroll
-    for (int t = 0; t < QT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) best[t][v] = 0xffffffffu;
 
     for (int64_t p0 = p_begin; p0 < p_end; p0 += 16) {
         const int64_t p = min(p0 + row, p_end - 1);
@@ -174,21 +183,18 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
                 if (ks < ks_n) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t][ks], B[ks], acc, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                // L2: |q'|^2 + |x'|^2 - 2 q'.x'; inner product: the key
-                const int dd = IP ? (int)((uint32_t)qn[t][v] + (uint32_t)xs - (uint32_t)acc[v])
-                                  : qn[t][v] + xs - 2 * acc[v];
-                const uint32_t du = (uint32_t)dd;
+                const int part = IP ? xs - acc[v] : xs - 2 * acc[v];
                 if (mode == SCAN_NN) {
-                    if (pvalid && du < best[t][v]) best[t][v] = du;
+                    if (pvalid && part < lim[t][v]) lim[t][v] = part;
                 } else {
-                    const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq &&
-                                     (int64_t)du <= rthr[t][v];
+                    const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq && part <= lim[t][v];
                     const unsigned long long hm = __ballot(hit);
                     if (hm) {
                         unsigned long long base = 0;
                         if (lane == (__ffsll((long long)hm) - 1))
                             base = atomicAdd(a.item_cursor, (unsigned long long)__popcll(hm));
                         base = __shfl(base, __ffsll((long long)hm) - 1);
+                        const uint32_t qn = (uint32_t)__shfl(qn_own[t], 4 * grp + v);
                         if (hit) {
                             const int64_t pos = (int64_t)base + __builtin_amdgcn_mbcnt_hi(
                                 (unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
                             if (pos < a.item_cap) {
                                 a.item_task[pos] = (int32_t)q;
                                 a.item_id[pos] = (int32_t)(p0 + row);
-                                ((uint32_t *)a.item_dist)[pos] = du;
+                                ((uint32_t *)a.item_dist)[pos] = qn + (uint32_t)part;
                                 atomicAdd(&a.task_cnt[q], 1ull);
                             } else {
                                 atomicOr(a.overflow, 64ull);
@@ -212,11 +218,14 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
         for (int t = 0; t < QT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                uint32_t b = best[t][v];
+                int b = lim[t][v];
 #pragma unroll
-                for (int m = 1; m < 16; m <<= 1) b = min(b, (uint32_t)__shfl_xor((int)b, m));
+                for (int m = 1; m < 16; m <<= 1) b = min(b, __shfl_xor(b, m));
+                const uint32_t qn = (uint32_t)__shfl(qn_own[t], 4 * grp + v);
                 const int64_t q = q0 + t * 16 + 4 * grp + v;
-                if (row == 0 && q < a.nq) atomicMin(&a.nn_bits[q], (unsigned long long)b);
+                // every chunk has at least one valid row, so b was lowered
+                if (row == 0 && q < a.nq && b != INT_MAX)
+                    atomicMin(&a.nn_bits[q], (unsigned long long)(qn + (uint32_t)b));
             }
     }
 }
@@ -225,8 +234,9 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a, int mode) {
 // B: lane l holds x[j=l%16][k=4s+l/16].  The FP64 output tile differs from
 // the integer one: lane l, register v holds row (l/16) + 4v, column l%16.
 #define F64_ROW(grp, v) ((grp) + 4 * (v))
-template <bool IP>
-__global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a, int mode) {
+template <bool IP, int MODE>
+__global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a) {
+    constexpr int mode = MODE;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int row = lane & 15, grp = lane >> 4;
@@ -342,6 +352,14 @@ __global__ void k_identity_tasks(int32_t *task_q, int64_t nq, unsigned long long
     if (blockIdx.x == 0 && threadIdx.x == 0) counters[CTR_TASKS] = (unsigned long long)nq;
 }
 
+template <int K, int MODE>
+static void launch_scan_int(const ScanArgs &a, bool ip, dim3 grid, dim3 block, hipStream_t s) {
+    if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true, MODE>), grid, block, 0, s, a);
+    else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false, MODE>), grid, block, 0, s, a);
+    else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true, MODE>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false, MODE>), grid, block, 0, s, a);
+}
+
 static hipError_t launch_scan(const ScanArgs &a0, int mode, hipStream_t s) {
     ScanArgs a = a0;
     const int qper = a.ix.dtype == RR_F32 ? 4 * 2 * 16 : 4 * QT * 16;
@@ -359,17 +377,17 @@ static hipError_t launch_scan(const ScanArgs &a0, int mode, hipStream_t s) {
     dim3 grid((unsigned)qblocks, (unsigned)pblocks), block(256);
     const bool ip = a.ix.metric == RR_IP;
     if (a.ix.dtype == RR_F32) {
-        if (ip) hipLaunchKernelGGL(k_scan_f32<true>, grid, block, 0, s, a, mode);
-        else hipLaunchKernelGGL(k_scan_f32<false>, grid, block, 0, s, a, mode);
+        if (ip && mode == SCAN_NN) hipLaunchKernelGGL((k_scan_f32<true, SCAN_NN>), grid, block, 0, s, a);
+        else if (ip) hipLaunchKernelGGL((k_scan_f32<true, SCAN_RANGE>), grid, block, 0, s, a);
+        else if (mode == SCAN_NN) hipLaunchKernelGGL((k_scan_f32<false, SCAN_NN>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_scan_f32<false, SCAN_RANGE>), grid, block, 0, s, a);
         return hipGetLastError();
     }
     const int ks = a.ix.row_bytes / 64;
 #define RR_SCAN_KS(K)                                                                         \
     if (ks == K) {                                                                            \
-        if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true>), grid, block, 0, s, a, mode); \
-        else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false>), grid, block, 0, s, a, mode); \
-        else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true>), grid, block, 0, s, a, mode); \
-        else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false>), grid, block, 0, s, a, mode);  \
+        if (mode == SCAN_NN) launch_scan_int<K, SCAN_NN>(a, ip, grid, block, s);                 \
+        else launch_scan_int<K, SCAN_RANGE>(a, ip, grid, block, s);                                \
         return hipGetLastError();                                                             \
     }
     RR_SCAN_KS(1) RR_SCAN_KS(2) RR_SCAN_KS(3) RR_SCAN_KS(4) RR_SCAN_KS(6) RR_SCAN_KS(8)
