@@ -185,7 +185,9 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
             for (int v = 0; v < 4; ++v) {
                 const int part = IP ? xs - acc[v] : xs - 2 * acc[v];
                 if (mode == SCAN_NN) {
-                    if (pvalid && part < lim[t][v]) lim[t][v] = part;
+                    // rows past the chunk repeat its last row, which leaves
+                    // the minimum unchanged, so no validity test is needed
+                    lim[t][v] = min(lim[t][v], part);
                 } else {
                     const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq && part <= lim[t][v];
                     const unsigned long long hm = __ballot(hit);
