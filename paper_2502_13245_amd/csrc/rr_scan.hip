@@ -127,34 +127,49 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
     }
     // Every distance (or key) is qn + part with the query's constant qn and
     // part = |x'|^2 - 2 q'.x' (inner product: the base row's part - q.x),
-    // exact in int32.  The loop works on part alone: the nearest-neighbour
-    // minimum adds qn at the end, and the range test compares part with
-    // r_int - qn (saturated to int32; rows past nq never hit).  This keeps
-    // one register per (tile, row) instead of three.
-    int lim[QT][4]; // SCAN_NN: the smallest part so far; SCAN_RANGE: r_int - qn
+    // exact in int32.  The loop works on neg = -part = 2 q'.x' - |x'|^2 (one
+    // shift-add per element): the nearest-neighbour minimum of part is the
+    // negated maximum of neg, and the range test part <= r_int - qn is
+    // neg >= qn - r_int (saturated to int32; rows past nq never hit).  This
+    // keeps one register per (tile, row).
+    int lim[QT][4]; // SCAN_NN: the largest neg so far; SCAN_RANGE: qn - r_int
 #pragma unroll
     for (int t = 0; t < QT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             if (mode == SCAN_NN) {
-                lim[t][v] = INT_MAX;
+                lim[t][v] = INT_MIN;
             } else {
                 const int64_t q = q0 + t * 16 + 4 * grp + v;
                 const int64_t qn = __shfl(qn_own[t], 4 * grp + v);
                 const int64_t r = q < a.nq ? a.qth[q].r_int : -1;
-                lim[t][v] = (int)max((int64_t)INT_MIN, min((int64_t)INT_MAX, r - qn));
+                lim[t][v] = (int)max((int64_t)-INT_MAX, min((int64_t)INT_MAX, qn - r));
             }
         }
 
+    // the next tile's rows are loaded while the current one is multiplied
+    // (clamped to the chunk's last row, so every load is in bounds)
+    uint4 nxt[KSMAX];
+    {
+        const uint8_t *xr = a.ix.base + min(p_begin + row, p_end - 1) * a.ix.row_bytes + grp * 16;
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) nxt[ks] = *reinterpret_cast<const uint4 *>(xr + ks * 64);
+    }
     for (int64_t p0 = p_begin; p0 < p_end; p0 += 16) {
-        const int64_t p = min(p0 + row, p_end - 1);
-        const uint8_t *xr = a.ix.base + p * a.ix.row_bytes + grp * 16;
+        uint4 cur[KSMAX];
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) cur[ks] = nxt[ks];
+        {
+            const uint8_t *xr = a.ix.base + min(p0 + 16 + row, p_end - 1) * a.ix.row_bytes + grp * 16;
+#pragma unroll
+            for (int ks = 0; ks < KSMAX; ++ks) nxt[ks] = *reinterpret_cast<const uint4 *>(xr + ks * 64);
+        }
         v4i B[KSMAX];
         int xs = 0;
 #pragma unroll
         for (int ks = 0; ks < KSMAX; ++ks) {
             if (ks < ks_n) {
-                uint4 v = *reinterpret_cast<const uint4 *>(xr + ks * 64);
+                uint4 v = cur[ks];
                 if (IP && DTYPE == RR_U8) xs = row_sum_u8(v, xs);
                 if (DTYPE == RR_U8) {
                     v.x = shift_u8(v.x);
@@ -174,6 +189,10 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
         xs += __shfl_xor(xs, 16);
         xs += __shfl_xor(xs, 32);
         if (IP) xs = -128 * xs; // the base row's part of the uint8 key (0 for int8)
+        int nxs = -xs;
+        // opaque to the optimiser, so that 2 acc + nxs stays one shift-add
+        // instead of being refolded into a shift and a subtraction
+        asm volatile("" : "+v"(nxs));
         const bool pvalid = p0 + row < p_end;
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
@@ -183,13 +202,13 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
                 if (ks < ks_n) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t][ks], B[ks], acc, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int part = IP ? xs - acc[v] : xs - 2 * acc[v];
+                const int neg = IP ? acc[v] + nxs : 2 * acc[v] + nxs;
                 if (mode == SCAN_NN) {
                     // rows past the chunk repeat its last row, which leaves
-                    // the minimum unchanged, so no validity test is needed
-                    lim[t][v] = min(lim[t][v], part);
+                    // the maximum unchanged, so no validity test is needed
+                    lim[t][v] = max(lim[t][v], neg);
                 } else {
-                    const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq && part <= lim[t][v];
+                    const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq && neg >= lim[t][v];
                     const unsigned long long hm = __ballot(hit);
                     if (hm) {
                         unsigned long long base = 0;
@@ -204,7 +223,7 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
                             if (pos < a.item_cap) {
                                 a.item_task[pos] = (int32_t)q;
                                 a.item_id[pos] = (int32_t)(p0 + row);
-                                ((uint32_t *)a.item_dist)[pos] = qn + (uint32_t)part;
+                                ((uint32_t *)a.item_dist)[pos] = qn - (uint32_t)neg;
                                 atomicAdd(&a.task_cnt[q], 1ull);
                             } else {
                                 atomicOr(a.overflow, 64ull);
@@ -222,12 +241,12 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
             for (int v = 0; v < 4; ++v) {
                 int b = lim[t][v];
 #pragma unroll
-                for (int m = 1; m < 16; m <<= 1) b = min(b, __shfl_xor(b, m));
+                for (int m = 1; m < 16; m <<= 1) b = max(b, __shfl_xor(b, m));
                 const uint32_t qn = (uint32_t)__shfl(qn_own[t], 4 * grp + v);
                 const int64_t q = q0 + t * 16 + 4 * grp + v;
-                // every chunk has at least one valid row, so b was lowered
-                if (row == 0 && q < a.nq && b != INT_MAX)
-                    atomicMin(&a.nn_bits[q], (unsigned long long)(qn + (uint32_t)b));
+                // every chunk has at least one valid row, so b was raised
+                if (row == 0 && q < a.nq && b != INT_MIN)
+                    atomicMin(&a.nn_bits[q], (unsigned long long)(qn - (uint32_t)b));
             }
     }
 }
