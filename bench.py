@@ -174,11 +174,15 @@ def main():
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
         tops = 2.0 * len(w.queries) * len(w.base) * 128 / (ms * 1e-3) / 1e12
+        ev0.record()
         for _ in range(args.steps):
-            rr.brute_force(ix, q, radius)
+            res = rr.brute_force(ix, q, radius)
+        ev1.record()
         torch.cuda.synchronize()
+        ms_r = ev0.elapsed_time(ev1) / args.steps
         log(f"scan-only run done: {args.steps} x nn scan ({ms:.3f} ms, {tops:.0f} TOP/s) "
-            f"and {args.steps} x range scan at radius {radius:.0f}")
+            f"and {args.steps} x range scan at radius {radius:.0f} ({ms_r:.3f} ms per call with "
+            f"its result assembly, {int(res.offsets[-1])} results)")
         return
     t0 = time.time()
     if args.graph and os.path.exists(args.graph):

@@ -51,6 +51,35 @@ struct ScanArgs {
 };
 
 constexpr int QT = 4; // 16-query tiles per wave
+constexpr int SCAP = 256; // range hits staged in LDS per wave before a flush
+
+// Range hits of one wave, staged in its own LDS slice and appended to the
+// item arrays in one block: one cursor atomic per flush instead of one per
+// ballot (a single device-wide counter serialises under many writers).
+// Every lane of the wave calls it with the same n.
+template <typename DT>
+__device__ __forceinline__ void flush_hits(const ScanArgs &a, const uint32_t *st_task, const uint32_t *st_id,
+                                           const DT *st_dist, int n, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.item_cursor, (unsigned long long)n);
+    base = __shfl(base, 0);
+    for (int i = lane; i < n; i += 64) {
+        const int64_t pos = (int64_t)base + i;
+        const uint32_t q = st_task[i];
+        if (pos < a.item_cap) {
+            a.item_task[pos] = (int32_t)q;
+            a.item_id[pos] = (int32_t)st_id[i];
+            ((DT *)a.item_dist)[pos] = st_dist[i];
+            atomicAdd(&a.task_cnt[q], 1ull);
+        } else {
+            atomicOr(a.overflow, 64ull);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 __device__ __forceinline__ uint32_t shift_u8(uint32_t w) { return w ^ 0x80808080u; }
 
@@ -86,6 +115,9 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
     const int64_t p_begin = (int64_t)blockIdx.y * a.chunk;
     const int64_t p_end = min(a.ix.n, p_begin + a.chunk);
     if (q0 >= a.nq || p_begin >= p_end) return;
+    __shared__ uint32_t stage[MODE == SCAN_RANGE ? 4 * 3 * SCAP : 1];
+    uint32_t *st_task = stage + wid * 3 * SCAP, *st_id = st_task + SCAP, *st_dist = st_id + SCAP;
+    int scnt = 0; // staged hits of this wave (wave-uniform)
 
     constexpr int KSMAX = KS;
     v4i A[QT][KSMAX];
@@ -140,10 +172,13 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
             if (mode == SCAN_NN) {
                 lim[t][v] = INT_MIN;
             } else {
+                // |neg| < 2^26 for every valid pair (d <= 512), so clamping
+                // the bound below at -2^28 changes no decision; rows past nq
+                // get INT_MAX, which no neg reaches
                 const int64_t q = q0 + t * 16 + 4 * grp + v;
                 const int64_t qn = __shfl(qn_own[t], 4 * grp + v);
-                const int64_t r = q < a.nq ? a.qth[q].r_int : -1;
-                lim[t][v] = (int)max((int64_t)-INT_MAX, min((int64_t)INT_MAX, qn - r));
+                lim[t][v] = q < a.nq ? (int)max(-(int64_t)(1 << 28), min((int64_t)INT_MAX, qn - a.qth[q].r_int))
+                                     : INT_MAX;
             }
         }
 
@@ -190,50 +225,55 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
         xs += __shfl_xor(xs, 32);
         if (IP) xs = -128 * xs; // the base row's part of the uint8 key (0 for int8)
         int nxs = -xs;
+        // rows past the chunk (clamped copies of its last row) get a neg
+        // below -2^28, under every range bound
+        if (mode == SCAN_RANGE && p0 + row >= p_end) nxs = -(1 << 30);
         // opaque to the optimiser, so that 2 acc + nxs stays one shift-add
         // instead of being refolded into a shift and a subtraction
         asm volatile("" : "+v"(nxs));
-        const bool pvalid = p0 + row < p_end;
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
             v4i acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KSMAX; ++ks)
                 if (ks < ks_n) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t][ks], B[ks], acc, 0, 0, 0);
+            int neg[4];
+            bool any = false;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int neg = IP ? acc[v] + nxs : 2 * acc[v] + nxs;
-                if (mode == SCAN_NN) {
-                    // rows past the chunk repeat its last row, which leaves
-                    // the maximum unchanged, so no validity test is needed
-                    lim[t][v] = max(lim[t][v], neg);
-                } else {
-                    const bool hit = pvalid && q0 + t * 16 + 4 * grp + v < a.nq && neg >= lim[t][v];
+                neg[v] = IP ? acc[v] + nxs : 2 * acc[v] + nxs;
+                // SCAN_NN: rows past the chunk repeat its last row, which
+                // leaves the maximum unchanged, so no validity test is needed
+                if (mode == SCAN_NN) lim[t][v] = max(lim[t][v], neg[v]);
+                else any |= neg[v] >= lim[t][v];
+            }
+            // hits are rare: one wave-wide test per tile before the per-row work
+            if (mode == SCAN_RANGE && __ballot(any)) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const bool hit = neg[v] >= lim[t][v];
                     const unsigned long long hm = __ballot(hit);
                     if (hm) {
-                        unsigned long long base = 0;
-                        if (lane == (__ffsll((long long)hm) - 1))
-                            base = atomicAdd(a.item_cursor, (unsigned long long)__popcll(hm));
-                        base = __shfl(base, __ffsll((long long)hm) - 1);
+                        const int nh = __popcll(hm);
+                        if (scnt + nh > SCAP) {
+                            flush_hits(a, st_task, st_id, st_dist, scnt, lane);
+                            scnt = 0;
+                        }
                         const uint32_t qn = (uint32_t)__shfl(qn_own[t], 4 * grp + v);
                         if (hit) {
-                            const int64_t pos = (int64_t)base + __builtin_amdgcn_mbcnt_hi(
+                            const int slot = scnt + (int)__builtin_amdgcn_mbcnt_hi(
                                 (unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
-                            const int64_t q = q0 + t * 16 + 4 * grp + v;
-                            if (pos < a.item_cap) {
-                                a.item_task[pos] = (int32_t)q;
-                                a.item_id[pos] = (int32_t)(p0 + row);
-                                ((uint32_t *)a.item_dist)[pos] = qn - (uint32_t)neg;
-                                atomicAdd(&a.task_cnt[q], 1ull);
-                            } else {
-                                atomicOr(a.overflow, 64ull);
-                            }
+                            st_task[slot] = (uint32_t)(q0 + t * 16 + 4 * grp + v);
+                            st_id[slot] = (uint32_t)(p0 + row);
+                            st_dist[slot] = qn - (uint32_t)neg[v];
                         }
+                        scnt += nh;
                     }
                 }
             }
         }
     }
+    if (mode == SCAN_RANGE && scnt > 0) flush_hits(a, st_task, st_id, st_dist, scnt, lane);
     if (mode == SCAN_NN) {
 #pragma unroll
         for (int t = 0; t < QT; ++t)
@@ -268,6 +308,11 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a) {
     const int64_t p_begin = (int64_t)blockIdx.y * a.chunk;
     const int64_t p_end = min(a.ix.n, p_begin + a.chunk);
     if (q0 >= a.nq || p_begin >= p_end) return;
+    __shared__ uint32_t stage_ti[MODE == SCAN_RANGE ? 4 * 2 * SCAP : 1];
+    __shared__ double stage_d[MODE == SCAN_RANGE ? 4 * SCAP : 1];
+    uint32_t *st_task = stage_ti + wid * 2 * SCAP, *st_id = st_task + SCAP;
+    double *st_dist = stage_d + wid * SCAP;
+    int scnt = 0; // staged hits of this wave (wave-uniform)
     double qn_own[QTF];
     for (int t = 0; t < QTF; ++t) {
         const int64_t q = min(q0 + t * 16 + row, a.nq - 1);
@@ -326,27 +371,24 @@ __global__ __launch_bounds__(256) void k_scan_f32(ScanArgs a) {
                     const bool hit = pvalid && qrow < a.nq && dd <= rr_[t][v];
                     const unsigned long long hm = __ballot(hit);
                     if (hm) {
-                        unsigned long long base = 0;
-                        const int leader = __ffsll((long long)hm) - 1;
-                        if (lane == leader) base = atomicAdd(a.item_cursor, (unsigned long long)__popcll(hm));
-                        base = __shfl(base, leader);
-                        if (hit) {
-                            const int64_t pos = (int64_t)base + __builtin_amdgcn_mbcnt_hi(
-                                (unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
-                            const int64_t q = q0 + t * 16 + F64_ROW(grp, v);
-                            if (pos < a.item_cap) {
-                                a.item_task[pos] = (int32_t)q;
-                                a.item_id[pos] = (int32_t)(p0 + row);
-                                ((double *)a.item_dist)[pos] = dd;
-                                atomicAdd(&a.task_cnt[q], 1ull);
-                            } else {
-                                atomicOr(a.overflow, 64ull);
-                            }
+                        const int nh = __popcll(hm);
+                        if (scnt + nh > SCAP) {
+                            flush_hits(a, st_task, st_id, st_dist, scnt, lane);
+                            scnt = 0;
                         }
+                        if (hit) {
+                            const int slot = scnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                (unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
+                            st_task[slot] = (uint32_t)qrow;
+                            st_id[slot] = (uint32_t)(p0 + row);
+                            st_dist[slot] = dd;
+                        }
+                        scnt += nh;
                     }
                 }
             }
     }
+    if (mode == SCAN_RANGE && scnt > 0) flush_hits(a, st_task, st_id, st_dist, scnt, lane);
     if (mode == SCAN_NN) {
         for (int t = 0; t < QTF; ++t)
             for (int v = 0; v < 4; ++v) {
