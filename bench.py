@@ -229,28 +229,26 @@ def main():
     radius = float(nn_sorted[math.ceil(0.25 * nq) - 1])
     scan_tops = 2.0 * nq * n * d / (nn_ms * 1e-3) / 1e12
     log(f"radius {radius:.0f} (nn scan {nn_ms:.2f} ms, {scan_tops:.0f} TOP/s int8 MFMA)")
-    # context for the search kernels' rooflines: the rate of a plain random
-    # row gather (PyTorch index_select of d-byte rows at seeded random ids;
-    # reads random, writes sequential)
-    base_t = torch.from_numpy(w.base).cuda().view(torch.int64)  # rows of d/8 8-byte words
-    g_rows = 4_000_000
-    gidx = torch.from_numpy(np.random.default_rng(7).integers(0, n, size=g_rows)).cuda()
-    torch.index_select(base_t, 0, gidx)
+    # context for the search kernels' rooflines: the rate at which the GPU
+    # reads whole base rows at random when no read waits on another (the
+    # library's probe kernel, rows split over lanes as the search splits them)
+    g_rows = 16_000_000
+    rr.probe_row_gather(ix, g_rows, seed=7)
     g_ts = []
     for _ in range(5):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        torch.index_select(base_t, 0, gidx)
+        rr.probe_row_gather(ix, g_rows, seed=7)
         e1.record()
         torch.cuda.synchronize()
         g_ts.append(e0.elapsed_time(e1))
     g_ms = float(np.median(g_ts))
-    gather = {"op": "torch.index_select of random rows", "rows": g_rows, "row_bytes": d,
-              "ms": round(g_ms, 4), "rows_per_s": round(g_rows / (g_ms * 1e-3), 1),
-              "random_read_GBs": round(g_rows * d / (g_ms * 1e-3) / 1e9, 1)}
+    row_bytes = w.base.shape[1] * w.base.itemsize  # 128: no row padding at this width
+    gather = {"op": "rr_probe_row_gather: independent random reads of whole base rows", "rows": g_rows,
+              "row_bytes": row_bytes, "ms": round(g_ms, 4), "rows_per_s": round(g_rows / (g_ms * 1e-3), 1),
+              "random_read_GBs": round(g_rows * row_bytes / (g_ms * 1e-3) / 1e9, 1)}
     log(f"random row gather (context): {gather['rows_per_s'] / 1e9:.1f}G rows/s, "
         f"{gather['random_read_GBs']:.0f} GB/s of random reads")
-    del base_t, gidx
     t0 = time.time()
     truth_h = rr.brute_force_async(ix, q, radius)
     truth = truth_h.fetch(False)

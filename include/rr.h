@@ -245,6 +245,24 @@ rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t n
 rr_status rr_nn_dist(const rr_index *idx, const void *queries_dev, int64_t nq,
                      double *nn_dev, void *stream);
 
+/* Memory-system probe (not part of the paper's method): reads `gathers`
+ * whole base rows of the index at independent random row numbers, split
+ * over lanes as the search kernels split them, so that a caller timing it on
+ * `stream` gets the rate of random row reads the GPU sustains when no read
+ * waits on another: the ceiling for the search kernels, whose reads form
+ * dependent chains.  Gather i reads row (mix(seed + i + 0x9E3779B97F4A7C15)
+ * * n) >> 64 (64x64-bit product, high half; mix is the splitmix64
+ * finaliser z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27,
+ * z *= 0x94D049BB133111EB, z ^= z >> 31).  Workgroup w takes gathers
+ * [1024 w, 1024 w + 1024) and writes the wrapping uint32 sum of the 32-bit
+ * words of its rows (padding included) to sink_dev[w]; *parts receives the
+ * number of workgroups, ceil(gathers / 1024), and sink_dev (device, uint64)
+ * must hold that many.  Launches on `stream` and returns without waiting.
+ * Errors: RR_EINVAL (NULL pointers, gathers < 0, sink_len too small),
+ * RR_ESTATE (index not on the device), RR_EHIP. */
+rr_status rr_probe_row_gather(const rr_index *idx, int64_t gathers, uint64_t seed,
+                              uint64_t *sink_dev, int64_t sink_len, int64_t *parts, void *stream);
+
 /* Early-stopping metrics (Section 4.3 and the paper's early-stopping
  * appendix): Algorithm 1 with beam `beam` and no stopping rule over the nq
  * queries, recording for each query the state when it is about to make its

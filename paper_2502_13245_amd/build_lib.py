@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "librr.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["rr_api.cpp", "rr_build.cpp", "rr_tune.cpp", "rr_server.cpp", "rr_kernels.hip", "rr_scan.hip"]
+SOURCES = ["rr_api.cpp", "rr_build.cpp", "rr_tune.cpp", "rr_server.cpp", "rr_kernels.hip", "rr_scan.hip", "rr_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall",

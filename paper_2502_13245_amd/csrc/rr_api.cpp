@@ -967,6 +967,25 @@ extern "C" rr_status rr_nn_dist(const rr_index *ix, const void *queries_dev, int
     return RR_OK;
 }
 
+extern "C" rr_status rr_probe_row_gather(const rr_index *ix, int64_t gathers, uint64_t seed,
+                                         uint64_t *sink_dev, int64_t sink_len, int64_t *parts,
+                                         void *stream) {
+    if (!ix) return fail(RR_EINVAL, "index is NULL");
+    if (!parts) return fail(RR_EINVAL, "parts is NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (gathers < 0) return fail(RR_EINVAL, "gathers < 0");
+    const int64_t need = rr::probe_parts(gathers);
+    *parts = need;
+    if (need == 0) return RR_OK;
+    if (!sink_dev) return fail(RR_EINVAL, "sink is NULL");
+    if (sink_len < need) return fail(RR_EINVAL, "sink holds %lld partial sums, %lld needed",
+                                     (long long)sink_len, (long long)need);
+    const hipError_t e = rr::launch_probe_rows(ix->dev, gathers, seed, (unsigned long long *)sink_dev,
+                                               (hipStream_t)stream);
+    if (e != hipSuccess) return fail(RR_EHIP, "probe_row_gather: %s", hipGetErrorString(e));
+    return RR_OK;
+}
+
 extern "C" rr_status rr_results_total(const rr_results *res, int64_t *total) {
     if (!res || !total) return fail(RR_EINVAL, "results or total is NULL");
     HIP_TRY(hipStreamSynchronize(res->stream));

@@ -192,6 +192,10 @@ size_t results_copy_tmp_bytes(int64_t nq);
 // brute force (rr_scan.hip)
 hipError_t launch_brute_force(const DevIndex &ix, const uint8_t *qpad, const QThresh *qth,
                               int64_t nq, SearchBufs &sb, int num_cus, hipStream_t s);
+// memory-system probe (rr_probe.hip): partial sums written, and the launch
+int64_t probe_parts(int64_t gathers);
+hipError_t launch_probe_rows(const DevIndex &ix, int64_t gathers, uint64_t seed, unsigned long long *sink,
+                             hipStream_t s);
 hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, double *nn,
                           unsigned long long *bits, hipStream_t s);
 hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s);

@@ -149,6 +149,7 @@ SIGNATURES = {
     "rr_brute_force": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, C.POINTER(Allocator), _VP,
                                  C.POINTER(_VP)]),
     "rr_nn_dist": (C.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    "rr_probe_row_gather": (C.c_int, [_VP, _I64, C.c_uint64, _VP, _I64, C.POINTER(C.c_int64), _VP]),
     "rr_results_total": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "rr_results_copy": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "rr_results_stats": (C.c_int, [_VP, C.POINTER(QueryStats), C.POINTER(BatchStats)]),
@@ -552,6 +553,22 @@ def nn_dist(index: Index, queries, stream=None):
     _check(lib().rr_nn_dist(index._h, C.c_void_p(q.data_ptr()), q.shape[0],
                             C.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
+
+
+def probe_row_gather(index: Index, gathers: int, seed: int = 1, stream=None):
+    """Launch the random row-read probe (rr_probe_row_gather) on `stream`.
+
+    Returns the device tensor of per-workgroup uint32 word sums (int64)."""
+    import torch
+    if index.device is None:
+        raise RRError(5, "index is not on the device (to_device)")
+    n_parts = (int(gathers) + 1023) // 1024
+    sink = torch.zeros(max(1, n_parts), dtype=torch.int64, device=index.device)
+    parts = C.c_int64(0)
+    _check(lib().rr_probe_row_gather(index._h, int(gathers), C.c_uint64(int(seed) & (2**64 - 1)),
+                                     C.c_void_p(sink.data_ptr()), sink.numel(), C.byref(parts),
+                                     _stream_handle(stream)))
+    return sink[:parts.value]
 
 
 # ---------------------------------------------------------------------------
