@@ -50,7 +50,9 @@ struct ScanArgs {
     unsigned long long *overflow;
 };
 
-constexpr int QT = 4; // 16-query tiles per wave
+// 16-query tiles per wave: 8 for the nearest-distance scan of rows up to
+// 128 bytes (twice the MFMA work per base tile loaded), else 4
+constexpr int scan_qt(int mode, int ks) { return (mode == 0 && ks <= 2) ? 8 : 4; }
 constexpr int SCAP = 256; // range hits staged in LDS per wave before a flush
 
 // Range hits of one wave, staged in its own LDS slice and appended to the
@@ -104,7 +106,7 @@ __device__ __forceinline__ double dbl_unorder(unsigned long long k) {
 
 // MODE (SCAN_NN / SCAN_RANGE) is a template parameter so that each
 // instantiation keeps only its own per-query state in registers
-template <int DTYPE, int KS, bool IP, int MODE>
+template <int DTYPE, int KS, bool IP, int MODE, int QT>
 __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
     constexpr int mode = MODE;
     const int lane = threadIdx.x & 63;
@@ -417,15 +419,15 @@ __global__ void k_identity_tasks(int32_t *task_q, int64_t nq, unsigned long long
 
 template <int K, int MODE>
 static void launch_scan_int(const ScanArgs &a, bool ip, dim3 grid, dim3 block, hipStream_t s) {
-    if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true, MODE>), grid, block, 0, s, a);
-    else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false, MODE>), grid, block, 0, s, a);
-    else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true, MODE>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false, MODE>), grid, block, 0, s, a);
+    if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
+    else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
+    else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
 }
 
 static hipError_t launch_scan(const ScanArgs &a0, int mode, hipStream_t s) {
     ScanArgs a = a0;
-    const int qper = a.ix.dtype == RR_F32 ? 4 * 2 * 16 : 4 * QT * 16;
+    const int qper = a.ix.dtype == RR_F32 ? 4 * 2 * 16 : 4 * scan_qt(mode, a.ix.row_bytes / 64) * 16;
     const int64_t qblocks = (a.nq + qper - 1) / qper;
     // enough workgroups to fill the machine several times over
     int64_t target = 4096;
