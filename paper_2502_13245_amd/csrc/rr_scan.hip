@@ -12,7 +12,7 @@
 // d = -q.x; integer data keeps the search's unsigned key key_off - q.x,
 // where for uint8 q.x = q'.x' + 128 (sum q + sum x) - 128^2 P over the P
 // padded coordinates (padding is 0 before the shift).
-// Each wave keeps QT tiles of 16 queries in registers (A operand) and
+// Each wave keeps QT (8 or 4) tiles of 16 queries in registers (A operand) and
 // streams 16-point base tiles (B operand); the four waves of a workgroup
 // share the base tiles through the L1 cache.  Output tile layout of the int8
 // 16x16x64 MFMA: lane l, register v holds row 4*(l/16)+v, column l%16.
@@ -50,9 +50,9 @@ struct ScanArgs {
     unsigned long long *overflow;
 };
 
-// 16-query tiles per wave: 8 for the nearest-distance scan of rows up to
-// 128 bytes (twice the MFMA work per base tile loaded), else 4
-constexpr int scan_qt(int mode, int ks) { return (mode == 0 && ks <= 2) ? 8 : 4; }
+// 16-query tiles per wave: 8 for rows up to 128 bytes (twice the MFMA work
+// per base tile loaded), 4 for longer rows, whose A operands would not fit
+constexpr int scan_qt(int ks) { return ks <= 2 ? 8 : 4; }
 constexpr int SCAP = 256; // range hits staged in LDS per wave before a flush
 
 // Range hits of one wave, staged in its own LDS slice and appended to the
@@ -419,15 +419,15 @@ __global__ void k_identity_tasks(int32_t *task_q, int64_t nq, unsigned long long
 
 template <int K, int MODE>
 static void launch_scan_int(const ScanArgs &a, bool ip, dim3 grid, dim3 block, hipStream_t s) {
-    if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
-    else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
-    else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false, MODE, scan_qt(MODE, K)>), grid, block, 0, s, a);
+    if (a.ix.dtype == RR_U8 && ip) hipLaunchKernelGGL((k_scan_int<RR_U8, K, true, MODE, scan_qt(K)>), grid, block, 0, s, a);
+    else if (a.ix.dtype == RR_U8) hipLaunchKernelGGL((k_scan_int<RR_U8, K, false, MODE, scan_qt(K)>), grid, block, 0, s, a);
+    else if (ip) hipLaunchKernelGGL((k_scan_int<RR_I8, K, true, MODE, scan_qt(K)>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_scan_int<RR_I8, K, false, MODE, scan_qt(K)>), grid, block, 0, s, a);
 }
 
 static hipError_t launch_scan(const ScanArgs &a0, int mode, hipStream_t s) {
     ScanArgs a = a0;
-    const int qper = a.ix.dtype == RR_F32 ? 4 * 2 * 16 : 4 * scan_qt(mode, a.ix.row_bytes / 64) * 16;
+    const int qper = a.ix.dtype == RR_F32 ? 4 * 2 * 16 : 4 * scan_qt(a.ix.row_bytes / 64) * 16;
     const int64_t qblocks = (a.nq + qper - 1) / qper;
     // enough workgroups to fill the machine several times over
     int64_t target = 4096;
