@@ -202,30 +202,76 @@ __device__ __forceinline__ int64_t xcd_block() {
     return (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
 }
 
+// the value of lane (lane ^ J) for a compile-time J, without the address
+// arithmetic and LDS round trip of ds_bpermute where the hardware allows:
+// DPP quad permutes for 1 and 2, ds_swizzle in bit mode (xor mask, within
+// 32 lanes) for 4, 8 and 16.  Every lane of the wave must be active.
+template <int J> __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+    else return (uint32_t)__shfl_xor((int)v, J);
+}
+template <int J, typename D> __device__ __forceinline__ D xor_lane_d(D v) {
+    if constexpr (sizeof(D) == 4) {
+        return __builtin_bit_cast(D, xor_lane<J>(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = xor_lane<J>((uint32_t)u), hi = xor_lane<J>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(D, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// sum over aligned groups of G lanes (every lane of the wave active)
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m);
+    if constexpr (G >= 2) v += xor_lane_d<1>(v);
+    if constexpr (G >= 4) v += xor_lane_d<2>(v);
+    if constexpr (G >= 8) v += xor_lane_d<4>(v);
+    if constexpr (G >= 16) v += xor_lane_d<8>(v);
+    if constexpr (G >= 32) v += xor_lane_d<16>(v);
+    if constexpr (G >= 64) v += xor_lane_d<32>(v);
     return v;
 }
 
+// one compare-exchange stage of the bitonic network (merge size K, distance J)
+template <int K, int J, typename D>
+__device__ __forceinline__ void bitonic_stage(D &d, uint32_t &id, int lane) {
+    const D od = xor_lane_d<J>(d);
+    const uint32_t oi = xor_lane<J>(id);
+    const bool up = (lane & K) == 0;
+    const bool lower = (lane & J) == 0;
+    const bool take = (lower == up) ? key_less(od, oi, d, id) : key_less(d, id, od, oi);
+    if (take) {
+        d = od;
+        id = oi;
+    }
+}
+
 // bitonic sort of one (d, id) pair per lane, ascending over lanes 0..63
+// (called with every lane of the wave active)
 template <typename D> __device__ __forceinline__ void wave_sort(D &d, uint32_t &id) {
     const int lane = lane_id();
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            D od = __shfl_xor(d, j);
-            uint32_t oi = __shfl_xor(id, j);
-            bool up = (lane & k) == 0;
-            bool lower = (lane & j) == 0;
-            bool take = (lower == up) ? key_less(od, oi, d, id) : key_less(d, id, od, oi);
-            if (take) {
-                d = od;
-                id = oi;
-            }
-        }
-    }
+    bitonic_stage<2, 1>(d, id, lane);
+    bitonic_stage<4, 2>(d, id, lane);
+    bitonic_stage<4, 1>(d, id, lane);
+    bitonic_stage<8, 4>(d, id, lane);
+    bitonic_stage<8, 2>(d, id, lane);
+    bitonic_stage<8, 1>(d, id, lane);
+    bitonic_stage<16, 8>(d, id, lane);
+    bitonic_stage<16, 4>(d, id, lane);
+    bitonic_stage<16, 2>(d, id, lane);
+    bitonic_stage<16, 1>(d, id, lane);
+    bitonic_stage<32, 16>(d, id, lane);
+    bitonic_stage<32, 8>(d, id, lane);
+    bitonic_stage<32, 4>(d, id, lane);
+    bitonic_stage<32, 2>(d, id, lane);
+    bitonic_stage<32, 1>(d, id, lane);
+    bitonic_stage<64, 32>(d, id, lane);
+    bitonic_stage<64, 16>(d, id, lane);
+    bitonic_stage<64, 8>(d, id, lane);
+    bitonic_stage<64, 4>(d, id, lane);
+    bitonic_stage<64, 2>(d, id, lane);
+    bitonic_stage<64, 1>(d, id, lane);
 }
 
 // number of entries of the sorted arrays (ad, ai)[0, n) that are < (d, id);
