@@ -203,14 +203,23 @@ __device__ __forceinline__ int64_t xcd_block() {
 }
 
 // the value of lane (lane ^ J) for a compile-time J, without the address
-// arithmetic and LDS round trip of ds_bpermute where the hardware allows:
-// DPP quad permutes for 1 and 2, ds_swizzle in bit mode (xor mask, within
-// 32 lanes) for 4, 8 and 16.  Every lane of the wave must be active.
+// arithmetic and LDS round trip of ds_bpermute: DPP quad permutes for 1 and
+// 2, ds_swizzle in bit mode (xor mask, within 32 lanes) for 4, 8 and 16, and
+// for 32 the permlane32 swap (lanes 32-63 of one copy trade places with lanes
+// 0-31 of another: the first copy's upper half then holds the lower half's
+// values, the second copy's lower half the upper half's).  Every lane of the
+// wave must be active.
 template <int J> __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
-    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
-    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
-    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
-    else return (uint32_t)__shfl_xor((int)v, J);
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (J < 32) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane_id() & 32) ? r[0] : r[1];
+    }
 }
 template <int J, typename D> __device__ __forceinline__ D xor_lane_d(D v) {
     if constexpr (sizeof(D) == 4) {

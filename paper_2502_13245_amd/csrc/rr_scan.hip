@@ -85,6 +85,16 @@ __device__ __forceinline__ void flush_hits(const ScanArgs &a, const uint32_t *st
 
 __device__ __forceinline__ uint32_t shift_u8(uint32_t w) { return w ^ 0x80808080u; }
 
+// the value of lane (lane ^ 16) by ds_swizzle in bit mode, and of lane
+// (lane ^ 32) by the permlane32 swap (lanes 32-63 of one copy trade places
+// with lanes 0-31 of another), without ds_bpermute's address arithmetic and
+// LDS round trip; every lane of the wave must be active
+__device__ __forceinline__ int xor16(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x401F); }
+__device__ __forceinline__ int xor32(int v) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 32) ? r[0] : r[1]);
+}
+
 // running sum of the 16 unsigned bytes of v
 __device__ __forceinline__ int row_sum_u8(uint4 v, int s) {
     unsigned t = __builtin_amdgcn_udot4(v.x, 0x01010101u, (unsigned)s, false);
@@ -223,8 +233,8 @@ __global__ __launch_bounds__(256) void k_scan_int(ScanArgs a) {
                 }
             }
         }
-        xs += __shfl_xor(xs, 16);
-        xs += __shfl_xor(xs, 32);
+        xs += xor16(xs);
+        xs += xor32(xs);
         if (IP) xs = -128 * xs; // the base row's part of the uint8 key (0 for int8)
         int nxs = -xs;
         // rows past the chunk (clamped copies of its last row) get a neg
