@@ -249,7 +249,17 @@ __device__ __forceinline__ void bitonic_stage(D &d, uint32_t &id, int lane) {
     const uint32_t oi = xor_lane<J>(id);
     const bool up = (lane & K) == 0;
     const bool lower = (lane & J) == 0;
-    const bool take = (lower == up) ? key_less(od, oi, d, id) : key_less(d, id, od, oi);
+    bool take;
+    if constexpr (sizeof(D) == 4 && D(-1) > D(0)) {
+        // unsigned 32-bit distance: the (d, id) order is the order of the
+        // 64-bit key d:id.  A lane keeps the smaller key when lower == up and
+        // the larger one otherwise; for equal keys either choice leaves the
+        // lane's value unchanged.
+        const uint64_t mk = ((uint64_t)d << 32) | id, ok = ((uint64_t)od << 32) | oi;
+        take = (ok < mk) != (lower != up);
+    } else {
+        take = (lower == up) ? key_less(od, oi, d, id) : key_less(d, id, od, oi);
+    }
     if (take) {
         d = od;
         id = oi;
