@@ -17,6 +17,11 @@ OUT = os.path.join(HERE, "librr.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["rr_api.cpp", "rr_build.cpp", "rr_tune.cpp", "rr_server.cpp", "rr_kernels.hip", "rr_scan.hip", "rr_probe.hip"]
+# rr_inst.hip holds the search kernels of one kernel data type (element type
+# u8 0, i8 1, f32 2, bf16 pass 3, 8-bit pass 4; + 8 for the inner product);
+# it is compiled once per type so the instantiations build in parallel.
+INST_TYPES = {"u8": 0, "i8": 1, "f32": 2, "bf16": 3, "sq8": 4,
+              "u8ip": 8, "i8ip": 9, "f32ip": 10, "bf16ip": 11, "sq8ip": 12}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall",
@@ -29,8 +34,14 @@ PER_SOURCE = {"rr_scan.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE + PER_SOURCE.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
+    defs = []
+    if ":" in src:  # rr_inst.hip:<type>
+        src, tname = src.split(":")
+        defs = [f"-DRR_INST={INST_TYPES[tname]}"]
+        obj = os.path.join(BUILD, f"rr_inst_{tname}.o")
+    else:
+        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + COMMON + DEVICE + defs + PER_SOURCE.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -41,8 +52,8 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    srcs = [f"rr_inst.hip:{t}" for t in INST_TYPES] + [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]

@@ -81,6 +81,49 @@ def test_adaptive_full_size_sampled(rr, c2, beam):
     assert g.stats["expanded"].sum() > 100 and np.diff(g.numpy()[0]).max() > 1000
 
 
+@pytest.mark.parametrize("beam", [2, 3])
+@pytest.mark.parametrize("vl", [2, 3])
+@pytest.mark.parametrize("esr_scale", [1.0, 15.0, 20.0])
+def test_adaptive_narrow_beam_full_size_sampled(rr, c2, beam, vl, esr_scale):
+    """The benchmark's own region of settings (adaptive, b = 2 or 3, vl = 2
+    or 3, esr = r, 15r or 20r) over all 10,000 queries in one call, in the
+    benchmark's launch configuration; sampled queries (with the 20 heaviest)
+    bit-exact against the oracle."""
+    w, r = c2["w"], c2["r"]
+    es = dict(es_enable=True, es_visit_limit=vl, es_radius=r * esr_scale)
+    flush_print(f"full size adaptive b={beam} vl={vl} esr={esr_scale}r")
+    g = rr.range_search(c2["ix"], c2["q"], r, mode="adaptive", beam=beam, **es)
+    idx = _sample(np.diff(g.numpy()[0]), 17 * beam + vl)
+    o = oracle.range_search(w.base, c2["adj"], c2["entry"], w.queries[idx], r,
+                            mode=oracle.ADAPTIVE, beam=beam, **es)
+    _check_sample(g, o, idx, f"adaptive b={beam} vl={vl} esr={esr_scale}r")
+    assert g.stats["expanded"].sum() > 100
+
+
+def test_tuned_setting_full_size_sampled(rr, c2):
+    """The tuners' choice, as the benchmark makes it (rr_autotune for the
+    beam and kernel shape at recall 0.9, then rr_tune_early_stop for vl and
+    esr), fed unchanged to the oracle: sampled queries bit-exact in ids,
+    distances and counters."""
+    w, r = c2["w"], c2["r"]
+    flush_print("full size tuned setting")
+    truth = rr.brute_force_async(c2["ix"], c2["q"], r)
+    sp, rep = rr.autotune(c2["ix"], c2["q"], r, truth, target=0.9, reps=2, mode="adaptive",
+                          es_enable=True, es_visit_limit=10, es_radius=r)
+    sp, es_rep = rr.tune_early_stop(c2["ix"], c2["q"], r, truth, target=0.9, reps=2, params=sp)
+    flush_print(f"  tuned: beam {sp.beam}, es {sp.es_enable} vl {sp.es_visit_limit} "
+                f"esr {sp.es_radius}, shape {sp.waves_per_group}x{sp.cache_slots}")
+    g = rr.range_search(c2["ix"], c2["q"], r, params=sp)
+    idx = _sample(np.diff(g.numpy()[0]), 99)
+    o = oracle.range_search(w.base, c2["adj"], c2["entry"], w.queries[idx], r,
+                            mode=oracle.ADAPTIVE, beam=sp.beam, es_enable=bool(sp.es_enable),
+                            es_visit_limit=sp.es_visit_limit, es_radius=sp.es_radius)
+    _check_sample(g, o, idx, "tuned")
+    for k, qi in enumerate(idx):
+        assert g.stats["greedy_evals"][qi] == o.stats["greedy_evals"][k], f"tuned q{qi} greedy evals"
+    assert es_rep["met_target"] == 1
+
+
 def test_plain_es_and_brute_force_full_size(rr, c2):
     """Plain and early-stop beam search and the MFMA brute-force scan at
     full size: sampled queries against the oracle; on every query the

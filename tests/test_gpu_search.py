@@ -75,6 +75,25 @@ def test_adaptive_bit_exact(rr, small_u8, beam, es):
         assert g.stats["expanded"].sum() > 0
 
 
+@pytest.mark.parametrize("beam", [2, 3])
+@pytest.mark.parametrize("vl", [2, 3])
+@pytest.mark.parametrize("esr_scale", [1.0, 15.0, 20.0])
+def test_adaptive_narrow_beam_early_stop_bit_exact(rr, small_u8, beam, vl, esr_scale):
+    """The setting the tuners pick on the 1M workload: adaptive search with a
+    beam of 2 or 3 (expansion threshold = b), Algorithm 5 at vl = 2 or 3 and
+    an early-stop radius far above r (esr = 15r, 20r) as well as esr = r."""
+    esr = small_u8["r"] * esr_scale
+    flush_print(f"adaptive narrow beam={beam} vl={vl} esr={esr}")
+    kw = dict(es_enable=True, es_visit_limit=vl, es_radius=esr)
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive",
+                        beam=beam, **kw)
+    o = _orc(small_u8, mode=oracle.ADAPTIVE, beam=beam, **kw)
+    compare_exact(g, o, label=f"adaptive b={beam} vl={vl} esr={esr_scale}r")
+    assert g.stats["expanded"].sum() > 0
+    if esr_scale == 1.0:
+        assert g.stats["es_fired"].sum() > 0
+
+
 def _compare_doubling(g, o, label):
     """Doubling: bit-exact lists plus the counters that fix the rounds (beam
     evaluation counts differ by definition: a round reuses S's distances)."""

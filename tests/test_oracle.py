@@ -142,14 +142,15 @@ def test_golden_line_graphs(gname, case):
                                   mode=MODES[case["mode"]], beam=case["beam"],
                                   es_enable=case["mode"] == "es",
                                   es_visit_limit=case.get("vl", 0), es_radius=case.get("esr", 0.0),
-                                  lam=case.get("lambda", 1.0), metric=metric)
+                                  lam=case.get("lambda", 1.0), max_beam=case.get("max_beam", 1 << 20),
+                                  metric=metric)
     ids, dists = res.query(0)
     assert ids.tolist() == case["ids"]
     assert dists.tolist() == case["dists"]
     if res.stats is not None:
         st = res.stats[0]
         for key in ("visits", "es_fired", "expanded", "greedy_visits", "greedy_evals", "rounds",
-                    "final_beam"):
+                    "final_beam", "truncated"):
             if key in case:
                 assert st[key] == case[key], key
 
