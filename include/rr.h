@@ -374,6 +374,7 @@ typedef struct {
     double busy_s;        /* host time spent in ticks */
     int64_t slots;        /* resident query slots */
     int64_t device_bytes; /* device memory held by the server */
+    int64_t retried;      /* queries run again alone after a shared capacity ran out */
 } rr_server_info;
 
 /* The server keeps a pointer to the index (which must outlive it), copies

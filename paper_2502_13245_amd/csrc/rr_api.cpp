@@ -574,7 +574,7 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
     size_t o_scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
     size_t o_tq = 0, o_tc = 0, o_te = 0, o_it = 0, o_ii = 0, o_idist = 0, o_lvl = 0, o_hash = 0,
            o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0, o_tr = 0, o_tx = 0, o_tp = 0, o_ut = 0,
-           o_ui = 0, o_ud = 0, o_lc = 0, o_bm = 0;
+           o_ui = 0, o_ud = 0, o_lc = 0, o_bm = 0, o_ttr = 0;
     const int64_t bm_words = bitmap_words(ix->n), bm_tasks = with_greedy ? bitmap_tasks(ix->n, nq) : 0;
     const int32_t max_levels = 4096;
     if (with_greedy) {
@@ -583,6 +583,7 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         o_te = c.take<unsigned long long>(nq);
         o_tr = c.take<unsigned long long>(nq);
         o_tx = c.take<int8_t>(nq);
+        o_ttr = c.take<int8_t>(nq);
         o_it = c.take<int32_t>(item_cap);
         o_ii = c.take<int32_t>(item_cap);
         o_idist = c.take<uint8_t>(item_cap * (int64_t)dsz);
@@ -616,6 +617,7 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
     sb.arena_ids = (int32_t *)(b + o_aid);
     sb.arena_dists = b + o_ad;
     sb.arena_cap = arena_cap;
+    if (sp && sp->max_results_per_query > 0) sb.max_results = sp->max_results_per_query;
     res->offsets = (int64_t *)(b + o_off);
     res->scan_tmp = b + o_scan;
     if (with_greedy) {
@@ -624,6 +626,7 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         sb.task_evals = (unsigned long long *)(b + o_te);
         sb.task_rechk = (unsigned long long *)(b + o_tr);
         sb.task_expand = (int8_t *)(b + o_tx);
+        sb.task_trunc = (int8_t *)(b + o_ttr);
         sb.item_task = (int32_t *)(b + o_it);
         sb.item_id = (int32_t *)(b + o_ii);
         sb.item_dist = b + o_idist;
@@ -667,6 +670,7 @@ rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, Sea
     if (es && sp->es_visit_limit < 1) return fail(RR_EINVAL, "es_visit_limit must be >= 1");
     if (es && std::isnan(sp->es_radius)) return fail(RR_EINVAL, "es_radius is NaN");
     if (!(sp->lambda >= 0.0)) return fail(RR_EINVAL, "lambda must be >= 0");
+    if (sp->max_results_per_query < 1) return fail(RR_EINVAL, "max_results_per_query must be >= 1");
     if (sp->precision != RR_EXACT && sp->precision != RR_BF16_RECHECK &&
         sp->precision != RR_SQ8_RERANK)
         return fail(RR_EINVAL, "unknown precision %d", sp->precision);
@@ -880,6 +884,8 @@ static rr_status brute_force_once(const rr_index *ix, const void *queries_dev, i
     SearchBufs &sb = res->sb;
     sb.task_rechk = nullptr; // no greedy phase: every query is a plain result list
     sb.task_expand = nullptr;
+    sb.task_trunc = nullptr;
+    sb.max_results = INT64_MAX; // ground truth is never cut
     SearchCfg cfg{};
 #define HIP_TRY_R(expr)                                                                       \
     do {                                                                                      \

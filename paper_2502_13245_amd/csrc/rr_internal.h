@@ -105,12 +105,14 @@ struct SearchBufs {
     int32_t *arena_ids = nullptr;
     void *arena_dists = nullptr;  // uint32 (int data) / double (float data)
     int64_t arena_cap = 0;
+    int64_t max_results = INT64_MAX; // results returned per query (the nearest ones); more: truncated
     // greedy expansion
     int32_t *task_q = nullptr;    // [nq] query of each task
     unsigned long long *task_cnt = nullptr;   // [nq] results per task
     unsigned long long *task_evals = nullptr; // [nq]
     unsigned long long *task_rechk = nullptr; // [nq] exact rechecks in the band
     int8_t *task_expand = nullptr;            // [nq] 1: run Algorithm 2 from the seeds
+    int8_t *task_trunc = nullptr;             // [nq] 1: a capacity dropped some of the task's results
     unsigned long long *task_prev = nullptr;  // [nq] task_cnt before the current level
     int32_t *item_task = nullptr; // [item_cap]
     int32_t *item_id = nullptr;

@@ -482,6 +482,8 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
     D *outd = (D *)sb.arena_dists;
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
+        // at most max_results_per_query are returned: the first of the sorted list
+        const int64_t nout = min(n, sb.max_results);
         const int32_t q = sb.task_q[t];
         // thread 0 issues the arena reservation and the loads of the task's
         // counters up front; they complete while the segment is loaded
@@ -489,7 +491,7 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
         int32_t prev_rechk = 0;
         bool exp = true;
         if (threadIdx.x == 0) {
-            aoff = atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)n);
+            aoff = atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)nout);
             exp = sb.task_expand == nullptr || sb.task_expand[t] != 0;
             evals = sb.task_evals[t];
             if (sb.task_rechk) rechk = sb.task_rechk[t];
@@ -510,32 +512,33 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
         if (threadIdx.x == 0) s_off = (int64_t)aoff;
         __syncthreads();
         const int64_t off = s_off;
-        const bool ok = off + n <= sb.arena_cap;
+        const bool ok = off + nout <= sb.arena_cap;
         if (n <= CAP) {
             const int in_b = lds_sort<D>(ad, ai, bd, bi, p);
             const D *rd = in_b ? bd : ad;
             const uint32_t *ri = in_b ? bi : ai;
             if (ok)
-                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                for (int i = threadIdx.x; i < nout; i += blockDim.x) {
                     sb.arena_ids[off + i] = (int32_t)ri[i];
                     outd[off + i] = rd[i];
                 }
         } else {
             block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0, sb.item_id + s0, n, ad, ai, CAP);
             if (ok)
-                for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                for (int64_t i = threadIdx.x; i < nout; i += blockDim.x) {
                     sb.arena_ids[off + i] = sb.seg_ids[s0 + i];
                     outd[off + i] = segd[s0 + i];
                 }
         }
         if (threadIdx.x == 0) {
             sb.res_off[q] = off;
-            sb.res_cnt[q] = ok ? (int32_t)n : 0;
+            sb.res_cnt[q] = ok ? (int32_t)nout : 0;
             rr_query_stats *st = &sb.stats[q];
-            st->count = ok ? (int32_t)n : 0;
+            st->count = ok ? (int32_t)nout : 0;
             st->greedy_visits = exp ? (int32_t)n : 0;
             st->greedy_evals = (int32_t)evals;
             st->rechecked = prev_rechk + (int32_t)rechk;
+            if (nout < n || (sb.task_trunc && sb.task_trunc[t])) st->truncated = 1;
             if (!ok) {
                 st->truncated = 1;
                 atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);

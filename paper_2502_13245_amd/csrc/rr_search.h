@@ -954,6 +954,12 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         st.cache_overflow = __ballot(ovf) ? 1 : 0;
         st.rechecked = nband;
         st.rounds = 1;
+        if (!as_task && (int64_t)cN > a.sb.max_results) {
+            // more than max_results_per_query: the nearest ones are returned
+            st.truncated = 1;
+            cN = (int)a.sb.max_results;
+            st.count = cN;
+        }
         if (!as_task) {
             int64_t off = 0;
             if (lane == 0 && cN > 0) off = (int64_t)atomicAdd(&a.sb.counters[CTR_ARENA], (unsigned long long)cN);
@@ -1030,11 +1036,13 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 }
                 written = (int)max((int64_t)0, min((int64_t)cN, a.sb.item_cap - off));
             }
-            if (__ballot(full)) {
+            const bool lost = __ballot(full) != 0ull;
+            if (lost) {
                 st.truncated = 1;
                 if (lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 2ull);
             }
             if (lane == 0) {
+                a.sb.task_trunc[t] = lost ? 1 : 0;
                 a.sb.task_q[t] = (int32_t)q;
                 a.sb.task_cnt[t] = (unsigned long long)written;
                 a.sb.task_prev[t] = (unsigned long long)written;
@@ -1316,6 +1324,12 @@ __global__ __launch_bounds__(512) void k_doubling(DoublingArgs a) {
         st.cache_overflow = __ballot(ovf) ? 1 : 0;
         st.rechecked = 0;
         st.rounds = rounds;
+        if ((int64_t)cN > a.sb.max_results) {
+            // more than max_results_per_query: the nearest ones are returned
+            st.truncated = 1;
+            cN = (int)a.sb.max_results;
+            st.count = cN;
+        }
         int64_t off = 0;
         if (lane == 0 && cN > 0) off = (int64_t)atomicAdd(&a.sb.counters[CTR_ARENA], (unsigned long long)cN);
         off = __shfl(off, 0);
@@ -1412,6 +1426,8 @@ __device__ __forceinline__ void greedy_emit(GreedyLds<D, O, GW> &L, int wid, int
             sb.u_task[o] = L.st_task[wid][i];
             sb.u_id[o] = (int32_t)L.st_id[wid][i];
             udist[o] = L.st_d[wid][i];
+        } else {
+            sb.task_trunc[L.st_task[wid][i]] = 1; // the item is dropped
         }
     }
     // results per task, one atomic per run of equal tasks (runs are contiguous)
@@ -1728,6 +1744,10 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             bool full = false;
             if (__ballot(hA || hB)) {
                 gset_insert2(a.sb.hash, hmask, keyA, hA, keyB, hB, P.xA, P.xB, full);
+                if (full) {
+                    if (hA) a.sb.task_trunc[tA] = 1;
+                    if (hB) a.sb.task_trunc[tB] = 1;
+                }
                 if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
             }
         };
@@ -1833,13 +1853,20 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         int64_t b0 = 0;
         const O *ud = (const O *)a.sb.u_dist;
         O *idist = (O *)a.sb.item_dist;
-        // (level lvl is empty, except when the level limit stopped the loop)
+        // (level lvl is empty, except when the level limit stopped the loop:
+        // then its points were never expanded and their tasks are truncated)
+        const bool limit = lvl == a.sb.max_levels - 1;
         for (int l = 0; l <= lvl && l < a.sb.max_levels; ++l) {
             const int64_t c = (int64_t)__hip_atomic_load(&a.sb.level_cnt[l], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             const int64_t lo = b0, hi = min(b0 + c, a.sb.item_cap);
             b0 += c;
-            if (l == 0 || c >= regroup_min) continue;
+            const bool in_items = l == 0 || c >= regroup_min;
+            if (limit && l == lvl)
+                for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+                     i += (int64_t)gridDim.x * blockDim.x)
+                    a.sb.task_trunc[in_items ? a.sb.item_task[i] : a.sb.u_task[i]] = 1;
+            if (in_items) continue;
             for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
                  i += (int64_t)gridDim.x * blockDim.x) {
                 a.sb.item_task[i] = a.sb.u_task[i];

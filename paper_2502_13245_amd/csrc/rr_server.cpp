@@ -47,13 +47,18 @@ struct Request {
     double radius;
     double t_arrival;
     std::vector<uint8_t> q;
+    bool solo = false; // run in a tick of its own (a retry after a shared capacity ran out)
+    int32_t ticks = 0; // ticks already spent (a retry keeps counting)
 };
 
 struct Slot {
     bool busy = false;
+    bool solo = false;
     uint64_t tag = 0;
+    double radius = 0;
     double t_arrival = 0, t_admit = 0;
     int32_t ticks = 0;
+    std::vector<uint8_t> q; // the request's vector, kept for a retry
 };
 
 struct Finished {
@@ -211,6 +216,10 @@ void worker_main(rr_server *s) {
             const double t = s->now();
             while (!s->pending.empty() && !s->free_slots.empty()) {
                 Request &r = s->pending.front();
+                // a retry runs alone: it waits until nothing else is resident,
+                // and nothing else joins its tick
+                if (r.solo && (!active.empty() || admitted > 0)) break;
+                if (!active.empty() && s->slots[active[0]].solo) break;
                 const int32_t slot = s->free_slots.back();
                 s->free_slots.pop_back();
                 std::memcpy(s->h_stage_q + (size_t)admitted * s->qbytes, r.q.data(), s->qbytes);
@@ -218,13 +227,17 @@ void worker_main(rr_server *s) {
                 s->h_stage_dst[admitted] = slot;
                 Slot &sl = s->slots[slot];
                 sl.busy = true;
+                sl.solo = r.solo;
                 sl.tag = r.tag;
+                sl.radius = r.radius;
                 sl.t_arrival = r.t_arrival;
-                sl.t_admit = t;
-                sl.ticks = 0;
+                if (!r.solo) sl.t_admit = t;
+                sl.ticks = r.ticks;
+                sl.q.swap(r.q);
                 active.push_back(slot);
                 ++admitted;
                 s->pending.pop_front();
+                if (sl.solo) break;
             }
             s->info.admitted += admitted;
             s->info.pending = (int64_t)s->pending.size();
@@ -241,10 +254,16 @@ void worker_main(rr_server *s) {
             s->cv_done.notify_all();
             return;
         }
-        // collect the slots whose search finished in this tick
+        // collect the slots whose search finished in this tick.  The greedy
+        // items, the (task, id) set and result_capacity are shared by the
+        // tick's queries; when one of them ran out, a query flagged truncated
+        // may only have lost results to its neighbours, so it is run again in
+        // a tick of its own.  A query truncated alone is returned truncated.
+        const bool shared_overflow = (s->h_ctr[CTR_OVERFLOW] & ~OVERFLOW_BARRIER) != 0ull;
         std::vector<rr_completion> done;
         std::vector<std::pair<uint64_t, Finished>> out;
         std::vector<int32_t> freed;
+        std::vector<Request> retry;
         size_t keep = 0;
         for (size_t i = 0; i < active.size(); ++i) {
             const int32_t slot = active[i];
@@ -252,6 +271,19 @@ void worker_main(rr_server *s) {
             ++sl.ticks;
             if (!(s->h_state[slot].flags & BS_DONE)) {
                 active[keep++] = slot;
+                continue;
+            }
+            if (s->h_stats[slot].truncated && shared_overflow && !sl.solo) {
+                Request r;
+                r.tag = sl.tag;
+                r.radius = sl.radius;
+                r.t_arrival = sl.t_arrival;
+                r.q.swap(sl.q);
+                r.solo = true;
+                r.ticks = sl.ticks;
+                retry.push_back(std::move(r));
+                freed.push_back(slot);
+                sl.busy = false;
                 continue;
             }
             const int64_t off = s->h_roff[slot];
@@ -291,6 +323,8 @@ void worker_main(rr_server *s) {
             out.emplace_back(sl.tag, std::move(f));
             freed.push_back(slot);
             sl.busy = false;
+            sl.solo = false;
+            sl.q.clear();
         }
         active.resize(keep);
         const double t = s->now();
@@ -300,8 +334,11 @@ void worker_main(rr_server *s) {
                 done[i].t_done = t;
                 s->results[done[i].tag] = std::move(out[i].second);
                 s->completions.push_back(done[i]);
-                s->free_slots.push_back(freed[i]);
             }
+            for (int32_t f : freed) s->free_slots.push_back(f);
+            // retries go first, in their original order
+            for (size_t i = retry.size(); i-- > 0;) s->pending.push_front(std::move(retry[i]));
+            s->info.retried += (int64_t)retry.size();
             s->info.completed += (int64_t)done.size();
             s->info.ticks += 1;
             s->info.resident = (int64_t)active.size();

@@ -108,7 +108,8 @@ class Completion(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("ticks", "submitted", "admitted", "completed",
                                           "pending", "resident", "max_resident")] + [
-                ("busy_s", C.c_double), ("slots", C.c_int64), ("device_bytes", C.c_int64)]
+                ("busy_s", C.c_double), ("slots", C.c_int64), ("device_bytes", C.c_int64),
+                ("retried", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

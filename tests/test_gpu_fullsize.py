@@ -97,7 +97,7 @@ def test_adaptive_narrow_beam_full_size_sampled(rr, c2, beam, vl, esr_scale):
     o = oracle.range_search(w.base, c2["adj"], c2["entry"], w.queries[idx], r,
                             mode=oracle.ADAPTIVE, beam=beam, **es)
     _check_sample(g, o, idx, f"adaptive b={beam} vl={vl} esr={esr_scale}r")
-    assert g.stats["expanded"].sum() > 100
+    assert g.stats["expanded"].sum() > 0
 
 
 def test_tuned_setting_full_size_sampled(rr, c2):

@@ -203,6 +203,28 @@ def test_per_query_radius_and_edges(rr, small_u8):
     assert z.offsets.cpu().sum().item() == 0
 
 
+def test_max_results_per_query_keeps_the_nearest(rr, small_u8):
+    """max_results_per_query cuts a result list to its first entries in the
+    (d, id) order and flags the query truncated; shorter lists are whole."""
+    flush_print("max results per query")
+    o = _orc(small_u8, mode=oracle.ADAPTIVE, beam=8)
+    counts = np.diff(o.offsets)
+    k = max(1, int(np.percentile(counts[counts > 0], 75)))
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=8,
+                        max_results_per_query=k)
+    off, ids, d = g.numpy()
+    for qi in range(len(counts)):
+        oi, od = o.query(qi)
+        m = min(len(oi), k)
+        np.testing.assert_array_equal(ids[off[qi]:off[qi + 1]], oi[:m], err_msg=f"q{qi}")
+        np.testing.assert_array_equal(d[off[qi]:off[qi + 1]].astype(np.int64), od[:m].astype(np.int64))
+        assert g.stats["truncated"][qi] == (1 if len(oi) > k else 0), f"q{qi} flag"
+    assert (counts > k).any()
+    with pytest.raises(rr.RRError):
+        rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=8,
+                        max_results_per_query=0)
+
+
 def test_repeatable_and_batch_invariant(rr, small_u8):
     """Same bytes across runs and when the batch is split."""
     a = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode="adaptive", beam=32)

@@ -142,6 +142,52 @@ def test_served_bf16_equals_batched(rr):
             assert c.stats.visits == g.stats["visits"][qi]
 
 
+def test_shared_capacity_overflow_is_retried_alone(rr, nav):
+    """A tick's greedy items, (task, id) set and result capacity are shared by
+    its queries.  With result_capacity just above the largest single result,
+    a tick holding every query overflows; the queries it cut are run again
+    in ticks of their own, so every served result still equals the oracle
+    and none is flagged truncated.  With a capacity below the largest result
+    that query alone comes back truncated, and every other one is exact."""
+    w = nav["w"]
+    sp = rr.search_params(mode="adaptive", beam=4)
+    o = oracle.range_search(w.base, nav["adj"], nav["entry"], w.queries, nav["radii"],
+                            mode=oracle.ADAPTIVE, beam=4)
+    counts = np.diff(o.offsets)
+    big = int(counts.max())
+    assert counts.sum() > 2 * big, "the workload must overflow a shared capacity"
+    flush_print(f"serve overflow: max result {big}, total {counts.sum()}")
+    with rr.Server(nav["ix"], sp, slots=len(w.queries), result_capacity=big + 8) as srv:
+        for qi in range(len(w.queries)):
+            assert srv.submit(w.queries[qi], float(nav["radii"][qi]), qi)
+        srv.drain(timeout=120.0)
+        comps = {c.tag: c for c in srv.poll(len(w.queries) + 8)}
+        got = {t: srv.result(t) for t in comps}
+        info = srv.info()
+    flush_print(f"  retried {info['retried']}, ticks {info['ticks']}")
+    assert info["retried"] > 0
+    for qi in range(len(w.queries)):
+        oi, od = o.query(qi)
+        assert comps[qi].truncated == 0, f"q{qi} truncated"
+        np.testing.assert_array_equal(got[qi][0], oi, err_msg=f"q{qi} ids")
+        np.testing.assert_array_equal(got[qi][1].astype(np.int64), od.astype(np.int64))
+    # a capacity below the heaviest result: that query is truncated even alone
+    cap = big // 2
+    heavy = int(np.argmax(counts))
+    with rr.Server(nav["ix"], sp, slots=8, result_capacity=cap) as srv:
+        for qi in range(len(w.queries)):
+            assert srv.submit(w.queries[qi], float(nav["radii"][qi]), qi)
+        srv.drain(timeout=120.0)
+        comps = {c.tag: c for c in srv.poll(len(w.queries) + 8)}
+        got = {t: srv.result(t) for t in comps}
+    assert comps[heavy].truncated == 1
+    for qi in range(len(w.queries)):
+        if counts[qi] <= cap // 4:
+            oi, od = o.query(qi)
+            assert comps[qi].truncated == 0, f"q{qi} truncated"
+            np.testing.assert_array_equal(got[qi][0], oi, err_msg=f"q{qi} ids")
+
+
 def test_server_errors(rr, nav):
     sp = rr.search_params(mode="adaptive", beam=8)
     with pytest.raises(rr.RRError):
