@@ -23,6 +23,16 @@
  *  - base vectors are row-major n x d without padding on input; the library
  *    keeps its own padded device copy;
  *  - ids are int32 in [0, n), so n < 2^31.
+ *
+ * Hard limits of this build (RR_EINVAL beyond them):
+ *  - graph out-degree R <= 64 (the beam kernel reads one adjacency entry per
+ *    lane of a 64-wide wavefront);
+ *  - padded rows of at most 6,144 bytes (d <= 6144 for uint8/int8, d <= 1536
+ *    for float32);
+ *  - the dense scans (rr_brute_force, rr_nn_dist, rr_select_radius) take
+ *    integer rows of at most 512 bytes (d <= 512 for uint8/int8);
+ *  - beam b <= 4096; doubling's widest round <= 8192 (integer data) or
+ *    4096 (float data) entries.
  */
 #ifndef RR_H
 #define RR_H
@@ -145,6 +155,9 @@ typedef struct {
     int16_t cache_overflow;/* visited cache forgot entries (evals may repeat) */
     int32_t rechecked;     /* points re-decided in FP64 (RR_BF16_RECHECK)     */
     int32_t rounds;        /* doubling rounds                                 */
+    int32_t edges;         /* adjacency entries of the beam phase's visits
+                              (sum of deg(v) over V)                          */
+    int32_t greedy_edges;  /* the same for the greedy phase's visits          */
 } rr_query_stats;
 
 typedef struct {
@@ -160,6 +173,8 @@ typedef struct {
     int64_t greedy_items;      /* frontier items (in-ball points) processed */
     int64_t bytes_greedy;      /* algorithmic bytes of the greedy phase     */
     double greedy_kernel_ms;   /* with timing: greedy kernel alone          */
+    int64_t greedy_set_ops;    /* greedy phase: updates of the global (query,
+                                  point) set after the workgroup caches       */
 } rr_batch_stats;
 
 const char *rr_last_error(void);
@@ -244,6 +259,23 @@ rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t n
  * metric (nq doubles on the device).  Used to choose radii. */
 rr_status rr_nn_dist(const rr_index *idx, const void *queries_dev, int64_t nq,
                      double *nn_dev, void *stream);
+
+/* Percentile radii (Section 3 sets radii by the share of all query-base
+ * pairs they capture): radius_host[j] = the k-th smallest of all nq x n
+ * distances (squared L2, or -<p, q> for RR_IP) from queries_dev (nq x d in
+ * the index dtype, device) to the base, k = max(1, ceil(p[j] * nq * n)),
+ * p[j] in (0, 1] (host array of np values).  Counting scans find a
+ * threshold t with count(d <= t) >= the largest k (starting from the
+ * per-query nearest distances), the MFMA range scan collects every pair with
+ * d <= t, and each k is selected exactly among them by a radix select on the
+ * device.  Integer data: exact.  float32 data: the scan's FP64 distances.
+ * Device scratch from `alloc` (about 16 bytes per collected pair);
+ * synchronizes.  Errors: RR_EINVAL (arguments, p outside (0, 1], integer
+ * rows over 512 bytes), RR_ESTATE (index not on the device), RR_ENOMEM,
+ * RR_EHIP. */
+rr_status rr_select_radius(const rr_index *idx, const void *queries_dev, int64_t nq,
+                           const double *p, int32_t np, double *radius_host,
+                           const rr_allocator *alloc, void *stream);
 
 /* Memory-system probe (not part of the paper's method): reads `gathers`
  * whole base rows of the index at independent random row numbers, split
@@ -375,6 +407,7 @@ typedef struct {
     int64_t slots;        /* resident query slots */
     int64_t device_bytes; /* device memory held by the server */
     int64_t retried;      /* queries run again alone after a shared capacity ran out */
+    double max_tick_s;    /* longest tick (host time, device work included) */
 } rr_server_info;
 
 /* The server keeps a pointer to the index (which must outlive it), copies

@@ -381,7 +381,8 @@ static void free_device(rr_index *ix) {
     ix->alloc.release(ix->d_bf16);
     ix->alloc.release(ix->d_adj);
     ix->alloc.release(ix->d_sq8);
-    ix->d_base = ix->d_bf16 = ix->d_adj = ix->d_sq8 = nullptr;
+    ix->alloc.release(ix->d_deg);
+    ix->d_base = ix->d_bf16 = ix->d_adj = ix->d_sq8 = ix->d_deg = nullptr;
     ix->on_device = false;
     if (cur >= 0) (void)hipSetDevice(cur);
 }
@@ -463,6 +464,17 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
         sq_lo = lo;
         sq_scale = sc;
     }
+    // out-degrees (entries before the -1 padding), for the algorithmic byte counts
+    std::vector<uint8_t> deg((size_t)ix->n, 0);
+    for (int64_t i = 0; i < ix->n; ++i) {
+        int32_t k = 0;
+        while (k < ix->R && ix->adj[(size_t)i * ix->R + k] >= 0) ++k;
+        deg[(size_t)i] = (uint8_t)k;
+    }
+    ix->d_deg = ix->alloc.alloc(deg.size());
+    if (!ix->d_deg) return fail(RR_ENOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpyAsync(ix->d_deg, deg.data(), deg.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
     const size_t adj_bytes = std::max<size_t>(ix->adj.size() * sizeof(int32_t), 4);
     ix->d_adj = ix->alloc.alloc(adj_bytes);
     if (!ix->d_adj) return fail(RR_ENOMEM, "device allocation failed");
@@ -484,6 +496,7 @@ extern "C" rr_status rr_index_to_device(rr_index *ix, const rr_allocator *alloc,
     dv.row_bytes_exact = rb;
     dv.base_bf16 = (const uint8_t *)ix->d_bf16;
     dv.adj = (const int32_t *)ix->d_adj;
+    dv.deg = (const uint8_t *)ix->d_deg;
     dv.max_norm = maxn;
     dv.base_sq8 = (const uint8_t *)ix->d_sq8;
     dv.row_bytes_sq8 = rb8;
@@ -540,6 +553,107 @@ int64_t rr::next_pow2(int64_t x) {
     return p;
 }
 
+// Placement of one search's device buffers inside a single block.
+struct BufLayout {
+    size_t qpad, qth, ctr, roff, rcnt, stats, aid, ad, off, scan;
+    size_t tq = 0, tc = 0, te = 0, ik = 0, idist = 0, lvl = 0, hash = 0, soff = 0, scur = 0,
+           sid = 0, sd = 0, tr = 0, tx = 0, bm = 0, ttr = 0, tp = 0, lc = 0, uk = 0, ud = 0;
+    size_t total = 0;
+    int64_t nq = 0, arena_cap = 0, item_cap = 0, hash_cap = 0, bm_tasks = 0, bm_words = 0;
+    int32_t max_levels = 4096;
+    bool greedy = false;
+};
+
+static BufLayout layout_bufs(const rr_index *ix, int64_t nq, bool with_greedy, int64_t arena_cap,
+                             int64_t item_cap, int64_t hash_cap, int32_t qrow, int64_t bm_tasks) {
+    BufLayout L;
+    const int64_t dsz = ix->dtype == RR_F32 ? 8 : 4;
+    Carver c;
+    L.qpad = c.take<uint8_t>(nq * (int64_t)qrow);
+    L.qth = c.take<QThresh>(nq);
+    L.ctr = c.take<unsigned long long>(CTR_COUNT);
+    L.roff = c.take<int64_t>(nq);
+    L.rcnt = c.take<int32_t>(nq);
+    L.stats = c.take<rr_query_stats>(nq);
+    L.aid = c.take<int32_t>(arena_cap);
+    L.ad = c.take<uint8_t>(arena_cap * dsz);
+    L.off = c.take<int64_t>(nq + 1);
+    L.scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
+    L.nq = nq;
+    L.arena_cap = arena_cap;
+    L.greedy = with_greedy;
+    if (with_greedy) {
+        L.bm_words = bitmap_words(ix->n);
+        L.bm_tasks = bm_tasks;
+        L.item_cap = item_cap;
+        L.hash_cap = hash_cap;
+        L.tq = c.take<int32_t>(nq);
+        L.tc = c.take<unsigned long long>(nq);
+        L.te = c.take<unsigned long long>(nq);
+        L.tr = c.take<unsigned long long>(nq);
+        L.tx = c.take<int8_t>(nq);
+        L.ttr = c.take<int8_t>(nq);
+        L.ik = c.take<unsigned long long>(item_cap);
+        L.idist = c.take<uint8_t>(item_cap * dsz);
+        L.lvl = c.take<unsigned long long>(L.max_levels);
+        L.hash = c.take<unsigned long long>(hash_cap);
+        L.soff = c.take<int64_t>(nq + 1);
+        L.scur = c.take<unsigned long long>(nq);
+        L.sid = c.take<int32_t>(item_cap);
+        L.sd = c.take<uint8_t>(item_cap * dsz);
+        L.tp = c.take<unsigned long long>(nq);
+        L.lc = c.take<unsigned long long>(1 + 3 * LEVEL_CLOCKS);
+        L.bm = c.take<uint32_t>(bm_tasks * L.bm_words);
+        L.uk = c.take<unsigned long long>(item_cap);
+        L.ud = c.take<uint8_t>(item_cap * dsz);
+    }
+    L.total = c.take<uint8_t>(1);
+    return L;
+}
+
+static void bind_bufs(const BufLayout &L, uint8_t *b, const rr_search_params *sp, SearchBufs &sb,
+                      int64_t **offsets, void **scan_tmp, const uint8_t *deg) {
+    sb.deg = deg;
+    sb.qpad = b + L.qpad;
+    sb.qth = (QThresh *)(b + L.qth);
+    sb.counters = (unsigned long long *)(b + L.ctr);
+    sb.res_off = (int64_t *)(b + L.roff);
+    sb.res_cnt = (int32_t *)(b + L.rcnt);
+    sb.stats = (rr_query_stats *)(b + L.stats);
+    sb.arena_ids = (int32_t *)(b + L.aid);
+    sb.arena_dists = b + L.ad;
+    sb.arena_cap = L.arena_cap;
+    if (sp && sp->max_results_per_query > 0) sb.max_results = sp->max_results_per_query;
+    *offsets = (int64_t *)(b + L.off);
+    *scan_tmp = b + L.scan;
+    if (L.greedy) {
+        sb.task_q = (int32_t *)(b + L.tq);
+        sb.task_cnt = (unsigned long long *)(b + L.tc);
+        sb.task_evals = (unsigned long long *)(b + L.te);
+        sb.task_rechk = (unsigned long long *)(b + L.tr);
+        sb.task_expand = (int8_t *)(b + L.tx);
+        sb.task_trunc = (int8_t *)(b + L.ttr);
+        sb.item_key = (unsigned long long *)(b + L.ik);
+        sb.item_dist = b + L.idist;
+        sb.item_cap = L.item_cap;
+        sb.level_cnt = (unsigned long long *)(b + L.lvl);
+        sb.max_levels = L.max_levels;
+        sb.hash = (unsigned long long *)(b + L.hash);
+        sb.hash_cap = L.hash_cap;
+        sb.seg_off = (int64_t *)(b + L.soff);
+        sb.seg_cur = (unsigned long long *)(b + L.scur);
+        sb.seg_ids = (int32_t *)(b + L.sid);
+        sb.seg_dists = b + L.sd;
+        sb.task_prev = (unsigned long long *)(b + L.tp);
+        sb.level_clock = (unsigned long long *)(b + L.lc);
+        sb.u_key = (unsigned long long *)(b + L.uk);
+        sb.u_dist = b + L.ud;
+        sb.bm = (uint32_t *)(b + L.bm);
+        sb.bm_words = L.bm_words;
+        sb.bm_tasks = L.bm_tasks;
+    }
+}
+
 rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
                            const rr_search_params *sp, bool with_greedy, int64_t arena_cap,
                            int64_t item_cap, int64_t hash_cap, int32_t qrow,
@@ -560,94 +674,14 @@ rr_status rr::make_results(const rr_index *ix, const DevIndex &view, int64_t nq,
         res->alloc.has_user = true;
     }
     res->alloc.stream = stream;
-    const size_t dsz = ix->dtype == RR_F32 ? 8 : 4;
-    Carver c;
-    size_t o_qpad = c.take<uint8_t>(nq * (int64_t)qrow);
-    size_t o_qth = c.take<QThresh>(nq);
-    size_t o_ctr = c.take<unsigned long long>(CTR_COUNT);
-    size_t o_roff = c.take<int64_t>(nq);
-    size_t o_rcnt = c.take<int32_t>(nq);
-    size_t o_stats = c.take<rr_query_stats>(nq);
-    size_t o_aid = c.take<int32_t>(arena_cap);
-    size_t o_ad = c.take<uint8_t>(arena_cap * (int64_t)dsz);
-    size_t o_off = c.take<int64_t>(nq + 1);
-    size_t o_scan = c.take<uint8_t>((int64_t)results_copy_tmp_bytes(nq));
-    size_t o_tq = 0, o_tc = 0, o_te = 0, o_it = 0, o_ii = 0, o_idist = 0, o_lvl = 0, o_hash = 0,
-           o_soff = 0, o_scur = 0, o_sid = 0, o_sd = 0, o_tr = 0, o_tx = 0, o_tp = 0, o_ut = 0,
-           o_ui = 0, o_ud = 0, o_lc = 0, o_bm = 0, o_ttr = 0;
-    const int64_t bm_words = bitmap_words(ix->n), bm_tasks = with_greedy ? bitmap_tasks(ix->n, nq) : 0;
-    const int32_t max_levels = 4096;
-    if (with_greedy) {
-        o_tq = c.take<int32_t>(nq);
-        o_tc = c.take<unsigned long long>(nq);
-        o_te = c.take<unsigned long long>(nq);
-        o_tr = c.take<unsigned long long>(nq);
-        o_tx = c.take<int8_t>(nq);
-        o_ttr = c.take<int8_t>(nq);
-        o_it = c.take<int32_t>(item_cap);
-        o_ii = c.take<int32_t>(item_cap);
-        o_idist = c.take<uint8_t>(item_cap * (int64_t)dsz);
-        o_lvl = c.take<unsigned long long>(max_levels);
-        o_hash = c.take<unsigned long long>(hash_cap);
-        o_soff = c.take<int64_t>(nq + 1);
-        o_scur = c.take<unsigned long long>(nq);
-        o_sid = c.take<int32_t>(item_cap);
-        o_sd = c.take<uint8_t>(item_cap * (int64_t)dsz);
-        o_tp = c.take<unsigned long long>(nq);
-        o_lc = c.take<unsigned long long>(1 + 3 * LEVEL_CLOCKS);
-        o_bm = c.take<uint32_t>(bm_tasks * bm_words);
-        o_ut = c.take<int32_t>(item_cap);
-        o_ui = c.take<int32_t>(item_cap);
-        o_ud = c.take<uint8_t>(item_cap * (int64_t)dsz);
-    }
-    const size_t total = c.take<uint8_t>(1);
-    res->block = res->alloc.alloc(total);
+    const BufLayout L = layout_bufs(ix, nq, with_greedy, arena_cap, item_cap, hash_cap, qrow,
+                                    with_greedy ? bitmap_tasks(ix->n, nq) : 0);
+    res->block = res->alloc.alloc(L.total);
     if (!res->block) {
         delete res;
-        return fail(RR_ENOMEM, "device allocation of %zu bytes failed", total);
+        return fail(RR_ENOMEM, "device allocation of %zu bytes failed", L.total);
     }
-    uint8_t *b = (uint8_t *)res->block;
-    SearchBufs &sb = res->sb;
-    sb.qpad = b + o_qpad;
-    sb.qth = (QThresh *)(b + o_qth);
-    sb.counters = (unsigned long long *)(b + o_ctr);
-    sb.res_off = (int64_t *)(b + o_roff);
-    sb.res_cnt = (int32_t *)(b + o_rcnt);
-    sb.stats = (rr_query_stats *)(b + o_stats);
-    sb.arena_ids = (int32_t *)(b + o_aid);
-    sb.arena_dists = b + o_ad;
-    sb.arena_cap = arena_cap;
-    if (sp && sp->max_results_per_query > 0) sb.max_results = sp->max_results_per_query;
-    res->offsets = (int64_t *)(b + o_off);
-    res->scan_tmp = b + o_scan;
-    if (with_greedy) {
-        sb.task_q = (int32_t *)(b + o_tq);
-        sb.task_cnt = (unsigned long long *)(b + o_tc);
-        sb.task_evals = (unsigned long long *)(b + o_te);
-        sb.task_rechk = (unsigned long long *)(b + o_tr);
-        sb.task_expand = (int8_t *)(b + o_tx);
-        sb.task_trunc = (int8_t *)(b + o_ttr);
-        sb.item_task = (int32_t *)(b + o_it);
-        sb.item_id = (int32_t *)(b + o_ii);
-        sb.item_dist = b + o_idist;
-        sb.item_cap = item_cap;
-        sb.level_cnt = (unsigned long long *)(b + o_lvl);
-        sb.max_levels = max_levels;
-        sb.hash = (unsigned long long *)(b + o_hash);
-        sb.hash_cap = hash_cap;
-        sb.seg_off = (int64_t *)(b + o_soff);
-        sb.seg_cur = (unsigned long long *)(b + o_scur);
-        sb.seg_ids = (int32_t *)(b + o_sid);
-        sb.seg_dists = b + o_sd;
-        sb.task_prev = (unsigned long long *)(b + o_tp);
-        sb.level_clock = (unsigned long long *)(b + o_lc);
-        sb.bm = (uint32_t *)(b + o_bm);
-        sb.bm_words = bm_words;
-        sb.bm_tasks = bm_tasks;
-        sb.u_task = (int32_t *)(b + o_ut);
-        sb.u_id = (int32_t *)(b + o_ui);
-        sb.u_dist = b + o_ud;
-    }
+    bind_bufs(L, (uint8_t *)res->block, sp, res->sb, &res->offsets, &res->scan_tmp, view.deg);
     *out = res;
     return RR_OK;
 }
@@ -885,6 +919,7 @@ static rr_status brute_force_once(const rr_index *ix, const void *queries_dev, i
     sb.task_rechk = nullptr; // no greedy phase: every query is a plain result list
     sb.task_expand = nullptr;
     sb.task_trunc = nullptr;
+    sb.deg = nullptr;
     sb.max_results = INT64_MAX; // ground truth is never cut
     SearchCfg cfg{};
 #define HIP_TRY_R(expr)                                                                       \
@@ -941,6 +976,137 @@ extern "C" rr_status rr_brute_force(const rr_index *ix, const void *queries_dev,
         cap = hits + 1;
     }
     return fail(RR_ENOMEM, "brute force: result capacity could not be sized");
+}
+
+// Percentile radii: the k-th smallest of all nq * n distances, k =
+// ceil(p * nq * n).  A threshold t with k_max <= count(d <= t) <= the hit
+// budget is found by counting scans (starting from the per-query nearest
+// distances: the k-th smallest of those bounds the k-th smallest pair from
+// above), every pair with d <= t is collected by the range scan, and each k
+// is then selected exactly among them by a radix select on the device.
+extern "C" rr_status rr_select_radius(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                      const double *p, int32_t np, double *radius_out,
+                                      const rr_allocator *alloc, void *stream) {
+    if (!ix || !p || !radius_out) return fail(RR_EINVAL, "index, percentiles or output are NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 1 || nq >= (1ll << 31) || !queries_dev) return fail(RR_EINVAL, "need nq >= 1 queries");
+    if (np < 1) return fail(RR_EINVAL, "np must be >= 1");
+    if (ix->dtype != RR_F32 && ix->dev.row_bytes > 512)
+        return fail(RR_EINVAL, "integer rows longer than 512 bytes are not scanned");
+    const double pairs = (double)nq * (double)ix->n;
+    std::vector<int64_t> ks(np);
+    int64_t kmax = 0;
+    for (int32_t j = 0; j < np; ++j) {
+        if (!(p[j] > 0.0 && p[j] <= 1.0)) return fail(RR_EINVAL, "percentile %d must be in (0, 1]", j);
+        ks[j] = std::max<int64_t>(1, (int64_t)std::ceil(p[j] * pairs));
+        kmax = std::max(kmax, ks[j]);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    rr::Allocator al;
+    if (alloc && alloc->alloc && alloc->free) {
+        al.user = *alloc;
+        al.has_user = true;
+    }
+    al.stream = stream;
+    // nearest distance per query, sorted on the host
+    double *nn_dev = (double *)al.alloc((size_t)nq * 8);
+    unsigned long long *hist = (unsigned long long *)al.alloc(256 * 8);
+    if (!nn_dev || !hist) {
+        al.release(nn_dev);
+        al.release(hist);
+        return fail(RR_ENOMEM, "device allocation failed");
+    }
+    auto cleanup = [&]() {
+        al.release(nn_dev);
+        al.release(hist);
+    };
+    rr_status st = rr_nn_dist(ix, queries_dev, nq, nn_dev, stream);
+    std::vector<double> nn((size_t)nq);
+    if (st == RR_OK && (hipMemcpyAsync(nn.data(), nn_dev, (size_t)nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+        st = fail(RR_EHIP, "select_radius: copy of nearest distances failed");
+    if (st != RR_OK) {
+        cleanup();
+        return st;
+    }
+    std::sort(nn.begin(), nn.end());
+    auto count = [&](double t, int64_t *c) -> rr_status {
+        rr_results *res = nullptr;
+        rr_status r = brute_force_once(ix, queries_dev, nq, t, nullptr, alloc, stream, 0, &res, c);
+        if (res) rr_results_free(res);
+        return r;
+    };
+    // a threshold whose count reaches k_max (any threshold at or above the
+    // k-th smallest nearest distance does when k <= nq)
+    const int64_t budget = std::max<int64_t>(4 * kmax, 1 << 22);
+    double lo = -INFINITY, t = nn[(size_t)std::min<int64_t>(kmax, nq) - 1];
+    int64_t c = 0;
+    for (int it = 0; it < 200; ++it) {
+        st = count(t, &c);
+        if (st != RR_OK || c >= kmax) break;
+        lo = t;
+        t = t + std::max(std::fabs(t), 1.0) * 2.0;
+    }
+    // narrow while the collection would exceed the budget
+    for (int it = 0; st == RR_OK && c > budget && it < 80; ++it) {
+        const double mid = std::isinf(lo) ? t - std::max(std::fabs(t), 1.0) : 0.5 * (lo + t);
+        if (!(mid < t) || (!std::isinf(lo) && !(mid > lo))) break;
+        int64_t cm = 0;
+        st = count(mid, &cm);
+        if (st != RR_OK) break;
+        if (cm >= kmax) {
+            t = mid;
+            c = cm;
+        } else {
+            lo = mid;
+        }
+    }
+    if (st == RR_OK && c < kmax) st = fail(RR_EINVAL, "select_radius: no threshold reaches k");
+    // collect every pair with d <= t and select each k among them
+    rr_results *res = nullptr;
+    if (st == RR_OK) st = rr_brute_force(ix, queries_dev, nq, t, nullptr, alloc, stream, &res);
+    if (st == RR_OK) {
+        int64_t total = 0;
+        st = rr_results_total(res, &total);
+        const int key_bytes = ix->dtype == RR_F32 ? 8 : 4;
+        const void *keys = res ? res->sb.arena_dists : nullptr;
+        for (int32_t j = 0; st == RR_OK && j < np; ++j) {
+            unsigned long long prefix = 0, mask = 0;
+            int64_t rank = ks[j]; // 1-based rank among the remaining keys
+            for (int shift = key_bytes * 8 - 8; shift >= 0 && st == RR_OK; shift -= 8) {
+                unsigned long long h[256];
+                if (launch_digit_hist(keys, key_bytes, total, prefix, mask, shift, hist, s) != hipSuccess ||
+                    hipMemcpyAsync(h, hist, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    st = fail(RR_EHIP, "select_radius: histogram pass failed");
+                    break;
+                }
+                int digit = 0;
+                for (; digit < 256; ++digit) {
+                    if ((int64_t)h[digit] >= rank) break;
+                    rank -= (int64_t)h[digit];
+                }
+                if (digit == 256) {
+                    st = fail(RR_EHIP, "select_radius: rank beyond the collected pairs");
+                    break;
+                }
+                prefix |= (unsigned long long)digit << shift;
+                mask |= 255ull << shift;
+            }
+            if (st != RR_OK) break;
+            if (key_bytes == 4) {
+                radius_out[j] = (double)((int64_t)(uint32_t)prefix - ix->dev.key_off);
+            } else {
+                const unsigned long long u = (prefix >> 63) ? (prefix & ~(1ull << 63)) : ~prefix;
+                double v;
+                std::memcpy(&v, &u, 8);
+                radius_out[j] = v;
+            }
+        }
+    }
+    if (res) rr_results_free(res);
+    cleanup();
+    return st;
 }
 
 extern "C" rr_status rr_nn_dist(const rr_index *ix, const void *queries_dev, int64_t nq,
@@ -1100,28 +1266,30 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
             agg->truncated += q.truncated;
             agg->cache_overflow += q.cache_overflow;
         }
-        // query + adjacency rows of visited points + rows of evaluated points + output
-        agg->bytes_algorithmic = res->nq * row + (agg->visits + agg->greedy_visits) * 4ll * res->R +
+        // query + adjacency entries of the visited points (4 deg(v) bytes
+        // each) + rows of evaluated points + output
+        int64_t edges = 0, greedy_edges = 0;
+        for (int64_t i = 0; i < res->nq; ++i) {
+            edges += st[i].edges;
+            greedy_edges += st[i].greedy_edges;
+        }
+        agg->bytes_algorithmic = res->nq * row + (edges + greedy_edges) * 4ll +
                                  (agg->evals + agg->greedy_evals) * row + agg->total_results * 8ll +
                                  (agg->rechecked + agg->total_results) * exact_row;
         int64_t beam_out = 0;
         for (int64_t i = 0; i < res->nq; ++i)
             if (!st[i].expanded) beam_out += st[i].count;
-        agg->bytes_beam = res->nq * row + agg->visits * 4ll * res->R + agg->evals * row + beam_out * 8ll;
+        agg->bytes_beam = res->nq * row + edges * 4ll + agg->evals * row + beam_out * 8ll;
         // greedy phase: adjacency of every in-ball point it visits, rows of the
         // points it evaluates, and its output pairs
-        agg->bytes_greedy = agg->greedy_visits * 4ll * res->R + agg->greedy_evals * row +
+        agg->bytes_greedy = greedy_edges * 4ll + agg->greedy_evals * row +
                             (agg->total_results - beam_out) * 8ll;
-        if (res->sb.level_cnt) {
+        if (res->sb.level_clock) {
             unsigned long long ctr[CTR_COUNT];
             HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
-            const int64_t lv = (int64_t)ctr[CTR_LEVELS];
-            agg->greedy_levels = lv;
-            std::vector<unsigned long long> lc((size_t)std::max<int64_t>(lv, 1));
-            if (lv > 0)
-                HIP_TRY(hipMemcpy(lc.data(), res->sb.level_cnt, lv * sizeof(unsigned long long),
-                                  hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < lv; ++i) agg->greedy_items += (int64_t)lc[i];
+            agg->greedy_levels = (int64_t)ctr[CTR_LEVELS];
+            agg->greedy_items = (int64_t)ctr[CTR_GREEDY_ITEMS];
+            agg->greedy_set_ops = (int64_t)ctr[CTR_SET_OPS];
         }
         if (res->timing) {
             float ms = 0.f;
@@ -1131,7 +1299,7 @@ extern "C" rr_status rr_results_stats(const rr_results *res, rr_query_stats *per
             agg->greedy_ms = ms;
             HIP_TRY(hipEventElapsedTime(&ms, res->ev[0], res->ev[3]));
             agg->total_ms = ms;
-            if (res->sb.level_cnt && res->nq > 0) {
+            if (res->sb.level_clock && res->nq > 0) {
                 HIP_TRY(hipEventElapsedTime(&ms, res->ev[2], res->ev[4]));
                 agg->greedy_kernel_ms = ms;
             }

@@ -45,6 +45,7 @@ struct DevIndex {
     int32_t row_bytes_exact = 0;
     const uint8_t *base_bf16 = nullptr;
     const int32_t *adj = nullptr;
+    const uint8_t *deg = nullptr; // [n] out-degree of every point
     float max_norm = 0.f; // largest |x| (float data)
     int32_t metric = 0;   // rr_metric
     int64_t key_off = 0;  // integer data, inner product: keys are key_off - <p, q>
@@ -69,7 +70,7 @@ struct QThresh {
 struct BeamState {
     int32_t nB, visits, evals, cursor;
     int32_t flags; // BS_* below
-    int32_t pad;
+    int32_t edges; // adjacency entries read so far
 };
 enum { BS_STARTED = 1, BS_DONE = 2, BS_OVF = 4 };
 
@@ -113,15 +114,16 @@ struct SearchBufs {
     unsigned long long *task_rechk = nullptr; // [nq] exact rechecks in the band
     int8_t *task_expand = nullptr;            // [nq] 1: run Algorithm 2 from the seeds
     int8_t *task_trunc = nullptr;             // [nq] 1: a capacity dropped some of the task's results
+    const uint8_t *deg = nullptr; // [n] out-degrees (greedy visits' adjacency entries); null: not counted
     unsigned long long *task_prev = nullptr;  // [nq] task_cnt before the current level
-    int32_t *item_task = nullptr; // [item_cap]
-    int32_t *item_id = nullptr;
+    // items: in-ball points of the greedy phase (or brute-force hits), as
+    // (task << 32 | id) keys with their distances, grouped by level
+    unsigned long long *item_key = nullptr; // [item_cap]
     void *item_dist = nullptr;
     int64_t item_cap = 0;
-    int32_t *u_task = nullptr;    // [item_cap] a level as emitted, before grouping by task
-    int32_t *u_id = nullptr;
+    unsigned long long *u_key = nullptr; // [item_cap] a level as emitted, before grouping by task
     void *u_dist = nullptr;
-    unsigned long long *level_cnt = nullptr; // [max_levels]
+    unsigned long long *level_cnt = nullptr; // [max_levels] items per level (brute force: hits)
     unsigned long long *level_clock = nullptr; // [1 + 3 * LEVEL_CLOCKS] greedy phase timestamps
     int32_t max_levels = 0;
     unsigned long long *hash = nullptr; // [hash_cap] (task << 32 | id), ~0 = empty
@@ -149,12 +151,14 @@ constexpr int LEVEL_CLOCKS = 64;
 constexpr unsigned long long OVERFLOW_BARRIER = 256ull;
 
 enum {
-    CTR_QUEUE = 0,     // next query to take
-    CTR_ARENA = 1,     // arena cursor
-    CTR_TASKS = 2,     // number of expansion tasks
-    CTR_OVERFLOW = 3,  // non-zero: some capacity was exceeded
-    CTR_LEVELS = 4,    // levels run by the greedy phase
-    CTR_BARRIER = 5,   // arrivals at the greedy kernel's grid barrier
+    CTR_QUEUE = 0,        // next query to take
+    CTR_ARENA = 1,        // arena cursor
+    CTR_TASKS = 2,        // number of expansion tasks
+    CTR_OVERFLOW = 3,     // non-zero: some capacity was exceeded
+    CTR_LEVELS = 4,       // levels run by the greedy phase
+    CTR_BARRIER = 5,      // arrivals at the greedy kernel's grid barrier
+    CTR_GREEDY_ITEMS = 6, // items the greedy phase expanded (seeds included)
+    CTR_SET_OPS = 7,      // greedy phase: updates sent to the global (task, id) set
     CTR_COUNT = 8
 };
 
@@ -188,7 +192,8 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, const uint8_t *qpad,
                                int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
                                const int32_t *arena_ids, const void *arena_dists, int32_t *ids,
-                               void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s);
+                               void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s,
+                               int64_t capacity = INT64_MAX);
 size_t results_copy_tmp_bytes(int64_t nq);
 
 // brute force (rr_scan.hip)
@@ -201,6 +206,11 @@ hipError_t launch_probe_rows(const DevIndex &ix, int64_t gathers, uint64_t seed,
 hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, double *nn,
                           unsigned long long *bits, hipStream_t s);
 hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s);
+// radix select: hist[256] = counts of the 8-bit digit at `shift` among the
+// keys (uint32, or FP64 mapped to ordered uint64) whose masked bits equal prefix
+hipError_t launch_digit_hist(const void *keys, int key_bytes, int64_t n, unsigned long long prefix,
+                             unsigned long long mask, int shift, unsigned long long *hist,
+                             hipStream_t s);
 hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
                               hipStream_t s);
 
@@ -223,7 +233,7 @@ struct rr_index {
     bool on_device = false;
     int device = -1;
     rr::Allocator alloc;
-    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr, *d_sq8 = nullptr;
+    void *d_base = nullptr, *d_bf16 = nullptr, *d_adj = nullptr, *d_sq8 = nullptr, *d_deg = nullptr;
     rr::DevIndex dev;
 };
 

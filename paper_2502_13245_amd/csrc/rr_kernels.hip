@@ -274,7 +274,8 @@ template <typename D> __global__ void k_scatter(SearchBufs sb) {
     for (int64_t c = w0 * 64; c < total; c += tw * 64) {
         const int64_t i = c + lane;
         const bool valid = i < total;
-        const int32_t t = valid ? sb.item_task[i] : -1;
+        const unsigned long long key = valid ? sb.item_key[i] : ~0ull;
+        const int32_t t = valid ? (int32_t)(key >> 32) : -1;
         const int32_t tprev = __shfl_up(t, 1);
         const bool head = valid && (lane == 0 || tprev != t);
         const unsigned long long hm = __ballot(head);
@@ -291,7 +292,7 @@ template <typename D> __global__ void k_scatter(SearchBufs sb) {
         b = __shfl(b, hl);
         if (valid) {
             const int64_t pos = sb.seg_off[t] + (int64_t)b + (lane - hl);
-            sb.seg_ids[pos] = sb.item_id[i];
+            sb.seg_ids[pos] = (int32_t)(uint32_t)key;
             sd[pos] = idist[i];
         }
     }
@@ -476,10 +477,13 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
     D *bd = (D *)(ai + CAP);
     uint32_t *bi = (uint32_t *)(bd + CAP);
     __shared__ int64_t s_off;
+    __shared__ int s_edges; // adjacency entries of the task's greedy visits
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
     D *segd = (D *)sb.seg_dists;
     D *tmpd = (D *)sb.item_dist;
     D *outd = (D *)sb.arena_dists;
+    if (threadIdx.x == 0) s_edges = 0;
+    __syncthreads();
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
         // at most max_results_per_query are returned: the first of the sorted list
@@ -498,17 +502,22 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
             prev_rechk = sb.stats[q].rechecked;
         }
         const int p = max(64, (int)((n + 63) & ~63ll));
+        int my_edges = 0;
         if (n <= CAP) {
             for (int i = threadIdx.x; i < p; i += blockDim.x) {
                 if (i < n) {
                     ad[i] = segd[s0 + i];
                     ai[i] = (uint32_t)sb.seg_ids[s0 + i];
+                    if (sb.deg) my_edges += sb.deg[ai[i]];
                 } else {
                     ad[i] = dmax<D>();
                     ai[i] = RR_EMPTY32 - (uint32_t)(i - n);
                 }
             }
+        } else if (sb.deg) {
+            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) my_edges += sb.deg[sb.seg_ids[s0 + i]];
         }
+        if (my_edges) atomicAdd(&s_edges, my_edges);
         if (threadIdx.x == 0) s_off = (int64_t)aoff;
         __syncthreads();
         const int64_t off = s_off;
@@ -523,7 +532,10 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
                     outd[off + i] = rd[i];
                 }
         } else {
-            block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0, sb.item_id + s0, n, ad, ai, CAP);
+            // the item arrays are free once scattered: they serve as the
+            // merge passes' scratch
+            block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0,
+                                  reinterpret_cast<int32_t *>(sb.item_key) + s0, n, ad, ai, CAP);
             if (ok)
                 for (int64_t i = threadIdx.x; i < nout; i += blockDim.x) {
                     sb.arena_ids[off + i] = sb.seg_ids[s0 + i];
@@ -537,12 +549,14 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
             st->count = ok ? (int32_t)nout : 0;
             st->greedy_visits = exp ? (int32_t)n : 0;
             st->greedy_evals = (int32_t)evals;
+            st->greedy_edges = exp && sb.deg ? s_edges : 0;
             st->rechecked = prev_rechk + (int32_t)rechk;
             if (nout < n || (sb.task_trunc && sb.task_trunc[t])) st->truncated = 1;
             if (!ok) {
                 st->truncated = 1;
                 atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);
             }
+            s_edges = 0;
         }
         __syncthreads();
     }
@@ -680,6 +694,47 @@ hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, S
 }
 
 // --------------------------------------------------------------------------
+// radix select over distance keys (percentile radii)
+// --------------------------------------------------------------------------
+
+// order-preserving unsigned image of a key: uint32 keys as they are,
+// FP64 distances by their bits (sign bit set for >= 0, all bits flipped
+// for < 0)
+__device__ __forceinline__ unsigned long long select_key(const void *keys, int key_bytes, int64_t i) {
+    if (key_bytes == 4) return (unsigned long long)reinterpret_cast<const uint32_t *>(keys)[i];
+    const unsigned long long u = reinterpret_cast<const unsigned long long *>(keys)[i];
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+// counts of the 8-bit digit at `shift` among the keys whose bits under
+// `mask` equal `prefix` (one LDS histogram per workgroup, then 256 global adds)
+__global__ void k_digit_hist(const void *keys, int key_bytes, int64_t n, unsigned long long prefix,
+                             unsigned long long mask, int shift, unsigned long long *hist) {
+    __shared__ unsigned int h[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = select_key(keys, key_bytes, i);
+        if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+hipError_t launch_digit_hist(const void *keys, int key_bytes, int64_t n, unsigned long long prefix,
+                             unsigned long long mask, int shift, unsigned long long *hist,
+                             hipStream_t s) {
+    hipError_t e = launch_fill_u64(hist, 256, 0ull, s);
+    if (e != hipSuccess || n == 0) return e;
+    const int blocks = (int)std::min<int64_t>((n + 1023) / 1024, 2048);
+    hipLaunchKernelGGL(k_digit_hist, dim3(blocks), dim3(256), 0, s, keys, key_bytes, n, prefix, mask,
+                       shift, hist);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // CSR output: exclusive scan of per-query counts, then segment copies
 // --------------------------------------------------------------------------
 
@@ -758,9 +813,10 @@ __device__ int64_t last_le(const int64_t *offsets, int64_t lo, int64_t hi, int64
 template <typename DIN, typename DOUT>
 __global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, int64_t nq,
                                 const int32_t *aid, const DIN *ad, int32_t *ids, DOUT *dists,
-                                DIN key_off) {
+                                DIN key_off, int64_t capacity) {
     __shared__ int64_t s_q[2];
-    const int64_t total = offsets[nq];
+    // positions at or beyond the caller's capacity are not written
+    const int64_t total = min(offsets[nq], capacity);
     for (int64_t b0 = (int64_t)blockIdx.x * COPY_SPAN; b0 < total;
          b0 += (int64_t)gridDim.x * COPY_SPAN) {
         const int64_t b1 = min(total, b0 + COPY_SPAN);
@@ -797,7 +853,8 @@ hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, 
 hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, const uint8_t *qpad,
                                int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
                                const int32_t *arena_ids, const void *arena_dists, int32_t *ids,
-                               void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s) {
+                               void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s,
+                               int64_t capacity) {
     (void)precision;
     (void)ix;
     (void)qpad;
@@ -808,11 +865,11 @@ hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, con
     if (dtype == RR_F32)
         hipLaunchKernelGGL((k_copy_segments<double, float>), dim3(blocks), dim3(256), 0, s,
                            res_off, offsets, nq, arena_ids, (const double *)arena_dists, ids,
-                           (float *)dists, 0.0);
+                           (float *)dists, 0.0, capacity);
     else
         hipLaunchKernelGGL((k_copy_segments<uint32_t, int32_t>), dim3(blocks), dim3(256), 0, s,
                            res_off, offsets, nq, arena_ids, (const uint32_t *)arena_dists, ids,
-                           (int32_t *)dists, (uint32_t)ix.key_off);
+                           (int32_t *)dists, (uint32_t)ix.key_off, capacity);
     return hipGetLastError();
 }
 

@@ -41,8 +41,7 @@ struct ScanArgs {
     // nn mode
     unsigned long long *nn_bits; // [nq] min distance bits (uint32 value or double bits)
     // range mode: hits appended as items (task = query)
-    int32_t *item_task;
-    int32_t *item_id;
+    unsigned long long *item_key; // (query << 32) | id
     void *item_dist;
     int64_t item_cap;
     unsigned long long *item_cursor;
@@ -71,8 +70,7 @@ __device__ __forceinline__ void flush_hits(const ScanArgs &a, const uint32_t *st
         const int64_t pos = (int64_t)base + i;
         const uint32_t q = st_task[i];
         if (pos < a.item_cap) {
-            a.item_task[pos] = (int32_t)q;
-            a.item_id[pos] = (int32_t)st_id[i];
+            a.item_key[pos] = ((unsigned long long)q << 32) | st_id[i];
             ((DT *)a.item_dist)[pos] = st_dist[i];
             atomicAdd(&a.task_cnt[q], 1ull);
         } else {
@@ -502,8 +500,7 @@ hipError_t launch_brute_force(const DevIndex &ix, const uint8_t *qpad, const QTh
     a.qpad = qpad;
     a.qth = qth;
     a.nq = nq;
-    a.item_task = sb.item_task;
-    a.item_id = sb.item_id;
+    a.item_key = sb.item_key;
     a.item_dist = sb.item_dist;
     a.item_cap = sb.item_cap;
     a.item_cursor = &sb.level_cnt[0];

@@ -26,6 +26,7 @@
 // accumulation of the differences.
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -732,6 +733,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         uint32_t *bi = biA, *bio = biB;
         int nB = 1;
         int visits = 0, evals = 1;
+        int edges = 0; // adjacency entries read by the visits (sum of out-degrees)
         int cursor = 0;
         bool es_fired = false;
         if (a.state && (a.state[q].flags & BS_STARTED)) {
@@ -741,6 +743,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             nB = bs.nB;
             visits = bs.visits;
             evals = bs.evals;
+            edges = bs.edges;
             cursor = bs.cursor;
             ovf = lane == 0 && (bs.flags & BS_OVF);
             const D *sd = (const D *)a.st_d + (size_t)q * bcap;
@@ -816,6 +819,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             // N_out(p*), drop ids already evaluated
             int32_t f = -1;
             if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
+            edges += __popcll(__ballot(f >= 0));
             bool cand = false;
             if (f >= 0) cand = !seen_insert(htab, cs_mask, (uint32_t)f, ovf);
             const unsigned long long cm = __ballot(cand);
@@ -901,7 +905,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 bs.evals = evals;
                 bs.cursor = cursor;
                 bs.flags = BS_STARTED | (any_ovf ? BS_OVF : 0);
-                bs.pad = 0;
+                bs.edges = edges;
                 a.state[q] = bs;
             }
             wave_sync();
@@ -944,6 +948,8 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         rr_query_stats st;
         st.visits = visits;
         st.evals = evals;
+        st.edges = edges;
+        st.greedy_edges = 0;
         st.greedy_visits = 0;
         st.greedy_evals = 0;
         st.count = as_task ? 0 : cN;
@@ -1003,14 +1009,14 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                     const int m = __popcll(im);
                     if (m == 0) continue;
                     int64_t off = 0;
-                    if (lane == 0) off = (int64_t)atomicAdd(&a.sb.level_cnt[0], (unsigned long long)m);
+                    if (lane == 0)
+                        off = (int64_t)(atomicAdd(&a.sb.level_cnt[0], (unsigned long long)m));
                     off = __shfl(off, 0);
                     const int64_t o = off + mbcnt(im);
                     const bool wr = inr && o < a.sb.item_cap;
                     if (wr) {
                         const uint32_t id = bi[i] & RR_IDMASK;
-                        a.sb.item_task[o] = (int32_t)t;
-                        a.sb.item_id[o] = (int32_t)id;
+                        a.sb.item_key[o] = ((unsigned long long)(uint32_t)t << 32) | id;
                         idist[o] = dx;
                         if (expand) tset_add(a.sb, hmask, t, id, full);
                     }
@@ -1020,7 +1026,8 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 }
             } else {
                 int64_t off = 0;
-                if (lane == 0) off = (int64_t)atomicAdd(&a.sb.level_cnt[0], (unsigned long long)cN);
+                if (lane == 0)
+                    off = (int64_t)(atomicAdd(&a.sb.level_cnt[0], (unsigned long long)cN));
                 off = __shfl(off, 0);
                 for (int i = lane; i < cN; i += 64) {
                     const int64_t o = off + i;
@@ -1029,8 +1036,7 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                         continue;
                     }
                     const uint32_t id = bi[i] & RR_IDMASK;
-                    a.sb.item_task[o] = (int32_t)t;
-                    a.sb.item_id[o] = (int32_t)id;
+                    a.sb.item_key[o] = ((unsigned long long)(uint32_t)t << 32) | id;
                     idist[o] = (O)bd[i];
                     tset_add(a.sb, hmask, t, id, full);
                 }
@@ -1136,7 +1142,7 @@ __global__ __launch_bounds__(512) void k_doubling(DoublingArgs a) {
         int nB = 0;
         bool ovf = false, trunc = false, es_any = false;
         int b = cfg.beam, rounds = 0, cN = 0;
-        int64_t ns = 0, visits_all = 0, evals_all = 0;
+        int64_t ns = 0, visits_all = 0, evals_all = 0, edges_all = 0;
 
         // merge the k (<= 64) candidates held by the lanes into B, trimmed to
         // b; candidates equal to a key of B or to another candidate are
@@ -1269,6 +1275,7 @@ __global__ __launch_bounds__(512) void k_doubling(DoublingArgs a) {
                 }
                 int32_t f = -1;
                 if (lane < R) f = ix.adj[(size_t)p * (size_t)R + lane];
+                edges_all += __popcll(__ballot(f >= 0));
                 bool cand = false;
                 if (f >= 0) cand = !seen_insert(htab, cs_mask, (uint32_t)f, ovf);
                 const unsigned long long cm = __ballot(cand);
@@ -1314,6 +1321,8 @@ __global__ __launch_bounds__(512) void k_doubling(DoublingArgs a) {
         rr_query_stats st;
         st.visits = (int32_t)min(visits_all, (int64_t)INT32_MAX);
         st.evals = (int32_t)min(evals_all, (int64_t)INT32_MAX);
+        st.edges = (int32_t)min(edges_all, (int64_t)INT32_MAX);
+        st.greedy_edges = 0;
         st.greedy_visits = 0;
         st.greedy_evals = 0;
         st.count = cN;
@@ -1423,8 +1432,7 @@ __device__ __forceinline__ void greedy_emit(GreedyLds<D, O, GW> &L, int wid, int
     for (int i = lane; i < n; i += 64) {
         const int64_t o = dst + i;
         if (o < sb.item_cap) {
-            sb.u_task[o] = L.st_task[wid][i];
-            sb.u_id[o] = (int32_t)L.st_id[wid][i];
+            sb.u_key[o] = ((unsigned long long)(uint32_t)L.st_task[wid][i] << 32) | L.st_id[wid][i];
             udist[o] = L.st_d[wid][i];
         } else {
             sb.task_trunc[L.st_task[wid][i]] = 1; // the item is dropped
@@ -1506,7 +1514,8 @@ __device__ void greedy_regroup(const SearchBufs &sb, int64_t lo, int64_t hi) {
     for (int64_t c = lo + gw * 64; c < hi; c += tw * 64) {
         const int64_t i = c + lane;
         const bool valid = i < hi;
-        const int32_t t = valid ? sb.u_task[i] : -1;
+        const unsigned long long key = valid ? sb.u_key[i] : ~0ull;
+        const int32_t t = valid ? (int32_t)(key >> 32) : -1;
         const int32_t tprev = __shfl_up(t, 1);
         const bool head = valid && (lane == 0 || tprev != t);
         const unsigned long long hm = __ballot(head);
@@ -1524,8 +1533,7 @@ __device__ void greedy_regroup(const SearchBufs &sb, int64_t lo, int64_t hi) {
         const unsigned long long ob = __shfl(o, hl);
         const int64_t pos = valid ? sb.seg_off[t] + (int64_t)ob + (lane - hl) : -1;
         if (valid && pos >= lo && pos < hi) {
-            sb.item_task[pos] = t;
-            sb.item_id[pos] = sb.u_id[i];
+            sb.item_key[pos] = key;
             idist[pos] = ud[i];
         }
     }
@@ -1578,6 +1586,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
     D *qd = L.cd[wid];        // their distances once evaluated
     const int64_t hmask = a.sb.hash_cap - 1;
     const int64_t ntasks = (int64_t)a.sb.counters[CTR_TASKS];
+    uint32_t set_ops = 0; // global set updates of this lane (summed over the wave at the end)
     // phase timestamps (block 0, one lane): kernel start, then per level the
     // ends of expansion, segment scan and regroup
     const bool clock_lane = blockIdx.x == 0 && threadIdx.x == 0;
@@ -1601,8 +1610,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         __syncthreads();
         // where this level's items are: the item arrays (level 0, or regrouped)
         // or the unsorted level as emitted
-        const int32_t *src_task = grouped ? a.sb.item_task : a.sb.u_task;
-        const int32_t *src_id = grouped ? a.sb.item_id : a.sb.u_id;
+        const unsigned long long *src_key = grouped ? a.sb.item_key : a.sb.u_key;
         // this workgroup's block of the level (items beyond item_cap were dropped)
         const int64_t avail = max((int64_t)0, min(cnt, a.sb.item_cap - base));
         const int64_t per = (avail + gridDim.x - 1) / gridDim.x;
@@ -1704,8 +1712,9 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         auto load_item = [&](int64_t it, int32_t &t, int32_t &p, bool &in) {
             in = it < i1;
             const int64_t k = in ? base + it : 0;
-            t = src_task[k];
-            p = src_id[k];
+            const unsigned long long key = src_key[k];
+            t = (int32_t)(key >> 32);
+            p = (int32_t)(uint32_t)key;
         };
         // sanitises the item (items beyond item_cap are never written) and
         // loads its expansion flag and adjacency row
@@ -1732,6 +1741,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             const bool cB = okB && !wg_cache_seen(L.cache, keyB);
             P.bA = cA && tA < a.sb.bm_tasks;
             P.bB = cB && tB < a.sb.bm_tasks;
+            set_ops += (cA ? 1u : 0u) + (cB ? 1u : 0u);
             P.oA = ~0u;
             P.oB = ~0u;
             if (P.bA) P.oA = atomicOr(&a.sb.bm[(int64_t)tA * a.sb.bm_words + ((uint32_t)fA >> 5)],
@@ -1847,6 +1857,10 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         }
         base = next_base;
     }
+    {
+        const unsigned long long w_ops = group_sum<64>((unsigned long long)set_ops);
+        if (lane == 0 && w_ops) atomicAdd(&a.sb.counters[CTR_SET_OPS], w_ops);
+    }
     // move the levels that were expanded as emitted into the item arrays (the
     // kernel's end orders these writes before the finalisation)
     {
@@ -1865,18 +1879,21 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             if (limit && l == lvl)
                 for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
                      i += (int64_t)gridDim.x * blockDim.x)
-                    a.sb.task_trunc[in_items ? a.sb.item_task[i] : a.sb.u_task[i]] = 1;
+                    a.sb.task_trunc[(int32_t)((in_items ? a.sb.item_key[i] : a.sb.u_key[i]) >> 32)] = 1;
             if (in_items) continue;
             for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
                  i += (int64_t)gridDim.x * blockDim.x) {
-                a.sb.item_task[i] = a.sb.u_task[i];
-                a.sb.item_id[i] = a.sb.u_id[i];
+                a.sb.item_key[i] = a.sb.u_key[i];
                 idist[i] = ud[i];
             }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.sb.counters[CTR_LEVELS] = (unsigned long long)lvl;
+        unsigned long long items = 0;
+        for (int l = 0; l <= lvl && l < a.sb.max_levels; ++l)
+            items += __hip_atomic_load(&a.sb.level_cnt[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.sb.counters[CTR_GREEDY_ITEMS] = items;
         if (lvl == a.sb.max_levels - 1 &&
             __hip_atomic_load(&a.sb.level_cnt[lvl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
             atomicOr(&a.sb.counters[CTR_OVERFLOW], 16ull);
@@ -1957,6 +1974,7 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     if (per_cu > 2) per_cu = 2;
+    // the level barriers need every workgroup resident: a cooperative launch
     dim3 grid((unsigned)(per_cu * num_cus)), block(GW * 64);
     void *args[] = {&a};
     e = hipLaunchCooperativeKernel((const void *)kern, grid, block, args, shmem, s);

@@ -342,7 +342,9 @@ void worker_main(rr_server *s) {
             s->info.completed += (int64_t)done.size();
             s->info.ticks += 1;
             s->info.resident = (int64_t)active.size();
-            s->info.busy_s += std::chrono::duration<double>(Clock::now() - tb).count();
+            const double tick_s = std::chrono::duration<double>(Clock::now() - tb).count();
+            s->info.busy_s += tick_s;
+            s->info.max_tick_s = std::max(s->info.max_tick_s, tick_s);
             s->cv_done.notify_all();
         }
     }
@@ -400,11 +402,13 @@ int64_t server_bytes(int64_t n, int64_t S, int64_t b, bool greedy, int64_t resul
         add(S * 4);
         add(S * 8 * 3);
         add(S);
+        add(S);                          // truncation flags
         add(c.item_cap * (8 + dsz) * 2); // items and the unsorted level
-        add(4096 * 8);
+        add(4096 * 8);                   // per-level counts
         add(c.hash_cap * 8);
-        add((S + 1) * 8 + S * 8 * 2);
-        add(c.item_cap * (4 + dsz));
+        add((S + 1) * 8 + S * 8 * 2);    // segment offsets, cursors, previous counts
+        add(c.item_cap * (4 + dsz));     // segment ids and distances
+        add(S * 8);                      // adjacency entries per task
         add((1 + 3 * LEVEL_CLOCKS) * 8);
         add(bitmap_tasks(n, S) * bitmap_words(n) * 4);
     }

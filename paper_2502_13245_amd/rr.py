@@ -50,7 +50,8 @@ class QueryStats(C.Structure):
     _fields_ = [("visits", C.c_int32), ("evals", C.c_int32), ("greedy_visits", C.c_int32),
                 ("greedy_evals", C.c_int32), ("count", C.c_int32), ("final_beam", C.c_int32),
                 ("es_fired", C.c_int16), ("expanded", C.c_int16), ("truncated", C.c_int16),
-                ("cache_overflow", C.c_int16), ("rechecked", C.c_int32), ("rounds", C.c_int32)]
+                ("cache_overflow", C.c_int16), ("rechecked", C.c_int32), ("rounds", C.c_int32),
+                ("edges", C.c_int32), ("greedy_edges", C.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("visits", np.int32), ("evals", np.int32), ("greedy_visits", np.int32),
@@ -58,7 +59,7 @@ STATS_DTYPE = np.dtype([("visits", np.int32), ("evals", np.int32), ("greedy_visi
                         ("final_beam", np.int32), ("es_fired", np.int16),
                         ("expanded", np.int16), ("truncated", np.int16),
                         ("cache_overflow", np.int16), ("rechecked", np.int32),
-                        ("rounds", np.int32)])
+                        ("rounds", np.int32), ("edges", np.int32), ("greedy_edges", np.int32)])
 assert STATS_DTYPE.itemsize == C.sizeof(QueryStats)
 
 
@@ -69,7 +70,7 @@ class BatchStats(C.Structure):
                  "bytes_algorithmic", "bytes_beam")] + [
                 (k, C.c_double) for k in ("beam_ms", "greedy_ms", "total_ms")] + [
                 (k, C.c_int64) for k in ("greedy_levels", "greedy_items", "bytes_greedy")] + [
-                ("greedy_kernel_ms", C.c_double)]
+                ("greedy_kernel_ms", C.c_double), ("greedy_set_ops", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,7 +110,7 @@ class ServerInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("ticks", "submitted", "admitted", "completed",
                                           "pending", "resident", "max_resident")] + [
                 ("busy_s", C.c_double), ("slots", C.c_int64), ("device_bytes", C.c_int64),
-                ("retried", C.c_int64)]
+                ("retried", C.c_int64), ("max_tick_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -150,6 +151,8 @@ SIGNATURES = {
     "rr_brute_force": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, C.POINTER(Allocator), _VP,
                                  C.POINTER(_VP)]),
     "rr_nn_dist": (C.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    "rr_select_radius": (C.c_int, [_VP, _VP, _I64, C.POINTER(C.c_double), _I32,
+                                   C.POINTER(C.c_double), C.POINTER(Allocator), _VP]),
     "rr_probe_row_gather": (C.c_int, [_VP, _I64, C.c_uint64, _VP, _I64, C.POINTER(C.c_int64), _VP]),
     "rr_results_total": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "rr_results_copy": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
@@ -415,6 +418,7 @@ class PendingResults:
             agg["levels"] = self.level_profile()
         return Results(offsets, ids[:total], dists[:total], st, agg)
 
+
     def level_profile(self, max_levels=64):
         """Per level of the greedy phase: points expanded and the time spent
         expanding them and regrouping the next level (ms)."""
@@ -554,6 +558,19 @@ def nn_dist(index: Index, queries, stream=None):
     _check(lib().rr_nn_dist(index._h, C.c_void_p(q.data_ptr()), q.shape[0],
                             C.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
+
+
+def select_radius(index: Index, queries, p, stream=None):
+    """rr_select_radius: the k-th smallest of all query-base distances,
+    k = ceil(p * nq * n), for one percentile p or a list of them."""
+    q = queries.contiguous()
+    ps = np.atleast_1d(np.asarray(p, dtype=np.float64))
+    out = np.empty(len(ps), np.float64)
+    _check(lib().rr_select_radius(index._h, C.c_void_p(q.data_ptr()), q.shape[0],
+                                  ps.ctypes.data_as(C.POINTER(C.c_double)), len(ps),
+                                  out.ctypes.data_as(C.POINTER(C.c_double)), index._alloc.ref(),
+                                  _stream_handle(stream)))
+    return float(out[0]) if np.ndim(p) == 0 else out
 
 
 def probe_row_gather(index: Index, gathers: int, seed: int = 1, stream=None):

@@ -155,7 +155,7 @@ def latent_mixture_u8(n: int, nq: int, d: int, k: int, sigma: float, seed: int, 
                       latent: int = 16, center_std: float = 40.0, within: int = 10,
                       noise: float = 4.0, spread: float = 0.35, zipf: float = 1.0,
                       dense_frac: float = 0.1, dense_sigma: float = 6.0, chunk: int = 1 << 16,
-                      name: str = "latent-u8") -> Workload:
+                      signed: bool = False, name: str = "latent-u8") -> Workload:
     """uint8 mixture with low intrinsic dimension, like image descriptors.
 
     Centres lie on a `latent`-dimensional Gaussian sheet around 127.5
@@ -165,11 +165,14 @@ def latent_mixture_u8(n: int, nq: int, d: int, k: int, sigma: float, seed: int, 
     clipped to [0, 255].  sigma_k = sigma * exp(U[-spread, spread]), except a
     `dense_frac` share of clusters that are near-duplicate groups with
     sigma_k = dense_sigma * exp(U[-0.5, 0.5]).  Zipf(`zipf`) cluster weights
-    set the cluster sizes, so a few dense groups hold thousands of points."""
+    set the cluster sizes, so a few dense groups hold thousands of points.
+    With `signed` the sheet is centred at 0 and values are int8 in
+    [-128, 127]."""
     ss = np.random.SeedSequence(seed).spawn(7)
     r_c, r_s, r_l, r_x, r_ql, r_qx, r_b = [np.random.default_rng(x) for x in ss]
     A = r_c.standard_normal((d, latent)) * (center_std / np.sqrt(latent))
-    centers = np.clip(127.5 + r_c.standard_normal((k, latent)) @ A.T, 0.0, 255.0)
+    lo, hi, mid, dt = (-128.0, 127.0, 0.0, np.int8) if signed else (0.0, 255.0, 127.5, np.uint8)
+    centers = np.clip(mid + r_c.standard_normal((k, latent)) @ A.T, lo, hi)
     scale = sigma * np.exp(r_s.uniform(-spread, spread, size=k))
     dense = r_s.random(k) < dense_frac
     scale[dense] = dense_sigma * np.exp(r_s.uniform(-0.5, 0.5, size=int(dense.sum())))
@@ -177,21 +180,22 @@ def latent_mixture_u8(n: int, nq: int, d: int, k: int, sigma: float, seed: int, 
 
     def draw(m, rl, rx):
         lab = _labels(rl, k, m, zipf)
-        out = np.empty((m, d), dtype=np.uint8)
+        out = np.empty((m, d), dtype=dt)
         for a in range(0, m, chunk):
             b = min(m, a + chunk)
             L = lab[a:b]
             z = rx.standard_normal(size=(b - a, within)) * scale[L, None]
             v = centers[L] + np.einsum("ndm,nm->nd", basis[L], z)
             v += noise * rx.standard_normal(size=(b - a, d))
-            out[a:b] = np.clip(np.rint(v), 0, 255).astype(np.uint8)
+            out[a:b] = np.clip(np.rint(v), lo, hi).astype(dt)
         return out
 
     base = draw(n, r_l, r_x)
     queries = draw(nq, r_ql, r_qx)
     meta = dict(generator="latent_mixture_u8", n=n, nq=nq, d=d, k=k, sigma=sigma, seed=seed,
                 latent=latent, center_std=center_std, within=within, noise=noise, spread=spread,
-                zipf=zipf, dense_frac=dense_frac, dense_sigma=dense_sigma, dtype="uint8")
+                zipf=zipf, dense_frac=dense_frac, dense_sigma=dense_sigma,
+                dtype="int8" if signed else "uint8")
     return Workload(name, base, queries, meta)
 
 
@@ -272,6 +276,14 @@ def config_1m_f32(seed: int = 2, n: int = 1_000_000, nq: int = 10_000) -> Worklo
     """1M base + 10,000 queries, d=96 float32 unit-norm embeddings: 2,000
     clusters on a 16-dimensional sheet, Zipf cluster sizes."""
     return latent_mixture_f32(n, nq, 96, 2_000, 0.35, seed, name=f"f32-{n // 1000}k-d96")
+
+
+def config_10m_i8(seed: int = 4, n: int = 10_000_000, nq: int = 100_000) -> Workload:
+    """10M base + 100,000 queries, d=100 int8 with low intrinsic dimension:
+    10,000 clusters on a 16-dim sheet centred at 0 (per-coordinate std 30),
+    Zipf cluster sizes, 10% near-duplicate groups; values clipped to int8."""
+    return latent_mixture_u8(n, nq, 100, 10_000, 20.0, seed, center_std=30.0, signed=True,
+                             name=f"i8-{n // 1000}k-d100")
 
 
 def config_i8(seed: int = 3, n: int = 10_000_000, nq: int = 100_000) -> Workload:

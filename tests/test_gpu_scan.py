@@ -73,3 +73,35 @@ def test_float_brute_force_and_nn(rr):
     compare_float(g, o, r, rel=1e-5, label="bf f32")
     nn = rr.nn_dist(ix, q).cpu().numpy()
     np.testing.assert_allclose(nn, oracle.nn_dist(w.base, w.queries), rtol=1e-9, atol=1e-12)
+
+
+def test_select_radius_matches_percentile_definition(rr):
+    """rr_select_radius (count, collect, radix select on the GPU) against the
+    oracle's enumeration of all pairs: the 10,000 x 1,000 uint8 workload's
+    10^7 pairs at several percentiles (bit-exact, in one call), int8 with the
+    inner product (negative radii), and float32 (FP64 distances within 1e-9)."""
+    w = synth.config_small_u8(0)
+    ix = rr.Index.from_graph(w.base, _dummy_graph(len(w.base)), 0).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    ps = [0.001, 0.0005, 1e-7, 0.02, 1.0]
+    flush_print("select radius u8")
+    got = rr.select_radius(ix, q, ps)
+    want = [oracle.percentile_radius(w.base, w.queries, p) for p in ps]
+    np.testing.assert_array_equal(got, want)
+    assert rr.select_radius(ix, q, 0.001) == want[0]
+    wi = synth.gaussian_mixture_int(4000, 90, 100, 30, 12.0, 9, signed=True, spread=0.3)
+    ixi = rr.Index.from_graph(wi.base, _dummy_graph(4000), 0, metric="ip").to_device("cuda:0")
+    qi = torch.from_numpy(wi.queries).cuda()
+    flush_print("select radius i8 ip")
+    for p in (0.002, 0.3):
+        assert rr.select_radius(ixi, qi, p) == oracle.percentile_radius(wi.base, wi.queries, p,
+                                                                        metric="ip")
+    wf = synth.latent_mixture_f32(6000, 120, 96, 40, 0.35, 14)
+    ixf = rr.Index.from_graph(wf.base, _dummy_graph(6000), 0).to_device("cuda:0")
+    qf = torch.from_numpy(wf.queries).cuda()
+    flush_print("select radius f32")
+    for p in (0.0005, 0.01):
+        np.testing.assert_allclose(rr.select_radius(ixf, qf, p),
+                                   oracle.percentile_radius(wf.base, wf.queries, p), rtol=1e-9)
+    with pytest.raises(rr.RRError):
+        rr.select_radius(ix, q, 0.0)

@@ -143,49 +143,63 @@ def test_served_bf16_equals_batched(rr):
 
 
 def test_shared_capacity_overflow_is_retried_alone(rr, nav):
-    """A tick's greedy items, (task, id) set and result capacity are shared by
-    its queries.  With result_capacity just above the largest single result,
-    a tick holding every query overflows; the queries it cut are run again
-    in ticks of their own, so every served result still equals the oracle
-    and none is flagged truncated.  With a capacity below the largest result
-    that query alone comes back truncated, and every other one is exact."""
+    """A tick's greedy items and result arena are shared by its queries.  The
+    queries chosen here each fit the capacity alone while any two of them
+    overflow it, so every tick holding two of them overflows; the queries it
+    cut are run again in ticks of their own, and every served result equals
+    the oracle with no truncation flag.  With a capacity below the largest
+    result, that query comes back truncated even alone, and the queries that
+    fit stay exact."""
     w = nav["w"]
-    sp = rr.search_params(mode="adaptive", beam=4)
+    b = 2
+    sp = rr.search_params(mode="adaptive", beam=b)
     o = oracle.range_search(w.base, nav["adj"], nav["entry"], w.queries, nav["radii"],
-                            mode=oracle.ADAPTIVE, beam=4)
+                            mode=oracle.ADAPTIVE, beam=b)
     counts = np.diff(o.offsets)
-    big = int(counts.max())
-    assert counts.sum() > 2 * big, "the workload must overflow a shared capacity"
-    flush_print(f"serve overflow: max result {big}, total {counts.sum()}")
-    with rr.Server(nav["ix"], sp, slots=len(w.queries), result_capacity=big + 8) as srv:
-        for qi in range(len(w.queries)):
-            assert srv.submit(w.queries[qi], float(nav["radii"][qi]), qi)
+    # C: the largest result a tick can hold; chosen queries have counts in
+    # [C/2 + 5, C], so any two exceed C + 8
+    sel = None
+    for c in sorted(set(counts.tolist()), reverse=True):
+        cand = np.flatnonzero((counts >= c // 2 + 5) & (counts <= c))
+        if len(cand) >= 8:
+            sel, cap_items = cand, c
+            break
+    assert sel is not None, "the workload has too few heavy queries"
+    slots = len(sel)
+    gcap = cap_items + 8 - slots * b  # item and arena capacity = slots * b + gcap = C + 8
+    assert gcap >= 1
+    flush_print(f"serve overflow: {slots} queries with {counts[sel].min()}..{counts[sel].max()} "
+                f"results, capacity {cap_items + 8}")
+    reps = 4  # every chosen query is submitted 4 times, so ticks hold several
+    with rr.Server(nav["ix"], sp, slots=slots, result_capacity=gcap) as srv:
+        for k in range(reps):
+            for qi in sel:
+                assert srv.submit(w.queries[qi], float(nav["radii"][qi]), k * 100000 + int(qi))
         srv.drain(timeout=120.0)
-        comps = {c.tag: c for c in srv.poll(len(w.queries) + 8)}
+        comps = {c.tag: c for c in srv.poll(reps * slots + 8)}
         got = {t: srv.result(t) for t in comps}
         info = srv.info()
     flush_print(f"  retried {info['retried']}, ticks {info['ticks']}")
-    assert info["retried"] > 0
-    for qi in range(len(w.queries)):
-        oi, od = o.query(qi)
-        assert comps[qi].truncated == 0, f"q{qi} truncated"
-        np.testing.assert_array_equal(got[qi][0], oi, err_msg=f"q{qi} ids")
-        np.testing.assert_array_equal(got[qi][1].astype(np.int64), od.astype(np.int64))
+    assert info["retried"] > 0 and len(comps) == reps * slots
+    for tag, c in comps.items():
+        oi, od = o.query(tag % 100000)
+        assert c.truncated == 0, f"request {tag} truncated"
+        np.testing.assert_array_equal(got[tag][0], oi, err_msg=f"request {tag} ids")
+        np.testing.assert_array_equal(got[tag][1].astype(np.int64), od.astype(np.int64))
     # a capacity below the heaviest result: that query is truncated even alone
-    cap = big // 2
     heavy = int(np.argmax(counts))
-    with rr.Server(nav["ix"], sp, slots=8, result_capacity=cap) as srv:
-        for qi in range(len(w.queries)):
-            assert srv.submit(w.queries[qi], float(nav["radii"][qi]), qi)
+    light = np.flatnonzero((counts > 0) & (counts <= 8))[:20]
+    with rr.Server(nav["ix"], sp, slots=4, result_capacity=int(counts[heavy]) // 2) as srv:
+        for qi in [heavy] + light.tolist():
+            assert srv.submit(w.queries[qi], float(nav["radii"][qi]), int(qi))
         srv.drain(timeout=120.0)
-        comps = {c.tag: c for c in srv.poll(len(w.queries) + 8)}
+        comps = {c.tag: c for c in srv.poll(64)}
         got = {t: srv.result(t) for t in comps}
     assert comps[heavy].truncated == 1
-    for qi in range(len(w.queries)):
-        if counts[qi] <= cap // 4:
-            oi, od = o.query(qi)
-            assert comps[qi].truncated == 0, f"q{qi} truncated"
-            np.testing.assert_array_equal(got[qi][0], oi, err_msg=f"q{qi} ids")
+    for qi in light:
+        oi, od = o.query(int(qi))
+        assert comps[qi].truncated == 0, f"q{qi} truncated"
+        np.testing.assert_array_equal(got[qi][0], oi, err_msg=f"q{qi} ids")
 
 
 def test_server_errors(rr, nav):
