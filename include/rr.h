@@ -249,6 +249,39 @@ rr_status rr_range_search(const rr_index *idx, const void *queries_dev, int64_t 
                           const rr_search_params *sp, const rr_allocator *alloc, void *stream,
                           rr_results **out);
 
+/* Bytes of the per-device scratch array behind rr_range_search_noalloc. */
+#define RR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid it):
+ * rr_range_search (modes RR_PLAIN, RR_ES, RR_ADAPTIVE; RR_DOUBLING is
+ * refused) with every internal buffer placed in a fixed scratch array of
+ * RR_NOALLOC_SCRATCH_BYTES that the library holds on each device, and the
+ * CSR result written straight into the caller's buffers:
+ *   offsets_dev  nq + 1 int64 (always complete: offsets_dev[nq] = total);
+ *   ids_dev, dists_dev  the first `capacity` entries of the CSR lists (int32
+ *                ids; int32 or float32 distances as in rr_results_copy);
+ *                entries at positions >= capacity are not written, so the
+ *                caller compares offsets_dev[nq] with capacity;
+ *   stats_dev    optional (NULL): nq rr_query_stats, device memory.
+ * The (task, id) set of the greedy phase is the hash table here (no n-bit
+ * membership bitmaps), and with result_capacity = 0 the greedy phase gets
+ * the largest capacity that fits the array; a request that does not fit
+ * (nq x beam entries, the padded queries and the greedy buffers) fails with
+ * RR_EINVAL before anything is launched.  Capacity overflows inside the
+ * search set `truncated` in the stats, as in rr_range_search.
+ * All work is enqueued on `stream`; nothing allocates, frees or
+ * synchronizes.  Every call on a device shares that device's array, which
+ * keeps the last call's contents: calls that overlap on one device (other
+ * streams, other threads) race and must be serialized by the caller.
+ * Errors: those of rr_range_search (argument checks), RR_EINVAL as above,
+ * RR_EHIP. */
+rr_status rr_range_search_noalloc(const rr_index *idx, const void *queries_dev, int64_t nq,
+                                  double radius, const double *radius_dev,
+                                  const rr_search_params *sp, int32_t *ids_dev, void *dists_dev,
+                                  int64_t capacity, int64_t *offsets_dev,
+                                  rr_query_stats *stats_dev, void *stream);
+
 /* Exact range search by a dense scan (Definition 2.1), for ground truth.
  * Same arguments and result layout as rr_range_search. */
 rr_status rr_brute_force(const rr_index *idx, const void *queries_dev, int64_t nq,

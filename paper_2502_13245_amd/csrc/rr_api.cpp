@@ -854,6 +854,116 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     return RR_OK;
 }
 
+// --------------------------------------------------------------------------
+// range search without allocation: every buffer in a fixed scratch array
+// --------------------------------------------------------------------------
+
+// The scratch array of rr_range_search_noalloc: one copy per device, held
+// by the loaded code object until the process ends.  In host code `scratch`
+// only names the symbol; its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is ever handed to kernels or
+// copies.
+static __device__ __align__(256) uint8_t scratch[RR_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[64] = {nullptr};
+
+static rr_status scratch_address(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(RR_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(RR_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return RR_OK;
+}
+
+extern "C" rr_status rr_range_search_noalloc(const rr_index *ix, const void *queries_dev, int64_t nq,
+                                             double radius, const double *radius_dev,
+                                             const rr_search_params *sp, int32_t *ids_dev,
+                                             void *dists_dev, int64_t capacity,
+                                             int64_t *offsets_dev, rr_query_stats *stats_dev,
+                                             void *stream) {
+    if (!ix || !sp) return fail(RR_EINVAL, "index or params are NULL");
+    if (!ix->on_device) return fail(RR_ESTATE, "index is not on the device (rr_index_to_device)");
+    if (nq < 0 || nq >= (1ll << 31)) return fail(RR_EINVAL, "nq out of range");
+    if (nq > 0 && !queries_dev) return fail(RR_EINVAL, "queries are NULL");
+    if (!offsets_dev) return fail(RR_EINVAL, "offsets are NULL");
+    if (capacity < 0) return fail(RR_EINVAL, "capacity < 0");
+    if (capacity > 0 && (!ids_dev || !dists_dev)) return fail(RR_EINVAL, "output buffers are NULL");
+    if (!radius_dev && check_radius(radius) != RR_OK) return RR_EINVAL;
+    if (sp->mode == RR_DOUBLING)
+        return fail(RR_EINVAL, "doubling search needs per-wave memory beyond the scratch array; "
+                               "use rr_range_search");
+    SearchCfg cfg{};
+    DevIndex view;
+    int32_t qrow = 0;
+    bool greedy = false;
+    rr_status st = prepare_search(ix, sp, &cfg, &view, &qrow, &greedy);
+    if (st != RR_OK) return st;
+    // capacities as in rr_range_search, but no membership bitmaps (n / 8
+    // bytes per expanding query): the (task, id) set is the hash table, and
+    // with result_capacity = 0 the greedy capacity is the largest that fits
+    const int64_t nb = nq * (int64_t)sp->beam;
+    auto layout = [&](int64_t gcap) {
+        const int64_t item_cap = greedy ? nb + gcap : 0;
+        const int64_t hash_cap = greedy ? next_pow2(std::max<int64_t>(4 * item_cap, 1024)) : 0;
+        return layout_bufs(ix, nq, greedy, nb + gcap, item_cap, hash_cap, qrow, 0);
+    };
+    const size_t room = RR_NOALLOC_SCRATCH_BYTES;
+    int64_t gcap = 0;
+    if (greedy) {
+        if (sp->result_capacity > 0) {
+            gcap = sp->result_capacity;
+        } else {
+            int64_t lo = 0, hi = 1 << 21;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) / 2;
+                if (layout(mid).total <= room) lo = mid;
+                else hi = mid - 1;
+            }
+            gcap = lo;
+        }
+    }
+    const BufLayout L = layout(gcap);
+    if (L.total > room || (greedy && gcap < 1))
+        return fail(RR_EINVAL,
+                    "rr_range_search_noalloc: %lld queries at beam %d (result capacity %lld) need "
+                    "%zu bytes of scratch; the library holds %zu per device",
+                    (long long)nq, sp->beam, (long long)gcap, L.total, room);
+    void *base = nullptr;
+    st = scratch_address(&base);
+    if (st != RR_OK) return st;
+    SearchBufs sb;
+    int64_t *offsets = nullptr;
+    void *scan_tmp = nullptr;
+    bind_bufs(L, (uint8_t *)base, sp, sb, &offsets, &scan_tmp, view.deg);
+    hipStream_t s = (hipStream_t)stream;
+    // the array keeps the previous call's contents: fill what must start
+    // cleared (fill kernels, not memset nodes, so the call can be captured)
+    const int cus = device_cus();
+    HIP_TRY(launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s));
+    if (greedy) {
+        HIP_TRY(launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s));
+        HIP_TRY(launch_fill_u64(sb.hash, sb.hash_cap, ~0ull, s));
+    }
+    HIP_TRY(launch_prep_queries(view, queries_dev, nq, radius, radius_dev, cfg, sb, s));
+    HIP_TRY(launch_beam(view, nq, cfg, sb, cus, s));
+    if (greedy) HIP_TRY(launch_greedy(view, nq, cfg, sb, cus, s));
+    HIP_TRY(launch_results_copy(ix->dtype, sp->precision, view, sb.qpad, nq, sb.res_off, sb.res_cnt,
+                                sb.arena_ids, sb.arena_dists, ids_dev, dists_dev, offsets_dev,
+                                scan_tmp, s, capacity));
+    if (stats_dev && nq > 0)
+        HIP_TRY(hipMemcpyAsync(stats_dev, sb.stats, (size_t)nq * sizeof(rr_query_stats),
+                               hipMemcpyDeviceToDevice, s));
+    return RR_OK;
+}
+
 extern "C" rr_status rr_es_profile(const rr_index *ix, const void *queries_dev, int64_t nq,
                                    double radius, const double *radius_dev, int32_t beam,
                                    int32_t step, double *metrics_host, int8_t *flags_host,

@@ -148,6 +148,8 @@ SIGNATURES = {
     "rr_index_free": (None, [_VP]),
     "rr_range_search": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, C.POINTER(SearchParams),
                                   C.POINTER(Allocator), _VP, C.POINTER(_VP)]),
+    "rr_range_search_noalloc": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP,
+                                          C.POINTER(SearchParams), _VP, _VP, _I64, _VP, _VP, _VP]),
     "rr_brute_force": (C.c_int, [_VP, _VP, _I64, C.c_double, _VP, C.POINTER(Allocator), _VP,
                                  C.POINTER(_VP)]),
     "rr_nn_dist": (C.c_int, [_VP, _VP, _I64, _VP, _VP]),
@@ -487,6 +489,42 @@ def range_search(index: Index, queries, radius, params: SearchParams | None = No
                  with_stats=True, **kw) -> Results:
     """range_search(queries, radius, params) -> (ids, dists, offsets) + per-query counters."""
     return range_search_async(index, queries, radius, params, stream, **kw).fetch(with_stats, stream)
+
+
+def range_search_noalloc(index: Index, queries, radius, capacity, params: SearchParams | None = None,
+                         stream=None, with_stats=True, **kw):
+    """rr_range_search_noalloc: the library allocates nothing; the caller's
+    buffers (allocated here with torch) receive the CSR result.  Returns
+    (offsets, ids, dists, stats): offsets int64 [nq + 1] (complete), ids and
+    dists the first `capacity` entries, stats a device tensor of nq
+    rr_query_stats records as raw bytes (or None)."""
+    import torch
+    if index.device is None:
+        raise RRError(RR_ESTATE, "index is not on the device")
+    sp = params if params is not None else search_params(**kw)
+    q = queries.contiguous()
+    nq = q.shape[0] if q.dim() == 2 else 0
+    r0, rdev, keep = _radius_args(radius, nq, q.device)
+    dev = q.device
+    dt = index.info()["dtype"]
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=dev)
+    dists = torch.empty(max(int(capacity), 1), dtype=torch.float32 if dt == F32 else torch.int32,
+                        device=dev)
+    stats = (torch.empty(max(nq, 1) * C.sizeof(QueryStats), dtype=torch.uint8, device=dev)
+             if with_stats else None)
+    _check(lib().rr_range_search_noalloc(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev,
+                                         C.byref(sp), C.c_void_p(ids.data_ptr()),
+                                         C.c_void_p(dists.data_ptr()), int(capacity),
+                                         C.c_void_p(offsets.data_ptr()),
+                                         C.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                         _stream_handle(stream)))
+    return offsets, ids, dists, stats
+
+
+def stats_from_bytes(raw) -> np.ndarray:
+    """Per-query counters from the raw bytes of nq rr_query_stats records."""
+    return np.frombuffer(raw.cpu().numpy().tobytes(), dtype=STATS_DTYPE)
 
 
 def brute_force_async(index: Index, queries, radius, stream=None) -> PendingResults:
