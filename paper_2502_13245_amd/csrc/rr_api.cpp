@@ -732,7 +732,10 @@ rr_status rr::prepare_search(const rr_index *ix, const rr_search_params *sp, Sea
     int64_t bcap = sp->beam;
     if (doubling)
         while (bcap < sp->max_beam && bcap < (1 << 20)) bcap *= 2;
-    const size_t per_wave = (size_t)(ix->dtype == RR_F32 ? 24 : 16) * bcap + 64 * 12 + cs * 4 + 128;
+    // LDS per wave: B (keys and ids; doubling keeps two copies, the beam
+    // kernel merges in place), 64 candidates, the visited cache
+    const size_t per_wave = (size_t)(doubling ? 2 : 1) * (ix->dtype == RR_F32 ? 12 : 8) * bcap +
+                            64 * 12 + cs * 4 + 128;
     const size_t lds_cap = 160 * 1024;
     if (per_wave > lds_cap) {
         if (doubling)

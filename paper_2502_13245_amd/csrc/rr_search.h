@@ -684,6 +684,15 @@ struct BeamArgs {
 
 template <typename D>
 __host__ __device__ inline int32_t beam_lds_bytes(int32_t bcap, int32_t cs) {
+    // the beam kernel merges in place: one copy of B
+    auto al = [](int64_t x) { return (int32_t)((x + 15) & ~15ll); };
+    return al((int64_t)bcap * sizeof(D)) + al(64 * sizeof(D)) + al((int64_t)bcap * 4) +
+           al(64 * 4) + al((int64_t)cs * 4);
+}
+
+// the doubling kernel double-buffers its beam
+template <typename D>
+__host__ __device__ inline int32_t doubling_lds_bytes(int32_t bcap, int32_t cs) {
     auto al = [](int64_t x) { return (int32_t)((x + 15) & ~15ll); };
     return al((int64_t)bcap * sizeof(D)) * 2 + al(64 * sizeof(D)) + al((int64_t)bcap * 4) * 2 +
            al(64 * 4) + al((int64_t)cs * 4);
@@ -700,14 +709,12 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
     auto al = [](int64_t x) { return (int64_t)((x + 15) & ~15ll); };
     const int bcap = a.bcap;
     const int cs = a.cfg.cache_slots;
-    D *bdA = (D *)my;
-    D *bdB = (D *)(my + al((int64_t)bcap * sizeof(D)));
-    D *cd = (D *)(my + 2 * al((int64_t)bcap * sizeof(D)));
-    uint8_t *p2 = my + 2 * al((int64_t)bcap * sizeof(D)) + al(64 * sizeof(D));
-    uint32_t *biA = (uint32_t *)p2;
-    uint32_t *biB = (uint32_t *)(p2 + al((int64_t)bcap * 4));
-    uint32_t *ci = (uint32_t *)(p2 + 2 * al((int64_t)bcap * 4));
-    uint32_t *htab = (uint32_t *)(p2 + 2 * al((int64_t)bcap * 4) + al(64 * 4));
+    D *const bd = (D *)my;
+    D *cd = (D *)(my + al((int64_t)bcap * sizeof(D)));
+    uint8_t *p2 = my + al((int64_t)bcap * sizeof(D)) + al(64 * sizeof(D));
+    uint32_t *const bi = (uint32_t *)p2;
+    uint32_t *ci = (uint32_t *)(p2 + al((int64_t)bcap * 4));
+    uint32_t *htab = (uint32_t *)(p2 + al((int64_t)bcap * 4) + al(64 * 4));
     const uint32_t cs_mask = (uint32_t)cs - 1u;
     const DevIndex &ix = a.ix;
     const SearchCfg &cfg = a.cfg;
@@ -729,8 +736,6 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
         wave_sync();
 
         bool ovf = false;
-        D *bd = bdA, *bdo = bdB;
-        uint32_t *bi = biA, *bio = biB;
         int nB = 1;
         int visits = 0, evals = 1;
         int edges = 0; // adjacency entries read by the visits (sum of out-degrees)
@@ -855,37 +860,44 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                 ci[r2] = myi;
             }
             wave_sync();
-            // merge: B entry i moves to i + #(survivors < B[i]); survivor j to j + lb_j
+            // merge in place: B entry i moves to i + #(survivors < B[i]) >= i,
+            // survivor j to j + lb_j.  Chunks of 64 entries are moved from the
+            // top down: a chunk's entries land at or above its own start, where
+            // every entry was read already, so nothing unread is overwritten.
             const int nB2 = min(b, nB + k2);
             int ipnew = ip;
-            for (int i = lane; i < nB; i += 64) {
-                const D di = bd[i];
-                const uint32_t ii = bi[i];
-                const int np = i + lower_bound_key(cd, ci, k2, di, ii & RR_IDMASK);
+            // entries below the first survivor's position keep their place
+            const int lb_first = k2 > 0 ? __shfl(lb, __ffsll((long long)km) - 1) : nB;
+            for (int base = (nB - 1) & ~63; base >= (lb_first & ~63); base -= 64) {
+                const int i = base + lane;
+                D di = D(0);
+                uint32_t ii = 0u;
+                int np = 1 << 30;
+                if (i < nB) {
+                    di = bd[i];
+                    ii = bi[i];
+                    np = i + lower_bound_key(cd, ci, k2, di, ii & RR_IDMASK);
+                }
+                wave_sync();
                 if (np < b) {
-                    bdo[np] = di;
-                    bio[np] = ii;
+                    bd[np] = di;
+                    bi[np] = ii;
                 }
                 if (i == ip) ipnew = np;
             }
+            wave_sync();
             ipnew = __shfl(ipnew, ip & 63);
             int firstnew = 1 << 30;
             if (keep) {
                 const int np = r2 + lb;
                 if (np < b) {
-                    bdo[np] = myd;
-                    bio[np] = myi;
+                    bd[np] = myd;
+                    bi[np] = myi;
                 }
                 if (r2 == 0) firstnew = np;
             }
             if (k2 > 0) firstnew = __shfl(firstnew, __ffsll((long long)km) - 1);
             wave_sync();
-            D *td = bd;
-            bd = bdo;
-            bdo = td;
-            uint32_t *ti = bi;
-            bi = bio;
-            bio = ti;
             nB = nB2;
             cursor = min(ipnew + 1, firstnew);
         }
@@ -1997,7 +2009,7 @@ static hipError_t run_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &
     a.sb = sb;
     a.nq = nq;
     a.bcap = cfg.bcap;
-    a.lds_per_wave = beam_lds_bytes<D>(cfg.bcap, cfg.cache_slots);
+    a.lds_per_wave = doubling_lds_bytes<D>(cfg.bcap, cfg.cache_slots);
     a.s_pool = (uint8_t *)s_pool;
     a.s_cap = s_cap;
     const int waves = cfg.waves;

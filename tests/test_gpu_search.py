@@ -52,6 +52,19 @@ def test_plain_bit_exact(rr, small_u8, beam):
     compare_exact(g, o, label=f"plain b={beam}")
 
 
+@pytest.mark.parametrize("mode,beam,cache", [("plain", 512, 2048), ("plain", 2048, 512),
+                                             ("es", 1024, 1024), ("plain", 4096, 4096)])
+def test_wide_beam_bit_exact(rr, small_u8, mode, beam, cache):
+    """Beams of hundreds to thousands of entries (the in-place merge moves
+    many 64-entry chunks per visit; small caches forget ids)."""
+    flush_print(f"{mode} beam={beam} cache={cache}")
+    kw = dict(es_visit_limit=10, es_radius=small_u8["r"]) if mode == "es" else {}
+    g = rr.range_search(small_u8["ix"], small_u8["q"], small_u8["r"], mode=mode, beam=beam,
+                        cache_slots=cache, **kw)
+    o = _orc(small_u8, mode=oracle.ES if mode == "es" else oracle.PLAIN, beam=beam, **kw)
+    compare_exact(g, o, label=f"{mode} b={beam}")
+
+
 @pytest.mark.parametrize("vl,esr_scale", [(1, 1.0), (5, 1.0), (20, 1.5)])
 def test_early_stop_bit_exact(rr, small_u8, vl, esr_scale):
     esr = small_u8["r"] * esr_scale
