@@ -174,14 +174,14 @@ __device__ __forceinline__ void gset_insert2(unsigned long long *tab, int64_t ca
 // well); later tasks fall back to the hash table.
 
 // wave-wide: clear task t's bitmap (all lanes call this; a no-op for tasks
-// that use the hash table).  The fence orders the clearing stores before
-// the wave's atomic updates of the same words.
+// that use the hash table).  The set is first updated by the greedy kernel,
+// so the kernel boundary orders these stores before those updates and the
+// wave does not wait for them.
 __device__ __forceinline__ void tset_clear(const SearchBufs &sb, int64_t t) {
     if (t >= sb.bm_tasks) return;
     uint4 *p = reinterpret_cast<uint4 *>(sb.bm + t * sb.bm_words);
     const uint4 z = make_uint4(0u, 0u, 0u, 0u);
     for (int64_t i = lane_id(); i < sb.bm_words / 4; i += 64) p[i] = z;
-    __threadfence();
 }
 
 // add (t, id) to the set (seeds: known not to be present)
@@ -1007,7 +1007,6 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
             bool full = false;
             int written = 0;
             O *idist = (O *)a.sb.item_dist;
-            const int64_t hmask = a.sb.hash_cap - 1;
             if constexpr (dapprox(DTYPE)) {
                 for (int base = 0; base < cH; base += 64) {
                     const int i = base + lane;
@@ -1030,7 +1029,6 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                         const uint32_t id = bi[i] & RR_IDMASK;
                         a.sb.item_key[o] = ((unsigned long long)(uint32_t)t << 32) | id;
                         idist[o] = dx;
-                        if (expand) tset_add(a.sb, hmask, t, id, full);
                     }
                     const int mw = __popcll(__ballot(wr));
                     written += mw;
@@ -1050,7 +1048,6 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
                     const uint32_t id = bi[i] & RR_IDMASK;
                     a.sb.item_key[o] = ((unsigned long long)(uint32_t)t << 32) | id;
                     idist[o] = (O)bd[i];
-                    tset_add(a.sb, hmask, t, id, full);
                 }
                 written = (int)max((int64_t)0, min((int64_t)cN, a.sb.item_cap - off));
             }
@@ -1612,6 +1609,30 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
     int lvl = 0;
     bool grouped = true;
     const int64_t regroup_min = 512 * (int64_t)gridDim.x;
+    {
+        // level 0 (the beam kernel's seeds, N of each expanding task) joins
+        // the (task, id) set before any expansion.  The beam kernel cleared
+        // the bitmaps; the kernel boundary orders those stores before these
+        // updates.
+        const int64_t c0 = min((int64_t)__hip_atomic_load(&a.sb.level_cnt[0], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT),
+                               a.sb.item_cap);
+        bool full = false;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c0;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const unsigned long long key = a.sb.item_key[i];
+            const int32_t t = (int32_t)(key >> 32);
+            if (t < 0 || t >= ntasks || !a.sb.task_expand[t]) continue;
+            bool f = false;
+            tset_add(a.sb, hmask, t, (uint32_t)key, f);
+            if (f) {
+                a.sb.task_trunc[t] = 1;
+                full = true;
+            }
+        }
+        if (__ballot(full) && lane == 0) atomicOr(&a.sb.counters[CTR_OVERFLOW], 8ull);
+        grid_sync();
+    }
     for (; lvl < a.sb.max_levels - 1; ++lvl) {
         const int64_t cnt = (int64_t)__hip_atomic_load(&a.sb.level_cnt[lvl], __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);

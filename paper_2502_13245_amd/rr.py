@@ -276,11 +276,15 @@ class Index:
         self._alloc = None
         self.device = None
 
+    def free(self):
+        """Release the host and device copies now (the index is unusable after)."""
+        if self._h and self._h.value:
+            lib().rr_index_free(self._h)
+            self._h = C.c_void_p(0)
+
     def __del__(self):
         try:
-            if self._h and self._h.value:
-                lib().rr_index_free(self._h)
-                self._h = C.c_void_p(0)
+            self.free()
         except Exception:
             pass
 
