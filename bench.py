@@ -303,9 +303,18 @@ def build_index(rr, base, args, label, **bp):
 
 
 def only_run(rr, ix, q, args):
-    """Profiling mode: the setting from --choice, --steps calls, nothing else."""
+    """Profiling mode: the setting from --choice, --steps calls, nothing else
+    (after the --copy-ref-mb reference copies, if asked)."""
     import torch
     ch = json.load(open(args.choice))
+    if args.copy_ref_mb:
+        src = torch.empty(args.copy_ref_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy reference: {args.copy_ref_mb} MiB device-to-device x3")
     for _ in range(args.steps):
         rr.range_search(ix, q, ch["radius"], mode=ch["mode"], beam=ch["beam"], with_stats=False,
                         **ch["kw"])

@@ -353,6 +353,7 @@ typedef struct {
     double ms;            /* median time of one search call with the choice  */
     double recall;        /* range recall of the choice against `truth`      */
     int32_t met_target;   /* 1 if recall >= target was reached                */
+    int32_t es_dropped;   /* 1 if the early stop of *inout was switched off   */
 } rr_tune_report;
 
 /* Pick the search parameters of a workload.  `truth` is an exact result of
@@ -364,7 +365,11 @@ typedef struct {
  * beam replaces a narrower one only if it is at least 3% faster), then the
  * fastest kernel shape for that beam (shapes never change results).  Each
  * setting is timed as the median of `reps` calls with HIP events on
- * `stream`.  If no beam reaches the target the highest-recall one is kept
+ * `stream`.  If no beam reaches the target with the early stop of *inout
+ * (an early stop can end searches that would still reach the ball, at every
+ * beam), the ladder runs again without it; if that does better, the choice
+ * has es_enable = 0 and es_dropped = 1 (rr_tune_early_stop can then pick a
+ * new one).  If no beam reaches the target the highest-recall one is kept
  * and met_target = 0.  Synchronizes.  Errors: those of rr_range_search. */
 rr_status rr_autotune(const rr_index *idx, const void *queries_dev, int64_t nq, double radius,
                       const double *radius_dev, const rr_results *truth, double target_recall,

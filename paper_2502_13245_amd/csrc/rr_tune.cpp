@@ -126,29 +126,58 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
     sp.cache_slots = 0;
     int tried = 0, best_beam = -1, top_beam = ladder[0];
     double best_ms = 0, best_rec = -1, top_rec = -1;
-    int past = 0;
-    for (int b : ladder) {
-        sp.beam = b;
-        Csr found;
-        double ms = 0;
-        st = time_setting(ix, queries_dev, nq, radius, radius_dev, sp, reps, alloc, stream, &ms, &found);
-        if (st == RR_EINVAL) break; // beyond what this build's LDS allows
-        if (st != RR_OK) return st;
-        ++tried;
-        const double rec = recall(gt, found, nq);
-        if (rec > top_rec) {
-            top_rec = rec;
-            top_beam = b;
-        }
-        if (rec >= target_recall) {
-            // a wider beam must be clearly faster (3%) to replace a narrower
-            // one: timing noise alone should not move the choice between runs
-            if (best_beam < 0 || ms < 0.97 * best_ms) {
-                best_beam = b;
-                best_ms = ms;
-                best_rec = rec;
+    auto run_ladder = [&]() -> rr_status {
+        best_beam = -1;
+        top_beam = ladder[0];
+        best_ms = 0;
+        best_rec = -1;
+        top_rec = -1;
+        int past = 0;
+        for (int b : ladder) {
+            sp.beam = b;
+            Csr found;
+            double ms = 0;
+            rr_status s2 =
+                time_setting(ix, queries_dev, nq, radius, radius_dev, sp, reps, alloc, stream, &ms, &found);
+            if (s2 == RR_EINVAL) return tried ? RR_OK : s2; // beyond what this build's LDS allows
+            if (s2 != RR_OK) return s2;
+            ++tried;
+            const double rec = recall(gt, found, nq);
+            if (rec > top_rec) {
+                top_rec = rec;
+                top_beam = b;
             }
-            if (++past >= 2) break; // two settings past the target: larger beams only cost more
+            if (rec >= target_recall) {
+                // a wider beam must be clearly faster (3%) to replace a narrower
+                // one: timing noise alone should not move the choice between runs
+                if (best_beam < 0 || ms < 0.97 * best_ms) {
+                    best_beam = b;
+                    best_ms = ms;
+                    best_rec = rec;
+                }
+                if (++past >= 2) break; // two settings past the target: larger beams only cost more
+            }
+        }
+        return RR_OK;
+    };
+    st = run_ladder();
+    if (st != RR_OK) return st;
+    // an early stop tuned for another workload can cap recall at every beam
+    // (it ends searches that would still reach the ball): the ladder then runs
+    // again without it, and the choice carries es_enable = 0
+    bool es_dropped = false;
+    if (best_beam < 0 && sp.es_enable) {
+        const int kb = top_beam;
+        const double kr = top_rec;
+        sp.es_enable = 0;
+        st = run_ladder();
+        if (st != RR_OK) return st;
+        if (best_beam >= 0 || top_rec > kr) {
+            es_dropped = true;
+        } else {
+            sp.es_enable = inout->es_enable;
+            top_beam = kb;
+            top_rec = kr;
         }
     }
     if (tried == 0) return st; // not even the smallest beam could run
@@ -177,8 +206,10 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
     inout->beam = best_beam;
     inout->waves_per_group = best_w;
     inout->cache_slots = best_c;
+    if (es_dropped) inout->es_enable = 0;
     if (report) {
         report->tried = tried;
+        report->es_dropped = es_dropped ? 1 : 0;
         report->beam = best_beam;
         report->waves_per_group = best_w;
         report->cache_slots = best_c;

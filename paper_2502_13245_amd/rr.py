@@ -79,7 +79,7 @@ class BatchStats(C.Structure):
 class TuneReport(C.Structure):
     _fields_ = [("tried", C.c_int32), ("beam", C.c_int32), ("waves_per_group", C.c_int32),
                 ("cache_slots", C.c_int32), ("ms", C.c_double), ("recall", C.c_double),
-                ("met_target", C.c_int32)]
+                ("met_target", C.c_int32), ("es_dropped", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -159,3 +159,66 @@ def test_metric_is_saved_and_old_files_load_as_l2(tmp_path):
     with pytest.raises(rr.RRError):
         lib = rr.lib()
         rr._check(lib.rr_index_set_metric(ix._h, 7))
+
+
+# every ctypes mirror of a header struct, with the C names of fields whose
+# Python names differ (`lambda` is a Python keyword)
+_STRUCTS = {"rr_allocator": ("Allocator", {}), "rr_build_params": ("BuildParams", {}),
+            "rr_search_params": ("SearchParams", {"lam": "lambda"}),
+            "rr_query_stats": ("QueryStats", {}), "rr_batch_stats": ("BatchStats", {}),
+            "rr_tune_report": ("TuneReport", {}), "rr_es_tune_report": ("ESTuneReport", {}),
+            "rr_server_config": ("ServerConfig", {}), "rr_completion": ("Completion", {}),
+            "rr_server_info": ("ServerInfo", {})}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and every field offset of the binding's ctypes structures equal
+    what a C compiler makes of include/rr.h, so a field added on one side
+    only fails here instead of shifting the fields after it."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rr.h"', "int main(void) {"]
+    for cname, (pyname, ren) in _STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in getattr(rr, pyname)._fields_:
+            cf = ren.get(f, f)
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        s, f, v = ln.split()
+        got[(s, f)] = int(v)
+    for cname, (pyname, _) in _STRUCTS.items():
+        cls = getattr(rr, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+    # and the same fields in the same order (a trailing field missing on one
+    # side can hide in tail padding)
+    hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "rr.h")).read(), flags=re.S)
+    for body, cname in re.findall(r"typedef struct\s*\{(.*?)\}\s*(rr_\w+)\s*;", hdr, flags=re.S):
+        if cname not in _STRUCTS:
+            continue
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            m = re.search(r"\(\*\s*(\w+)\)", decl)
+            if m:  # a function pointer
+                names.append(m.group(1))
+                continue
+            for part in decl.split(","):  # `int64_t a, b` declares two fields
+                names.append(re.search(r"(\w+)\s*(\[[^\]]*\])?\s*$", part).group(1))
+        pyname, ren = _STRUCTS[cname]
+        assert names == [ren.get(f, f) for f, _ in getattr(rr, pyname)._fields_], cname
