@@ -150,16 +150,24 @@ constexpr int LEVEL_CLOCKS = 64;
 // their capacity, OVERFLOW_BARRIER a grid barrier that gave up waiting
 constexpr unsigned long long OVERFLOW_BARRIER = 256ull;
 
+// Each counter sits on its own 128-byte line: returning atomics on one
+// address (or one line) are serialized at about 12 ns each on MI355X, so
+// counters that many waves update in the same kernel (the query queue, the
+// arena cursor, the task count) must not share a line.
+constexpr int CTR_STRIDE = 16;
+// the beam kernel's queue: stripe s hands out work items s, s + QSTRIPES, ...
+constexpr int QSTRIPES = 16;
 enum {
-    CTR_QUEUE = 0,        // next query to take
-    CTR_ARENA = 1,        // arena cursor
-    CTR_TASKS = 2,        // number of expansion tasks
-    CTR_OVERFLOW = 3,     // non-zero: some capacity was exceeded
-    CTR_LEVELS = 4,       // levels run by the greedy phase
-    CTR_BARRIER = 5,      // arrivals at the greedy kernel's grid barrier
-    CTR_GREEDY_ITEMS = 6, // items the greedy phase expanded (seeds included)
-    CTR_SET_OPS = 7,      // greedy phase: updates sent to the global (task, id) set
-    CTR_COUNT = 8
+    CTR_QUEUE = 0 * CTR_STRIDE,        // next query to take
+    CTR_ARENA = 1 * CTR_STRIDE,        // arena cursor
+    CTR_TASKS = 2 * CTR_STRIDE,        // number of expansion tasks
+    CTR_OVERFLOW = 3 * CTR_STRIDE,     // non-zero: some capacity was exceeded
+    CTR_LEVELS = 4 * CTR_STRIDE,       // levels run by the greedy phase
+    CTR_BARRIER = 5 * CTR_STRIDE,      // arrivals at the greedy kernel's grid barrier
+    CTR_GREEDY_ITEMS = 6 * CTR_STRIDE, // items the greedy phase expanded (seeds included)
+    CTR_SET_OPS = 7 * CTR_STRIDE,      // greedy phase: updates sent to the global (task, id) set
+    CTR_QSTRIPE = 8 * CTR_STRIDE,      // the beam kernel's striped query queue (QSTRIPES lines)
+    CTR_COUNT = (8 + 16) * CTR_STRIDE
 };
 
 // kernel launchers (rr_kernels.hip)

@@ -721,11 +721,33 @@ __global__ __launch_bounds__(512) void k_beam(BeamArgs a) {
     const int R = ix.R;
     const int b = cfg.beam;
 
+    // The work queue is striped over QSTRIPES counters on separate lines (one
+    // counter would serialize every fetch): stripe s hands out work items s,
+    // s + QSTRIPES, s + 2 QSTRIPES, ...  A wave starts at its own stripe and
+    // moves to the next one when a stripe runs dry; a stripe never refills, so
+    // a wave that has passed every stripe is done.  A relaxed load skips
+    // stripes already seen dry without an atomic.
+    int stripe = (int)(((int64_t)blockIdx.x * (blockDim.x >> 6) + wid) % QSTRIPES);
+    int dry = 0;
     for (;;) {
-        int64_t wk = 0;
-        if (lane == 0) wk = (int64_t)atomicAdd(&a.sb.counters[CTR_QUEUE], 1ull);
-        wk = __shfl(wk, 0);
-        if (wk >= a.nwork) break;
+        int64_t wk = -1;
+        while (dry < QSTRIPES) {
+            int64_t k = -1;
+            if (lane == 0) {
+                unsigned long long *c = &a.sb.counters[CTR_QSTRIPE + stripe * CTR_STRIDE];
+                const unsigned long long seen =
+                    __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((int64_t)stripe + (int64_t)seen * QSTRIPES < a.nwork) k = (int64_t)atomicAdd(c, 1ull);
+            }
+            k = __shfl(k, 0);
+            if (k >= 0 && (int64_t)stripe + k * QSTRIPES < a.nwork) {
+                wk = (int64_t)stripe + k * QSTRIPES;
+                break;
+            }
+            stripe = stripe + 1 == QSTRIPES ? 0 : stripe + 1;
+            ++dry;
+        }
+        if (wk < 0) break;
         const int64_t q = a.qlist ? (int64_t)a.qlist[wk] : wk;
 
         const QThresh th = a.sb.qth[q];
@@ -1595,7 +1617,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
     D *qd = L.cd[wid];        // their distances once evaluated
     const int64_t hmask = a.sb.hash_cap - 1;
     const int64_t ntasks = (int64_t)a.sb.counters[CTR_TASKS];
-    uint32_t set_ops = 0; // global set updates of this lane (summed over the wave at the end)
+    uint32_t set_ops = 0; // global set updates of the wave (a wave-uniform count)
     // phase timestamps (block 0, one lane): kernel start, then per level the
     // ends of expansion, segment scan and regroup
     const bool clock_lane = blockIdx.x == 0 && threadIdx.x == 0;
@@ -1774,7 +1796,7 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
             const bool cB = okB && !wg_cache_seen(L.cache, keyB);
             P.bA = cA && tA < a.sb.bm_tasks;
             P.bB = cB && tB < a.sb.bm_tasks;
-            set_ops += (cA ? 1u : 0u) + (cB ? 1u : 0u);
+            set_ops += (uint32_t)(__popcll(__ballot(cA)) + __popcll(__ballot(cB)));
             P.oA = ~0u;
             P.oB = ~0u;
             if (P.bA) P.oA = atomicOr(&a.sb.bm[(int64_t)tA * a.sb.bm_words + ((uint32_t)fA >> 5)],
@@ -1890,10 +1912,14 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
         }
         base = next_base;
     }
-    {
-        const unsigned long long w_ops = group_sum<64>((unsigned long long)set_ops);
-        if (lane == 0 && w_ops) atomicAdd(&a.sb.counters[CTR_SET_OPS], w_ops);
-    }
+    // the set-operation count: one global atomic per workgroup (one per wave,
+    // all arriving together at the end, would serialize on the counter)
+    __syncthreads();
+    if (threadIdx.x == 0) L.wg_base = 0ull;
+    __syncthreads();
+    if (lane == 0 && set_ops) atomicAdd(&L.wg_base, (unsigned long long)set_ops);
+    __syncthreads();
+    if (threadIdx.x == 0 && L.wg_base) atomicAdd(&a.sb.counters[CTR_SET_OPS], L.wg_base);
     // move the levels that were expanded as emitted into the item arrays (the
     // kernel's end orders these writes before the finalisation)
     {
