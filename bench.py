@@ -857,9 +857,8 @@ def main():
 
     def roof(kernel, nbytes, ms, tkey):
         ach = nbytes / (ms * 1e-3) / 1e9
-        t = None
-        if traffic and tkey in traffic:
-            t = traffic[tkey]
+        # the record's keys are the profiler's kernel names, arguments included
+        t = next((v for k, v in (traffic or {}).items() if k.startswith(tkey)), None)
         return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=t, kernel=kernel,
                     bytes_per_launch=int(nbytes), avg_ms=round(ms, 4))

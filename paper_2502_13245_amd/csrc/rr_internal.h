@@ -157,6 +157,9 @@ constexpr unsigned long long OVERFLOW_BARRIER = 256ull;
 constexpr int CTR_STRIDE = 16;
 // the beam kernel's queue: stripe s hands out work items s, s + QSTRIPES, ...
 constexpr int QSTRIPES = 16;
+// the greedy kernel's grid barrier: workgroups arrive on one of this many
+// group counters; the last of each group arrives on the top counter
+constexpr int BARRIER_GROUPS = 8;
 enum {
     CTR_QUEUE = 0 * CTR_STRIDE,        // next query to take
     CTR_ARENA = 1 * CTR_STRIDE,        // arena cursor
@@ -167,7 +170,8 @@ enum {
     CTR_GREEDY_ITEMS = 6 * CTR_STRIDE, // items the greedy phase expanded (seeds included)
     CTR_SET_OPS = 7 * CTR_STRIDE,      // greedy phase: updates sent to the global (task, id) set
     CTR_QSTRIPE = 8 * CTR_STRIDE,      // the beam kernel's striped query queue (QSTRIPES lines)
-    CTR_COUNT = (8 + 16) * CTR_STRIDE
+    CTR_BARRIER_GROUP = 24 * CTR_STRIDE, // the grid barrier's group arrivals (BARRIER_GROUPS lines)
+    CTR_COUNT = (24 + 8) * CTR_STRIDE
 };
 
 // kernel launchers (rr_kernels.hip)

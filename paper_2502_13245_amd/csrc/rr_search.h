@@ -1570,22 +1570,37 @@ __device__ void greedy_regroup(const SearchBufs &sb, int64_t lo, int64_t hi) {
     }
 }
 
-// Grid-wide barrier of a cooperative launch (every workgroup resident):
-// workgroups count their arrivals on one counter that only grows, so the
-// k-th barrier waits for k * gridDim.x arrivals.  The agent-scope release
-// before arriving and acquire after leaving make the workgroup's writes
-// visible to every other workgroup, as a grid sync must; this costs a few
-// microseconds where the cooperative-groups sync costs about 25.  The spin
-// is bounded: past the limit the search is marked as failed (overflow bit
-// 256) instead of waiting forever.
-__device__ __forceinline__ void grid_barrier(unsigned long long *ctr, unsigned long long target,
-                                             unsigned long long *overflow) {
+// Grid-wide barrier of a cooperative launch (every workgroup resident),
+// crossed for the k-th time (k >= 1).  Workgroup g arrives on group counter
+// g % BARRIER_GROUPS; the last arrival of a group (its returning add reaches
+// k times the group's size) arrives on the top counter, and every workgroup
+// waits for the top counter to reach k times the number of groups.  Counters
+// only grow, so the k-th crossing's targets are exact.  Arrivals on one
+// counter are serialized, so the groups cut the serial part from gridDim.x
+// atomics to gridDim.x / BARRIER_GROUPS plus BARRIER_GROUPS.  The agent-scope
+// release before arriving and acquire after leaving make the workgroup's
+// writes visible to every other workgroup, as a grid sync must; the last
+// arrival of a group also acquires what its group released before it passes
+// it on.  The spin is bounded: past the limit the search is marked as failed
+// (overflow bit 256) instead of waiting forever.
+__device__ __forceinline__ void grid_barrier(unsigned long long *groups, unsigned long long *top,
+                                             unsigned long long k, unsigned long long *overflow) {
     __syncthreads();
     if (threadIdx.x == 0) {
+        const unsigned ng = gridDim.x < BARRIER_GROUPS ? gridDim.x : BARRIER_GROUPS;
+        const unsigned g = blockIdx.x % ng;
+        const unsigned long long gsize = gridDim.x / ng + (g < gridDim.x % ng ? 1u : 0u);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long old =
+            __hip_atomic_fetch_add(groups + (size_t)g * CTR_STRIDE, 1ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == k * gsize) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_fetch_add(top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const unsigned long long target = k * ng;
         long spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1l << 26)) {
                 atomicOr(overflow, OVERFLOW_BARRIER);
@@ -1607,7 +1622,8 @@ __global__ __launch_bounds__((greedy_waves<DTYPE, CPL>() * 64)) void k_greedy(Gr
     unsigned long long barriers = 0;
     auto grid_sync = [&]() {
         ++barriers;
-        grid_barrier(&a.sb.counters[CTR_BARRIER], barriers * gridDim.x, &a.sb.counters[CTR_OVERFLOW]);
+        grid_barrier(&a.sb.counters[CTR_BARRIER_GROUP], &a.sb.counters[CTR_BARRIER], barriers,
+                     &a.sb.counters[CTR_OVERFLOW]);
     };
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
