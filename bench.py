@@ -69,6 +69,15 @@ def load_traffic(tag):
     return None
 
 
+def sorted_member(sorted_keys, keys):
+    """keys[i] in sorted_keys, by binary search (np.isin sorts both arrays
+    on every call: too slow for one short list against millions of keys)."""
+    if len(sorted_keys) == 0:
+        return np.zeros(len(keys), dtype=bool)
+    pos = np.minimum(np.searchsorted(sorted_keys, keys), len(sorted_keys) - 1)
+    return sorted_keys[pos] == keys
+
+
 def recall_of(found_off, found_ids, truth_keys, n, truth_total, qmap=None):
     """Range recall (average precision of the paper): sum |K & K'| / sum |K|.
     qmap[j] is the query number of found list j (default j)."""
@@ -76,7 +85,7 @@ def recall_of(found_off, found_ids, truth_keys, n, truth_total, qmap=None):
     q = np.repeat(np.arange(nq, dtype=np.int64) if qmap is None else np.asarray(qmap, np.int64),
                   np.diff(found_off))
     keys = q * n + found_ids.astype(np.int64)
-    hit = np.isin(keys, truth_keys, assume_unique=True).sum()
+    hit = sorted_member(truth_keys, keys).sum()
     return float(hit) / truth_total if truth_total else float("nan")
 
 
@@ -122,9 +131,11 @@ def serve_leg(rr, ix, queries, q, n, levels, sp, args):
     nq = len(queries)
     truth = []
     for lv in levels:
+        t0 = time.time()
         off, ids, _ = rr.brute_force(ix, q, lv).numpy()
         qq = np.repeat(np.arange(nq, dtype=np.int64), np.diff(off))
         truth.append((np.sort(qq * n + ids.astype(np.int64)), np.diff(off)))
+        log(f"serving truth at radius {lv:.6g}: {int(off[-1])} results ({time.time() - t0:.1f}s)")
     rng = np.random.default_rng(7)
     rates = [float(x) for x in args.serve_rates.split(",")]
     # one untimed server first: the first ticks of a process load the serving
@@ -170,7 +181,7 @@ def serve_leg(rr, ix, queries, q, n, levels, sp, args):
                 k = int(c.tag)
                 tk, tc = truth[lvl[k]]
                 keys = int(qidx[k]) * n + ids.astype(np.int64)
-                hits += int(np.isin(keys, tk, assume_unique=True).sum())
+                hits += int(sorted_member(tk, keys).sum())
                 found += len(ids)
                 want += int(tc[qidx[k]])
         lat = np.array([c.t_done - c.t_arrival for c in comps]) * 1e3

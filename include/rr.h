@@ -370,7 +370,10 @@ typedef struct {
  * beam), the ladder runs again without it; if that does better, the choice
  * has es_enable = 0 and es_dropped = 1 (rr_tune_early_stop can then pick a
  * new one).  If no beam reaches the target the highest-recall one is kept
- * and met_target = 0.  Synchronizes.  Errors: those of rr_range_search. */
+ * and met_target = 0.  A setting that overflows result_capacity is timed
+ * again with the capacity doubled (from the default if it was 0, at most 8
+ * times); *inout gets the capacity the tuning ended with.  Synchronizes.
+ * Errors: those of rr_range_search. */
 rr_status rr_autotune(const rr_index *idx, const void *queries_dev, int64_t nq, double radius,
                       const double *radius_dev, const rr_results *truth, double target_recall,
                       int32_t reps, rr_search_params *inout, rr_tune_report *report,
@@ -387,8 +390,8 @@ typedef struct {
 } rr_es_tune_report;
 
 /* Choose Algorithm 5's parameters for a search (mode, beam and the other
- * fields of *inout are kept; es_enable, es_visit_limit, es_radius are
- * written).  For vl in {2, 3, 5, 10, 20, 40} the metrics of rr_es_profile at step
+ * fields of *inout are kept; es_enable, es_visit_limit, es_radius and
+ * result_capacity are written).  For vl in {2, 3, 5, 10, 20, 40} the metrics of rr_es_profile at step
  * vl give, over the queries that have results (in `truth`) but no point
  * within r yet, the distances d(p*) an early stop would cut; esr candidates
  * are their maximum (cuts none of them at vl) and their 99th and 95th
@@ -396,7 +399,8 @@ typedef struct {
  * stop enabled) and the search without early stop are timed
  * (median of `reps`, HIP events) and the fastest one whose range recall
  * against `truth` reaches the target is kept (else the most accurate).
- * The paper sets esr by inspecting the same histograms.  Synchronizes.
+ * The paper sets esr by inspecting the same histograms.  result_capacity
+ * grows on overflow as in rr_autotune and is written back.  Synchronizes.
  * Errors: RR_EINVAL (NULL, nq < 1, reps < 1, plain mode), those of
  * rr_range_search. */
 rr_status rr_tune_early_stop(const rr_index *idx, const void *queries_dev, int64_t nq,

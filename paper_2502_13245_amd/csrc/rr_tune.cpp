@@ -72,29 +72,42 @@ double recall(const Csr &truth, const Csr &found, int64_t nq) {
     return tot ? (double)hit / (double)tot : 1.0;
 }
 
-// one timed call: search + total + copy, median over reps
+// one timed call: search + total + copy, median over reps.  *cap is the
+// greedy result capacity to search with (0: the library's default); when a
+// search overflows a capacity it is doubled (at most 8 times, from the
+// default if it was 0) and the setting timed again, and *cap keeps the
+// larger value for the settings timed after it.
 rr_status time_setting(const rr_index *ix, const void *q, int64_t nq, double radius,
-                       const double *rdev, const rr_search_params &sp, int reps,
+                       const double *rdev, const rr_search_params &sp0, int64_t *cap, int reps,
                        const rr_allocator *alloc, void *stream, double *ms, Csr *ids_out) {
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RR_EHIP;
+    rr_search_params sp = sp0;
     std::vector<double> ts;
     rr_status st = RR_OK;
-    for (int r = 0; r <= reps && st == RR_OK; ++r) { // r == 0 warms up and collects ids
-        rr_results *res = nullptr;
-        (void)hipEventRecord(e0, s);
-        st = rr_range_search(ix, q, nq, radius, rdev, &sp, alloc, stream, &res);
-        if (st != RR_OK) break;
-        int64_t total = 0;
-        st = rr_results_total(res, &total);
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float t = 0.f;
-        (void)hipEventElapsedTime(&t, e0, e1);
-        if (r == 0 && ids_out && st == RR_OK) st = fetch_ids(res, nq, stream, ids_out);
-        if (r > 0) ts.push_back(t);
-        rr_results_free(res);
+    for (int grow = 0;; ++grow) {
+        sp.result_capacity = *cap;
+        ts.clear();
+        st = RR_OK;
+        for (int r = 0; r <= reps && st == RR_OK; ++r) { // r == 0 warms up and collects ids
+            rr_results *res = nullptr;
+            (void)hipEventRecord(e0, s);
+            st = rr_range_search(ix, q, nq, radius, rdev, &sp, alloc, stream, &res);
+            if (st != RR_OK) break;
+            int64_t total = 0;
+            st = rr_results_total(res, &total);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (r == 0 && ids_out && st == RR_OK) st = fetch_ids(res, nq, stream, ids_out);
+            if (r > 0) ts.push_back(t);
+            rr_results_free(res);
+        }
+        if (st != RR_ENOMEM || grow == 8) break;
+        const int64_t now = *cap > 0 ? *cap : std::min<int64_t>(std::max<int64_t>(nq, 1) * 4096, 1 << 21);
+        *cap = 2 * now;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -124,6 +137,7 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
     sp.timing = 0;
     sp.waves_per_group = 0;
     sp.cache_slots = 0;
+    int64_t cap = inout->result_capacity; // grows if a setting overflows it
     int tried = 0, best_beam = -1, top_beam = ladder[0];
     double best_ms = 0, best_rec = -1, top_rec = -1;
     auto run_ladder = [&]() -> rr_status {
@@ -138,7 +152,7 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
             Csr found;
             double ms = 0;
             rr_status s2 =
-                time_setting(ix, queries_dev, nq, radius, radius_dev, sp, reps, alloc, stream, &ms, &found);
+                time_setting(ix, queries_dev, nq, radius, radius_dev, sp, &cap, reps, alloc, stream, &ms, &found);
             if (s2 == RR_EINVAL) return tried ? RR_OK : s2; // beyond what this build's LDS allows
             if (s2 != RR_OK) return s2;
             ++tried;
@@ -192,7 +206,7 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
             sp.cache_slots = cs;
             sp.waves_per_group = wv;
             double ms = 0;
-            st = time_setting(ix, queries_dev, nq, radius, radius_dev, sp, reps, alloc, stream, &ms, nullptr);
+            st = time_setting(ix, queries_dev, nq, radius, radius_dev, sp, &cap, reps, alloc, stream, &ms, nullptr);
             if (st == RR_EINVAL) continue; // this shape does not fit the LDS
             if (st != RR_OK) return st;
             ++tried;
@@ -206,6 +220,7 @@ extern "C" rr_status rr_autotune(const rr_index *ix, const void *queries_dev, in
     inout->beam = best_beam;
     inout->waves_per_group = best_w;
     inout->cache_slots = best_c;
+    inout->result_capacity = cap;
     if (es_dropped) inout->es_enable = 0;
     if (report) {
         report->tried = tried;
@@ -236,6 +251,7 @@ extern "C" rr_status rr_tune_early_stop(const rr_index *ix, const void *queries_
     int tried = 0;
     rr_search_params best = *inout, sp = *inout;
     sp.timing = 0;
+    int64_t cap = inout->result_capacity; // grows if a setting overflows it
     // the search without early stop (ES mode: its stop is the point, so the
     // reference is the setting as given)
     if (sp.mode != RR_ES) sp.es_enable = 0;
@@ -244,7 +260,7 @@ extern "C" rr_status rr_tune_early_stop(const rr_index *ix, const void *queries_
     {
         Csr found;
         double ms = 0;
-        st = time_setting(ix, queries_dev, nq, radius, radius_dev, sp, reps, alloc, stream, &ms, &found);
+        st = time_setting(ix, queries_dev, nq, radius, radius_dev, sp, &cap, reps, alloc, stream, &ms, &found);
         if (st != RR_OK) return st;
         ++tried;
         best = sp;
@@ -255,8 +271,8 @@ extern "C" rr_status rr_tune_early_stop(const rr_index *ix, const void *queries_
     auto consider = [&](const rr_search_params &cand) -> rr_status {
         Csr found;
         double ms = 0;
-        rr_status s2 = time_setting(ix, queries_dev, nq, radius, radius_dev, cand, reps, alloc, stream,
-                                    &ms, &found);
+        rr_status s2 = time_setting(ix, queries_dev, nq, radius, radius_dev, cand, &cap, reps, alloc,
+                                    stream, &ms, &found);
         if (s2 != RR_OK) return s2;
         ++tried;
         const double rec = recall(gt, found, nq);
@@ -311,6 +327,7 @@ extern "C" rr_status rr_tune_early_stop(const rr_index *ix, const void *queries_
     inout->es_enable = best.es_enable;
     inout->es_visit_limit = best.es_visit_limit;
     inout->es_radius = best.es_radius;
+    inout->result_capacity = cap;
     if (report) {
         report->tried = tried;
         report->es_enable = best.es_enable;
