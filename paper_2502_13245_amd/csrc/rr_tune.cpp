@@ -90,6 +90,7 @@ rr_status time_setting(const rr_index *ix, const void *q, int64_t nq, double rad
         sp.result_capacity = *cap;
         ts.clear();
         st = RR_OK;
+        bool overflow = false; // a capacity of the search, not a failed allocation
         for (int r = 0; r <= reps && st == RR_OK; ++r) { // r == 0 warms up and collects ids
             rr_results *res = nullptr;
             (void)hipEventRecord(e0, s);
@@ -97,6 +98,7 @@ rr_status time_setting(const rr_index *ix, const void *q, int64_t nq, double rad
             if (st != RR_OK) break;
             int64_t total = 0;
             st = rr_results_total(res, &total);
+            overflow = st == RR_ENOMEM;
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float t = 0.f;
@@ -105,7 +107,7 @@ rr_status time_setting(const rr_index *ix, const void *q, int64_t nq, double rad
             if (r > 0) ts.push_back(t);
             rr_results_free(res);
         }
-        if (st != RR_ENOMEM || grow == 8) break;
+        if (!overflow || grow == 8) break;
         const int64_t now = *cap > 0 ? *cap : std::min<int64_t>(std::max<int64_t>(nq, 1) * 4096, 1 << 21);
         *cap = 2 * now;
     }
