@@ -530,8 +530,14 @@ extern "C" void rr_results_free(rr_results *res) {
     delete res;
 }
 
+// A bitmap costs n/8 bytes to clear per task and answers a probe with one
+// atomic; the hash table costs a bucket read and a CAS per new key.  At 1M
+// points the bitmaps are faster (greedy kernel 0.83 against 0.94 ms); at 10M
+// the clears outweigh them (hash only: 25.0 against 25.7 ms; a 32 GiB budget
+// that covered every task: 38.5 ms), so above 4M points (512 KB per task)
+// every task uses the hash table unless RR_BITMAP_BYTES sets a budget.
 int64_t rr::bitmap_tasks(int64_t n, int64_t nq) {
-    int64_t budget = 2048ll << 20;
+    int64_t budget = n > (int64_t(1) << 22) ? 0 : 2048ll << 20;
     if (const char *e = std::getenv("RR_BITMAP_BYTES")) budget = std::max<int64_t>(0, std::atoll(e));
     const int64_t cap = budget / (bitmap_words(n) * 4);
     return std::min(nq, cap);
