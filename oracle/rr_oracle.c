@@ -269,6 +269,12 @@ static int cand_cmp(const void *x, const void *y) {
     return 0;
 }
 
+/* qsort of n candidates by (d, id); qsort's array may not be NULL, which an
+ * empty list's is */
+static void sort_cands(cand_t *a, int64_t n) {
+    if (n > 1) qsort(a, (size_t)n, sizeof(cand_t), cand_cmp);
+}
+
 /* ------------------------------------------------------------------ */
 /* Algorithm 1: BeamSearch(q, G, P, S, r, b, M)                        */
 /* with M = Algorithm 5 (EarlyStoppingExample) when es->enable         */
@@ -327,7 +333,7 @@ static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64
         touch(sc, s);
         cl_push(B, ds, s);
     }
-    qsort(B->a, (size_t)B->n, sizeof(cand_t), cand_cmp);
+    sort_cands(B->a, B->n);
     if (probe) {
         probe->reached = 0;
         probe->found = 0;
@@ -379,7 +385,7 @@ static void beam_search(const graph_t *G, const void *q, const int32_t *S, int64
             touch(sc, u);
             cl_push(B, du, u);
         }
-        qsort(B->a, (size_t)B->n, sizeof(cand_t), cand_cmp);
+        sort_cands(B->a, B->n);
         /* if |B| > b: keep the b closest */
         if (B->n > b) {
             for (int64_t i = b; i < B->n; i++) sc->inB[B->a[i].id] = 0;
@@ -467,7 +473,7 @@ static void greedy_search(const graph_t *G, const void *q, const cand_t *S, int6
             }
         }
     }
-    qsort(V->a, (size_t)V->n, sizeof(cand_t), cand_cmp);
+    sort_cands(V->a, V->n);
 }
 
 /* ------------------------------------------------------------------ */
@@ -547,7 +553,7 @@ static void bf_body(void *arg, int64_t qi, int tid) {
         double di = dist_pts(&c->P, row_ptr(&c->P, i), q);
         if (di <= c->radius[qi]) cl_push(&l, di, (int32_t)i);
     }
-    qsort(l.a, (size_t)l.n, sizeof(cand_t), cand_cmp);
+    sort_cands(l.a, l.n);
     qres_from(&c->qr[qi], l.a, l.n);
     free(l.a);
 }
@@ -918,7 +924,7 @@ static int32_t robust_prune(const points_t *P, int32_t p, const int32_t *cand, i
             }
         if (!rep) cl_push(&l, pdist(P, p, c), c);
     }
-    qsort(l.a, (size_t)l.n, sizeof(cand_t), cand_cmp);
+    sort_cands(l.a, l.n);
     dup = (uint8_t *)calloc((size_t)(l.n > 0 ? l.n : 1), 1); /* 1 = pruned */
     int32_t k = 0;
     for (int64_t i = 0; i < l.n && k < R; i++) {
@@ -1080,7 +1086,7 @@ int orc_build_vamana(const void *base, int dtype, int64_t n, int32_t d, int32_t 
                     ne++;
                 }
             }
-            qsort(edges, (size_t)ne, sizeof(edge_t), edge_cmp);
+            if (ne > 1) qsort(edges, (size_t)ne, sizeof(edge_t), edge_cmp);
             int32_t nt = 0;
             for (int64_t e = 0; e < ne; e++) {
                 if (e == 0 || edges[e].tgt != edges[e - 1].tgt) {
