@@ -238,9 +238,10 @@ void rr_index_free(rr_index *idx);
  * Device memory held by *out (from `alloc`): the padded queries, the result
  * arena, and for modes with a greedy or sort stage the greedy items plus
  * n/8 bytes of membership bitmap per query that may expand.  The bitmaps are
- * capped at 2 GiB per call: further queries use a hash table instead.  The
- * environment variable RR_BITMAP_BYTES sets another cap, and 0 disables the
- * bitmaps.
+ * capped at 2 GiB per call (and not used at all above 4M points, where their
+ * clearing costs more than they save): further queries use a hash table
+ * instead.  The environment variable RR_BITMAP_BYTES sets another cap, and 0
+ * disables the bitmaps.
  * Errors: RR_EINVAL (beam < 1, vl < 1 with early stopping, NaN radius, mode
  * or precision unknown, BF16 or SQ8 precision on integer data), RR_ESTATE
  * (index not on the device), RR_ENOMEM, RR_EHIP. */

@@ -23,47 +23,30 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <mutex>
+#include <memory>
 #include <new>
 #include <string>
-#include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "rr_internal.h"
+#include "rr_server_core.h"
 
 using namespace rr;
 
+struct rr_server;
+
 namespace {
 
-using Clock = std::chrono::steady_clock;
-
-struct Request {
-    uint64_t tag;
-    double radius;
-    double t_arrival;
-    std::vector<uint8_t> q;
-    bool solo = false; // run in a tick of its own (a retry after a shared capacity ran out)
-    int32_t ticks = 0; // ticks already spent (a retry keeps counting)
-};
-
-struct Slot {
-    bool busy = false;
-    bool solo = false;
-    uint64_t tag = 0;
-    double radius = 0;
-    double t_arrival = 0, t_admit = 0;
-    int32_t ticks = 0;
-    std::vector<uint8_t> q; // the request's vector, kept for a retry
-};
-
-struct Finished {
-    std::vector<int32_t> ids;
-    std::vector<uint8_t> dists; // int32 (integer data) or float32 (float data)
+// the device side of a tick (ServerCore's Dev): staging, the search kernels
+// over the resident slots, the read-back of states, counters and results
+struct HipDev {
+    rr_server *s = nullptr;
+    bool stage(int32_t k, int32_t slot, const ServerRequest &r);
+    bool tick(int32_t admitted, const int32_t *active, int32_t nwork, std::string &err);
+    SlotOutcome outcome(int32_t slot) const;
+    bool shared_overflow() const;
+    bool result(int32_t slot, ServerFinished &f, std::string &err) const;
 };
 
 } // namespace
@@ -107,21 +90,8 @@ struct rr_server {
     uint8_t *h_ad = nullptr;
     bool hash_dirty = true;
 
-    Clock::time_point t0;
-    std::thread worker;
-    mutable std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    bool stop = false;
-    bool failed = false;
-    std::string error;
-    std::deque<Request> pending;
-    std::vector<Slot> slots;
-    std::vector<int32_t> free_slots;
-    std::deque<rr_completion> completions;
-    std::unordered_map<uint64_t, Finished> results;
-    rr_server_info info{};
-
-    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    HipDev dev;
+    std::unique_ptr<ServerCore<HipDev>> core;
 };
 
 namespace {
@@ -194,162 +164,54 @@ hipError_t tick_device(rr_server *s, int32_t admitted, int32_t nwork) {
     return hipSuccess;
 }
 
-void worker_main(rr_server *s) {
-    if (hipSetDevice(s->device) != hipSuccess) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->failed = true;
-        s->error = "hipSetDevice failed in the server thread";
-        s->cv_done.notify_all();
-        return;
+bool HipDev::stage(int32_t k, int32_t slot, const ServerRequest &r) {
+    std::memcpy(s->h_stage_q + (size_t)k * s->qbytes, r.q.data(), (size_t)s->qbytes);
+    s->h_stage_r[k] = r.radius;
+    s->h_stage_dst[k] = slot;
+    return true;
+}
+
+bool HipDev::tick(int32_t admitted, const int32_t *active, int32_t nwork, std::string &err) {
+    for (int32_t i = 0; i < nwork; ++i) s->h_qlist[i] = active[i];
+    const hipError_t e = tick_device(s, admitted, nwork);
+    if (e != hipSuccess) {
+        err = hipGetErrorString(e);
+        return false;
     }
-    std::vector<int32_t> active;
-    active.reserve(s->S);
-    for (;;) {
-        int32_t admitted = 0;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] {
-                return s->stop || active.size() > 0 ||
-                       (!s->pending.empty() && !s->free_slots.empty());
-            });
-            if (s->stop && s->pending.empty() && active.empty()) break;
-            const double t = s->now();
-            while (!s->pending.empty() && !s->free_slots.empty()) {
-                Request &r = s->pending.front();
-                // a retry runs alone: it waits until nothing else is resident,
-                // and nothing else joins its tick
-                if (r.solo && (!active.empty() || admitted > 0)) break;
-                if (!active.empty() && s->slots[active[0]].solo) break;
-                const int32_t slot = s->free_slots.back();
-                s->free_slots.pop_back();
-                std::memcpy(s->h_stage_q + (size_t)admitted * s->qbytes, r.q.data(), s->qbytes);
-                s->h_stage_r[admitted] = r.radius;
-                s->h_stage_dst[admitted] = slot;
-                Slot &sl = s->slots[slot];
-                sl.busy = true;
-                sl.solo = r.solo;
-                sl.tag = r.tag;
-                sl.radius = r.radius;
-                sl.t_arrival = r.t_arrival;
-                if (!r.solo) sl.t_admit = t;
-                sl.ticks = r.ticks;
-                sl.q.swap(r.q);
-                active.push_back(slot);
-                ++admitted;
-                s->pending.pop_front();
-                if (sl.solo) break;
-            }
-            s->info.admitted += admitted;
-            s->info.pending = (int64_t)s->pending.size();
-            s->info.resident = (int64_t)active.size();
-            s->info.max_resident = std::max<int64_t>(s->info.max_resident, (int64_t)active.size());
-        }
-        const Clock::time_point tb = Clock::now();
-        for (size_t i = 0; i < active.size(); ++i) s->h_qlist[i] = active[i];
-        const hipError_t e = tick_device(s, admitted, (int32_t)active.size());
-        if (e != hipSuccess) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->failed = true;
-            s->error = std::string("server tick failed: ") + hipGetErrorString(e);
-            s->cv_done.notify_all();
-            return;
-        }
-        // collect the slots whose search finished in this tick.  The greedy
-        // items, the (task, id) set and result_capacity are shared by the
-        // tick's queries; when one of them ran out, a query flagged truncated
-        // may only have lost results to its neighbours, so it is run again in
-        // a tick of its own.  A query truncated alone is returned truncated.
-        const bool shared_overflow = (s->h_ctr[CTR_OVERFLOW] & ~OVERFLOW_BARRIER) != 0ull;
-        std::vector<rr_completion> done;
-        std::vector<std::pair<uint64_t, Finished>> out;
-        std::vector<int32_t> freed;
-        std::vector<Request> retry;
-        size_t keep = 0;
-        for (size_t i = 0; i < active.size(); ++i) {
-            const int32_t slot = active[i];
-            Slot &sl = s->slots[slot];
-            ++sl.ticks;
-            if (!(s->h_state[slot].flags & BS_DONE)) {
-                active[keep++] = slot;
-                continue;
-            }
-            if (s->h_stats[slot].truncated && shared_overflow && !sl.solo) {
-                Request r;
-                r.tag = sl.tag;
-                r.radius = sl.radius;
-                r.t_arrival = sl.t_arrival;
-                r.q.swap(sl.q);
-                r.solo = true;
-                r.ticks = sl.ticks;
-                retry.push_back(std::move(r));
-                freed.push_back(slot);
-                sl.busy = false;
-                continue;
-            }
-            const int64_t off = s->h_roff[slot];
-            const int32_t cnt = s->h_rcnt[slot];
-            const int64_t used = std::min<int64_t>((int64_t)s->h_ctr[CTR_ARENA], s->bufs->sb.arena_cap);
-            if (cnt < 0 || (cnt > 0 && (off < 0 || off + cnt > used))) {
-                std::lock_guard<std::mutex> lk(s->mu);
-                s->failed = true;
-                s->error = "server tick returned an inconsistent result segment";
-                s->cv_done.notify_all();
-                return;
-            }
-            Finished f;
-            f.ids.assign(s->h_aid + off, s->h_aid + off + cnt);
-            if (s->ix->dtype == RR_F32) {
-                f.dists.resize((size_t)cnt * 4);
-                const double *src = (const double *)s->h_ad + off;
-                float *dst = (float *)f.dists.data();
-                for (int32_t j = 0; j < cnt; ++j) dst[j] = (float)src[j];
-            } else {
-                // integer keys are key_off + d (mod 2^32)
-                const uint32_t *src = (const uint32_t *)s->h_ad + off;
-                const uint32_t ko = (uint32_t)s->view.key_off;
-                f.dists.resize((size_t)cnt * 4);
-                int32_t *dst = (int32_t *)f.dists.data();
-                for (int32_t j = 0; j < cnt; ++j) dst[j] = (int32_t)(src[j] - ko);
-            }
-            rr_completion c{};
-            c.tag = sl.tag;
-            c.count = cnt;
-            c.stats = s->h_stats[slot];
-            c.truncated = c.stats.truncated;
-            c.ticks = sl.ticks;
-            c.t_arrival = sl.t_arrival;
-            c.t_admit = sl.t_admit;
-            done.push_back(c);
-            out.emplace_back(sl.tag, std::move(f));
-            freed.push_back(slot);
-            sl.busy = false;
-            sl.solo = false;
-            sl.q.clear();
-        }
-        active.resize(keep);
-        const double t = s->now();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            for (size_t i = 0; i < done.size(); ++i) {
-                done[i].t_done = t;
-                s->results[done[i].tag] = std::move(out[i].second);
-                s->completions.push_back(done[i]);
-            }
-            for (int32_t f : freed) s->free_slots.push_back(f);
-            // retries go first, in their original order
-            for (size_t i = retry.size(); i-- > 0;) s->pending.push_front(std::move(retry[i]));
-            s->info.retried += (int64_t)retry.size();
-            s->info.completed += (int64_t)done.size();
-            s->info.ticks += 1;
-            s->info.resident = (int64_t)active.size();
-            const double tick_s = std::chrono::duration<double>(Clock::now() - tb).count();
-            s->info.busy_s += tick_s;
-            s->info.max_tick_s = std::max(s->info.max_tick_s, tick_s);
-            s->cv_done.notify_all();
-        }
+    return true;
+}
+
+SlotOutcome HipDev::outcome(int32_t slot) const {
+    SlotOutcome oc;
+    oc.done = (s->h_state[slot].flags & BS_DONE) != 0;
+    oc.stats = s->h_stats[slot];
+    return oc;
+}
+
+bool HipDev::shared_overflow() const { return (s->h_ctr[CTR_OVERFLOW] & ~OVERFLOW_BARRIER) != 0ull; }
+
+bool HipDev::result(int32_t slot, ServerFinished &f, std::string &err) const {
+    const int64_t off = s->h_roff[slot];
+    const int32_t cnt = s->h_rcnt[slot];
+    const int64_t used = std::min<int64_t>((int64_t)s->h_ctr[CTR_ARENA], s->bufs->sb.arena_cap);
+    if (cnt < 0 || (cnt > 0 && (off < 0 || off + cnt > used))) {
+        err = "server tick returned an inconsistent result segment";
+        return false;
     }
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->cv_done.notify_all();
+    f.ids.assign(s->h_aid + off, s->h_aid + off + cnt);
+    f.dists.resize((size_t)cnt * 4);
+    if (s->ix->dtype == RR_F32) {
+        const double *src = (const double *)s->h_ad + off;
+        float *dst = (float *)f.dists.data();
+        for (int32_t j = 0; j < cnt; ++j) dst[j] = (float)src[j];
+    } else {
+        // integer keys are key_off + d (mod 2^32)
+        const uint32_t *src = (const uint32_t *)s->h_ad + off;
+        const uint32_t ko = (uint32_t)s->view.key_off;
+        int32_t *dst = (int32_t *)f.dists.data();
+        for (int32_t j = 0; j < cnt; ++j) dst[j] = (int32_t)(src[j] - ko);
+    }
+    return true;
 }
 
 void destroy_buffers(rr_server *s) {
@@ -471,7 +333,6 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     s->qbytes = (int64_t)ix->d * (ix->dtype == RR_F32 ? 4 : 1);
     s->dsz = ix->dtype == RR_F32 ? 8 : 4;
     s->device = ix->device;
-    s->t0 = Clock::now();
     auto bail = [&](rr_status code, const char *msg, hipError_t e) {
         destroy_buffers(s);
         delete s;
@@ -486,8 +347,6 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     const int64_t S = s->S, b = sp->beam;
     const Caps caps = server_caps(ix->n, S, b, s->greedy, scfg->result_capacity);
     const int64_t item_cap = caps.item_cap, hash_cap = caps.hash_cap, arena_cap = caps.arena_cap;
-    s->info.slots = S;
-    s->info.device_bytes = server_bytes(ix->n, S, b, s->greedy, scfg->result_capacity, s->qrow, s->qbytes, s->dsz);
     st = make_results(ix, s->view, S, sp, s->greedy, arena_cap, item_cap, hash_cap, s->qrow, alloc,
                       s->stream, &s->bufs);
     if (st != RR_OK) {
@@ -551,12 +410,23 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     s->h_aid = (int32_t *)(hb + h_ai);
     s->h_ad = hb + h_ad;
 
-    s->slots.assign((size_t)S, Slot());
-    s->free_slots.reserve((size_t)S);
-    for (int64_t i = S - 1; i >= 0; --i) s->free_slots.push_back((int32_t)i);
-    try {
-        s->worker = std::thread(worker_main, s);
-    } catch (...) {
+    s->dev.s = s;
+    s->core.reset(new (std::nothrow) ServerCore<HipDev>(s->dev, s->S, s->max_pending, s->qbytes));
+    if (!s->core) {
+        destroy_buffers(s);
+        delete s;
+        return set_error(RR_ENOMEM, "host allocation failed");
+    }
+    s->core->set_device_bytes(
+        server_bytes(ix->n, S, b, s->greedy, scfg->result_capacity, s->qrow, s->qbytes, s->dsz));
+    const int dev = s->device;
+    const bool started = s->core->start([dev](std::string &why) {
+        if (hipSetDevice(dev) == hipSuccess) return true;
+        why = "hipSetDevice failed in the server thread";
+        return false;
+    });
+    if (!started) {
+        s->core.reset();
         destroy_buffers(s);
         delete s;
         return set_error(RR_ENOMEM, "could not start the server thread");
@@ -565,92 +435,50 @@ extern "C" rr_status rr_server_create(const rr_index *ix, const rr_search_params
     return RR_OK;
 }
 
-extern "C" double rr_server_clock(const rr_server *s) { return s ? s->now() : 0.0; }
+extern "C" double rr_server_clock(const rr_server *s) { return s && s->core ? s->core->now() : 0.0; }
 
 extern "C" rr_status rr_server_submit(rr_server *s, const void *query_host, double radius,
                                       uint64_t tag, double t_arrival) {
     if (!s || !query_host) return set_error(RR_EINVAL, "server or query is NULL");
     if (radius != radius) return set_error(RR_EINVAL, "radius is NaN");
-    Request r;
-    r.tag = tag;
-    r.radius = radius;
-    r.q.assign((const uint8_t *)query_host, (const uint8_t *)query_host + s->qbytes);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->failed) return set_error(RR_ESTATE, "%s", s->error.c_str());
-        if (s->stop) return set_error(RR_ESTATE, "server is stopping");
-        if ((int64_t)s->pending.size() >= s->max_pending)
-            return set_error(RR_EBUSY, "request queue is full (%d)", s->max_pending);
-        r.t_arrival = t_arrival >= 0 ? t_arrival : s->now();
-        s->pending.push_back(std::move(r));
-        s->info.submitted += 1;
-        s->info.pending = (int64_t)s->pending.size();
-    }
-    s->cv_work.notify_one();
-    return RR_OK;
+    std::string msg;
+    const rr_status st = s->core->submit(query_host, radius, tag, t_arrival, msg);
+    return st == RR_OK ? RR_OK : set_error(st, "%s", msg.c_str());
 }
 
 extern "C" rr_status rr_server_poll(rr_server *s, rr_completion *out, int32_t max, int32_t *n) {
     if (!s || !n || (max > 0 && !out)) return set_error(RR_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    int32_t k = 0;
-    while (k < max && !s->completions.empty()) {
-        out[k++] = s->completions.front();
-        s->completions.pop_front();
-    }
-    *n = k;
-    if (s->failed) return set_error(RR_ESTATE, "%s", s->error.c_str());
-    return RR_OK;
+    std::string msg;
+    const rr_status st = s->core->poll(out, max, n, msg);
+    return st == RR_OK ? RR_OK : set_error(st, "%s", msg.c_str());
 }
 
 extern "C" rr_status rr_server_result(rr_server *s, uint64_t tag, int32_t *ids_host,
                                       void *dists_host, int64_t capacity, int64_t *count) {
     if (!s || !count) return set_error(RR_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->results.find(tag);
-    if (it == s->results.end()) return set_error(RR_EINVAL, "no finished request with this tag");
-    const int64_t c = (int64_t)it->second.ids.size();
-    *count = c;
-    if (capacity < c) return set_error(RR_ENOMEM, "capacity %lld < %lld results", (long long)capacity, (long long)c);
-    if (c > 0 && (!ids_host || !dists_host)) return set_error(RR_EINVAL, "output buffers are NULL");
-    if (c > 0) {
-        std::memcpy(ids_host, it->second.ids.data(), (size_t)c * 4);
-        std::memcpy(dists_host, it->second.dists.data(), (size_t)c * 4);
-    }
-    s->results.erase(it);
-    return RR_OK;
+    std::string msg;
+    const rr_status st = s->core->result(tag, ids_host, dists_host, capacity, count, msg);
+    return st == RR_OK ? RR_OK : set_error(st, "%s", msg.c_str());
 }
 
 extern "C" rr_status rr_server_drain(rr_server *s, double timeout_s) {
     if (!s) return set_error(RR_EINVAL, "server is NULL");
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto idle = [&] {
-        return s->failed || (s->pending.empty() && s->info.completed == s->info.submitted);
-    };
-    if (timeout_s < 0) {
-        s->cv_done.wait(lk, idle);
-    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), idle)) {
-        return set_error(RR_EBUSY, "drain timed out");
-    }
-    if (s->failed) return set_error(RR_ESTATE, "%s", s->error.c_str());
-    return RR_OK;
+    std::string msg;
+    const rr_status st = s->core->drain(timeout_s, msg);
+    return st == RR_OK ? RR_OK : set_error(st, "%s", msg.c_str());
 }
 
 extern "C" rr_status rr_server_info_get(const rr_server *s, rr_server_info *info) {
     if (!s || !info) return set_error(RR_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    *info = s->info;
+    *info = s->core->info();
     return RR_OK;
 }
 
 extern "C" void rr_server_destroy(rr_server *s) {
     if (!s) return;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
-    }
-    s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    // the worker finishes the queued and resident requests, then ends
+    if (s->core) s->core->stop();
+    s->core.reset();
     (void)hipSetDevice(s->device);
     destroy_buffers(s);
     delete s;

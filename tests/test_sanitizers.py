@@ -11,6 +11,8 @@
 * The oracle's threaded routines built with ThreadSanitizer, driven by
   tests/sanitize/oracle_driver.c at 4 threads: no report, same digest as the
   plain build.
+* The serving loop's host side (rr::ServerCore) with a CPU test double of the
+  device, under ThreadSanitizer and under ASan + UBSan.
 
 The GPU kernels are not covered: device code runs without sanitizers."""
 import os
@@ -167,3 +169,23 @@ def test_oracle_threads_under_tsan(tmp_path, small):
              _env())
         outs.append(np.fromfile(out, dtype=np.uint8))
     np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("kind,flags", [
+    ("tsan", ["-fsanitize=thread"]),
+    ("asan_ubsan", ["-fsanitize=address,undefined"]),
+])
+def test_server_core_double(tmp_path, kind, flags):
+    """The serving loop's host side (rr::ServerCore, the code behind
+    rr_server_*) with a scripted device instead of the GPU: four submitting
+    threads and a polling one, forced shared-capacity overflows; every request
+    completes once and complete, retried requests run alone, the latency
+    accounting is ordered and the counters agree, a full queue is refused and
+    a failed worker start reaches every caller (tests/sanitize/server_double.cpp)."""
+    exe = str(tmp_path / f"server_double_{kind}")
+    subprocess.run([GXX, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", *flags,
+                    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                    os.path.join(SAN, "server_double.cpp"), "-o", exe, "-lpthread"],
+                   check=True, capture_output=True)
+    p = _run([exe, "300"], _env())
+    assert p.stdout.startswith("OK requests 1200"), p.stdout
