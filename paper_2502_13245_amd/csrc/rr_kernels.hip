@@ -148,45 +148,8 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
             th.esr_int = floor_key(esr, key_off);
             th.r_f = (float)r;
             th.esr_f = (float)esr;
-            th.lo = -1.f;
+            th.lo = -1.f; // the approximate passes' band: k_prep_band
             th.hi = -1.f;
-            if (pass != PASS_EXACT) {
-                // norms of the float32 query row
-                const float *qf = reinterpret_cast<const float *>(q + qi * row_in);
-                double n2 = 0.0, n1 = 0.0, sum = 0.0, dl2 = 0.0;
-                for (int i = 0; i < d; ++i) {
-                    const double x = (double)qf[i];
-                    n2 = fma(x, x, n2);
-                    n1 += fabs(x);
-                    sum += x;
-                    dl2 = fma(x - (double)sq_lo, x - (double)sq_lo, dl2);
-                }
-                const double u = 0x1p-24, slack = 1.0 + 1e-6;
-                if (pass == PASS_BF16 && !ip) {
-                    // bf16 rows: |x^ - x| <= 2^-8 |x| per coordinate
-                    band_l2(r, 0x1p-8 * maxnorm * slack, (double)(d + 2) * u, margin, &th.lo, &th.hi);
-                } else if (pass == PASS_BF16) {
-                    // |<x^ - x, q>| <= 2^-8 max|x| |q|, float32 sum error
-                    // <= gamma (1 + 2^-8) max|x| |q|
-                    const double g = (double)(d + 2) * u;
-                    band_ip(r, 0.0, (0x1p-8 + g * (1.0 + 0x1p-8)) * maxnorm * sqrt(n2) * slack, margin,
-                            &th.lo, &th.hi);
-                } else if (!ip) {
-                    // codes: within scale/2 per coordinate; the prepared query
-                    // within 2^-24 |q_i - lo| (in value units) per coordinate
-                    band_l2(r, (0.5 * (double)sq_scale * sqrt((double)d) + u * sqrt(dl2)) * slack,
-                            (double)(d + 4) * u, margin, &th.lo, &th.hi);
-                } else {
-                    // key = -scale sum(code q) = d + lo sum(q) + error, with
-                    // |error| <= scale |q|_1 (1/2 + 255 (d + 2) 2^-24)
-                    const double shift = (double)sq_lo * sum;
-                    const double delta0 =
-                        (double)sq_scale * n1 * (0.5 + 255.0 * (double)(d + 2) * u) * slack;
-                    band_ip(r, shift, delta0, margin, &th.lo, &th.hi);
-                    th.r_f = (float)(r + shift);
-                    th.esr_f = (float)(esr + shift);
-                }
-            }
             qth[qo] = th;
             if (state) {
                 BeamState bs{};
@@ -194,6 +157,65 @@ __global__ void k_prep_queries(const uint8_t *q, int64_t nq, int32_t row_in, int
             }
         }
     }
+}
+
+// The recheck band of the approximate passes (bf16 rows, 8-bit codes): one
+// wave per query sums the norms of its float32 row in FP64 (lanes stride over
+// the coordinates, then a butterfly), and lane 0 widens the query's
+// thresholds into the band [lo, hi] of approximate keys that the exact
+// distance must re-decide.  Runs after k_prep_queries, which wrote the exact
+// thresholds.
+__global__ void k_prep_band(const uint8_t *q, int64_t nq, int32_t row_in, double radius,
+                            const double *radius_dev, double esr, QThresh *qth, double maxnorm, int d,
+                            double margin, int pass, int ip, float sq_lo, float sq_scale,
+                            const int32_t *dst) {
+    const int lane = threadIdx.x & 63;
+    const int64_t qi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (qi >= nq) return; // whole waves leave together
+    const int64_t qo = dst ? (int64_t)dst[qi] : qi;
+    const float *qf = reinterpret_cast<const float *>(q + qi * row_in);
+    double n2 = 0.0, n1 = 0.0, sum = 0.0, dl2 = 0.0;
+    for (int i = lane; i < d; i += 64) {
+        const double x = (double)qf[i];
+        n2 = fma(x, x, n2);
+        n1 += fabs(x);
+        sum += x;
+        dl2 = fma(x - (double)sq_lo, x - (double)sq_lo, dl2);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        n2 += __shfl_xor(n2, o);
+        n1 += __shfl_xor(n1, o);
+        sum += __shfl_xor(sum, o);
+        dl2 += __shfl_xor(dl2, o);
+    }
+    if (lane != 0) return;
+    QThresh th = qth[qo];
+    const double r = radius_dev ? radius_dev[qi] : radius;
+    const double u = 0x1p-24, slack = 1.0 + 1e-6;
+    if (pass == PASS_BF16 && !ip) {
+        // bf16 rows: |x^ - x| <= 2^-8 |x| per coordinate
+        band_l2(r, 0x1p-8 * maxnorm * slack, (double)(d + 2) * u, margin, &th.lo, &th.hi);
+    } else if (pass == PASS_BF16) {
+        // |<x^ - x, q>| <= 2^-8 max|x| |q|, float32 sum error
+        // <= gamma (1 + 2^-8) max|x| |q|
+        const double g = (double)(d + 2) * u;
+        band_ip(r, 0.0, (0x1p-8 + g * (1.0 + 0x1p-8)) * maxnorm * sqrt(n2) * slack, margin, &th.lo,
+                &th.hi);
+    } else if (!ip) {
+        // codes: within scale/2 per coordinate; the prepared query
+        // within 2^-24 |q_i - lo| (in value units) per coordinate
+        band_l2(r, (0.5 * (double)sq_scale * sqrt((double)d) + u * sqrt(dl2)) * slack,
+                (double)(d + 4) * u, margin, &th.lo, &th.hi);
+    } else {
+        // key = -scale sum(code q) = d + lo sum(q) + error, with
+        // |error| <= scale |q|_1 (1/2 + 255 (d + 2) 2^-24)
+        const double shift = (double)sq_lo * sum;
+        const double delta0 = (double)sq_scale * n1 * (0.5 + 255.0 * (double)(d + 2) * u) * slack;
+        band_ip(r, shift, delta0, margin, &th.lo, &th.hi);
+        th.r_f = (float)(r + shift);
+        th.esr_f = (float)(esr + shift);
+    }
+    qth[qo] = th;
 }
 
 // the prep kernel's pass and output row width for a search configuration
@@ -219,6 +241,11 @@ hipError_t launch_prep_queries(const DevIndex &ix, const void *queries, int64_t 
                        cfg.esr, sb.qth, sb.qpad, (double)ix.max_norm, ix.d, cfg.margin, pass,
                        (int)(ix.metric == RR_IP), ix.key_off, ix.sq_lo, ix.sq_scale,
                        (const int32_t *)nullptr, (BeamState *)nullptr);
+    if (pass != PASS_EXACT)
+        hipLaunchKernelGGL(k_prep_band, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s,
+                           (const uint8_t *)queries, nq, ix.d * esz, radius, radius_dev, cfg.esr,
+                           sb.qth, (double)ix.max_norm, ix.d, cfg.margin, pass,
+                           (int)(ix.metric == RR_IP), ix.sq_lo, ix.sq_scale, (const int32_t *)nullptr);
     return hipGetLastError();
 }
 
@@ -236,6 +263,11 @@ hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
                        ix.d * esz, row_out, 0.0, radius_dev, cfg.esr, sb.qth, sb.qpad,
                        (double)ix.max_norm, ix.d, cfg.margin, pass, (int)(ix.metric == RR_IP),
                        ix.key_off, ix.sq_lo, ix.sq_scale, dst, state);
+    if (pass != PASS_EXACT)
+        hipLaunchKernelGGL(k_prep_band, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s,
+                           (const uint8_t *)queries, k, ix.d * esz, 0.0, radius_dev, cfg.esr, sb.qth,
+                           (double)ix.max_norm, ix.d, cfg.margin, pass, (int)(ix.metric == RR_IP),
+                           ix.sq_lo, ix.sq_scale, dst);
     return hipGetLastError();
 }
 
