@@ -563,7 +563,7 @@ int64_t rr::next_pow2(int64_t x) {
 struct BufLayout {
     size_t qpad, qth, ctr, roff, rcnt, stats, aid, ad, off, scan;
     size_t tq = 0, tc = 0, te = 0, ik = 0, idist = 0, lvl = 0, hash = 0, soff = 0, scur = 0,
-           sid = 0, sd = 0, tr = 0, tx = 0, bm = 0, ttr = 0, tp = 0, lc = 0, uk = 0, ud = 0;
+           sid = 0, sd = 0, tr = 0, tx = 0, bm = 0, ttr = 0, tp = 0, lc = 0, uk = 0, ud = 0, tout = 0, tlong = 0;
     size_t total = 0;
     int64_t nq = 0, arena_cap = 0, item_cap = 0, hash_cap = 0, bm_tasks = 0, bm_words = 0;
     int32_t max_levels = 4096;
@@ -605,6 +605,8 @@ static BufLayout layout_bufs(const rr_index *ix, int64_t nq, bool with_greedy, i
         L.hash = c.take<unsigned long long>(hash_cap);
         L.soff = c.take<int64_t>(nq + 1);
         L.scur = c.take<unsigned long long>(nq);
+        L.tout = c.take<int64_t>(nq);
+        L.tlong = c.take<int32_t>(nq);
         L.sid = c.take<int32_t>(item_cap);
         L.sd = c.take<uint8_t>(item_cap * dsz);
         L.tp = c.take<unsigned long long>(nq);
@@ -648,6 +650,8 @@ static void bind_bufs(const BufLayout &L, uint8_t *b, const rr_search_params *sp
         sb.hash_cap = L.hash_cap;
         sb.seg_off = (int64_t *)(b + L.soff);
         sb.seg_cur = (unsigned long long *)(b + L.scur);
+        sb.task_out = (int64_t *)(b + L.tout);
+        sb.task_long = (int32_t *)(b + L.tlong);
         sb.seg_ids = (int32_t *)(b + L.sid);
         sb.seg_dists = b + L.sd;
         sb.task_prev = (unsigned long long *)(b + L.tp);
@@ -1063,7 +1067,7 @@ static rr_status brute_force_once(const rr_index *ix, const void *queries_dev, i
         rr_results_free(res);
         return RR_OK; // caller retries with the exact capacity
     }
-    HIP_TRY_R(launch_finalize(ix->dtype, sb, s));
+    HIP_TRY_R(launch_finalize(ix->dtype, sb, device_cus(), s));
     HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
 #undef HIP_TRY_R
     *out = res;

@@ -136,6 +136,8 @@ struct SearchBufs {
     int64_t bm_tasks = 0;
     int64_t *seg_off = nullptr;   // [nq + 1] per-task segment offsets
     unsigned long long *seg_cur = nullptr;   // [nq]
+    int64_t *task_out = nullptr;  // [nq] arena offset of each task's sorted list (finalization)
+    int32_t *task_long = nullptr; // [nq] tasks of more than 64 items, longest size class first
     int32_t *seg_ids = nullptr;   // [item_cap]
     void *seg_dists = nullptr;
 };
@@ -171,7 +173,10 @@ enum {
     CTR_SET_OPS = 7 * CTR_STRIDE,      // greedy phase: updates sent to the global (task, id) set
     CTR_QSTRIPE = 8 * CTR_STRIDE,      // the beam kernel's striped query queue (QSTRIPES lines)
     CTR_BARRIER_GROUP = 24 * CTR_STRIDE, // the grid barrier's group arrivals (BARRIER_GROUPS lines)
-    CTR_COUNT = (24 + 8) * CTR_STRIDE
+    CTR_LONG_TASKS = 32 * CTR_STRIDE,  // finalization: tasks a whole workgroup sorts
+    CTR_SORT_QUEUE = 33 * CTR_STRIDE,  // finalization: next of them to sort
+    CTR_MID_TASKS = 34 * CTR_STRIDE,   // finalization: tasks one wave sorts in LDS
+    CTR_COUNT = 35 * CTR_STRIDE
 };
 
 // kernel launchers (rr_kernels.hip)
@@ -217,7 +222,7 @@ hipError_t launch_probe_rows(const DevIndex &ix, int64_t gathers, uint64_t seed,
                              hipStream_t s);
 hipError_t launch_nn_dist(const DevIndex &ix, const uint8_t *qpad, int64_t nq, double *nn,
                           unsigned long long *bits, hipStream_t s);
-hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s);
+hipError_t launch_finalize(int dtype, SearchBufs &sb, int num_cus, hipStream_t s);
 // radix select: hist[256] = counts of the 8-bit digit at `shift` among the
 // keys (uint32, or FP64 mapped to ordered uint64) whose masked bits equal prefix
 hipError_t launch_digit_hist(const void *keys, int key_bytes, int64_t n, unsigned long long prefix,

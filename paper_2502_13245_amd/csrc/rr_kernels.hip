@@ -272,23 +272,71 @@ hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
 }
 
 
-// exclusive scan of task_cnt[0, ntasks) into seg_off (one workgroup)
-__global__ void k_task_scan(SearchBufs sb) {
-    __shared__ unsigned long long part[1024];
+// One workgroup: task t's items go to seg_off[t] (prefix sum of the counts);
+// its sorted list (at most max_results entries) to task_out[t], inside one
+// arena range reserved here with a single atomic.  The tasks of more than 64
+// items are listed in task_long by size class, longest first: above lds_cap
+// (the global merge path), then above wave_cap (a workgroup's LDS sort),
+// then the rest (one wave's LDS sort).
+__global__ void k_task_scan(SearchBufs sb, int lds_cap, int wave_cap) {
+    __shared__ unsigned long long part[1024];  // items
+    __shared__ unsigned long long opart[1024]; // listed results
+    __shared__ uint32_t cpart[3][1024];        // tasks per size class
+    __shared__ unsigned long long s_base;
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
     const int tid = threadIdx.x;
     const int64_t per = (nt + blockDim.x - 1) / blockDim.x;
     const int64_t lo = min(nt, (int64_t)tid * per), hi = min(nt, lo + per);
-    unsigned long long s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += sb.task_cnt[i];
-    part[tid] = s;
-    __syncthreads();
-    block_inclusive_scan(part);
-    if (tid == (int)blockDim.x - 1) sb.seg_off[nt] = (int64_t)part[tid];
-    unsigned long long run = part[tid] - s;
+    const unsigned long long cap = (unsigned long long)sb.max_results;
+    // size class: 0 above lds_cap, 1 above wave_cap, 2 above 64, 3 short
+    auto cls = [&](unsigned long long c) {
+        return c > (unsigned long long)lds_cap ? 0 : c > (unsigned long long)wave_cap ? 1 : c > 64ull ? 2 : 3;
+    };
+    unsigned long long s = 0, o = 0;
+    uint32_t k[3] = {0u, 0u, 0u};
     for (int64_t i = lo; i < hi; ++i) {
+        const unsigned long long c = sb.task_cnt[i];
+        s += c;
+        o += min(c, cap);
+        const int z = cls(c);
+        if (z < 3) ++k[z];
+    }
+    part[tid] = s;
+    opart[tid] = o;
+    for (int z = 0; z < 3; ++z) cpart[z][tid] = k[z];
+    __syncthreads();
+    // the inclusive scans share their barriers (Hillis-Steele)
+    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+        const bool in = tid >= d;
+        const unsigned long long v = in ? part[tid - d] : 0ull;
+        const unsigned long long w = in ? opart[tid - d] : 0ull;
+        uint32_t x[3];
+        for (int z = 0; z < 3; ++z) x[z] = in ? cpart[z][tid - d] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        opart[tid] += w;
+        for (int z = 0; z < 3; ++z) cpart[z][tid] += x[z];
+        __syncthreads();
+    }
+    const int last = (int)blockDim.x - 1;
+    const uint32_t n0 = cpart[0][last], n1 = cpart[1][last];
+    if (tid == last) {
+        sb.seg_off[nt] = (int64_t)part[tid];
+        sb.counters[CTR_LONG_TASKS] = (unsigned long long)(n0 + n1);
+        sb.counters[CTR_MID_TASKS] = (unsigned long long)cpart[2][last];
+        s_base = atomicAdd(&sb.counters[CTR_ARENA], opart[tid]);
+    }
+    __syncthreads();
+    unsigned long long run = part[tid] - s, orun = s_base + opart[tid] - o;
+    uint32_t pos[3] = {cpart[0][tid] - k[0], n0 + cpart[1][tid] - k[1], n0 + n1 + cpart[2][tid] - k[2]};
+    for (int64_t i = lo; i < hi; ++i) {
+        const unsigned long long c = sb.task_cnt[i];
         sb.seg_off[i] = (int64_t)run;
-        run += sb.task_cnt[i];
+        sb.task_out[i] = (int64_t)orun;
+        run += c;
+        orun += min(c, cap);
+        const int z = cls(c);
+        if (z < 3) sb.task_long[pos[z]++] = (int32_t)i;
         sb.seg_cur[i] = 0ull;
     }
 }
@@ -330,99 +378,228 @@ template <typename D> __global__ void k_scatter(SearchBufs sb) {
     }
 }
 
-// Sort one segment by (d, id) with the whole workgroup.  Segments that fit
-// in LDS use a bitonic network; longer ones are sorted in runs of that size
-// and merged pairwise through `tmp` (same length) by rank computation.
 constexpr int SORT_THREADS = 1024;
 
+// Keys of the LDS sorts: a list entry (distance d, id) as one LDS element,
+// so that a merge step moves one element.  For 32-bit distances the
+// element is the 64-bit integer d:id, whose integer order is the (d, id)
+// order; for FP64 distances it is a 16-byte record compared by (d, id).
+template <typename D> struct SortKey;
+template <> struct SortKey<uint32_t> {
+    using E = unsigned long long;
+    static constexpr int PAD_SHIFT = 4; // one padding element per 16
+    static __device__ __forceinline__ E make(uint32_t d, uint32_t id) { return ((E)d << 32) | id; }
+    static __device__ __forceinline__ uint32_t dist(E e) { return (uint32_t)(e >> 32); }
+    static __device__ __forceinline__ uint32_t id(E e) { return (uint32_t)e; }
+    static __device__ __forceinline__ bool less(E a, E b) { return a < b; }
+    static __device__ __forceinline__ E pick(bool c, E a, E b) { return c ? a : b; }
+};
+struct __align__(16) DKey {
+    double d;
+    uint32_t id, pad;
+};
+template <> struct SortKey<double> {
+    using E = DKey;
+    static constexpr int PAD_SHIFT = 3; // one padding element per 8
+    static __device__ __forceinline__ E make(double d, uint32_t id) { return DKey{d, id, 0u}; }
+    static __device__ __forceinline__ double dist(const E &e) { return e.d; }
+    static __device__ __forceinline__ uint32_t id(const E &e) { return e.id; }
+    static __device__ __forceinline__ bool less(const E &a, const E &b) { return key_less(a.d, a.id, b.d, b.id); }
+    // field by field, so the selection stays in registers
+    static __device__ __forceinline__ E pick(bool c, const E &a, const E &b) {
+        E r;
+        r.d = c ? a.d : b.d;
+        r.id = c ? a.id : b.id;
+        r.pad = 0u;
+        return r;
+    }
+};
+
+// Segments of up to sort_cap keys are sorted in LDS: every wave sorts
+// 64-key chunks in registers, then merge passes double the sorted runs, one
+// barrier per pass.  Keys (distance, id) are unique within a task and
+// padding keys get distinct ids, so the order is total.  Longer segments
+// take the global merge path; segments of up to wave_sort_cap keys are
+// sorted by one wave in its slice of the workgroup's LDS.
+template <typename D> constexpr int sort_cap() { return sizeof(D) == 4 ? 8192 : 4096; }
+template <typename D> constexpr int wave_sort_cap() { return sort_cap<D>() / (SORT_THREADS / 64); }
+// Position of element i in an LDS sort array: one padding element after
+// every 2^PAD_SHIFT.  A merge pass's thread owns MERGE_E consecutive
+// outputs, so the lanes of a wave access elements MERGE_E apart; unpadded,
+// those fall on a few LDS banks, padded they spread over all of them.
+template <typename D> __device__ __forceinline__ int lp(int i) { return i + (i >> SortKey<D>::PAD_SHIFT); }
+template <typename D, int N> constexpr int lds_len() { return N + (N >> SortKey<D>::PAD_SHIFT); }
+
+// WAVE: one wave sorts alone (its own LDS arrays, wave-level syncs);
+// otherwise the whole workgroup.
+template <bool WAVE> __device__ __forceinline__ void sort_sync() {
+    if (WAVE) wave_sync();
+    else __syncthreads();
+}
+
+// Sort a[0, p) (lp layout, p a multiple of 64) by key, using b as the
+// other buffer of the merge passes; returns 1 if the result is in b.
+template <typename D, bool WAVE = false>
+__device__ int lds_sort(typename SortKey<D>::E *a, typename SortKey<D>::E *b, int p) {
+    using K = SortKey<D>;
+    using E = typename K::E;
+    const int lane = lane_id();
+    const int tid = WAVE ? lane : (int)threadIdx.x, nth = WAVE ? 64 : (int)blockDim.x;
+    const int wid = tid >> 6, nw = nth >> 6;
+    for (int c = wid; c < (p >> 6); c += nw) {
+        const E e = a[lp<D>(c * 64 + lane)];
+        D x = K::dist(e);
+        uint32_t xi = K::id(e);
+        wave_sort(x, xi);
+        a[lp<D>(c * 64 + lane)] = K::make(x, xi);
+    }
+    sort_sync<WAVE>();
+    E *s = a, *d = b;
+    int in_b = 0;
+    // merge passes: runs A = [a0, a0 + w) and B = [a0 + w, a0 + 2w) merge
+    // into the same range.  Each thread writes MERGE_E consecutive outputs:
+    // it finds how many of them come from A by a binary search on the merge
+    // path, then merges sequentially with the two run heads in registers
+    // (one LDS read per output).  p and 2w are multiples of 64, so a
+    // thread's outputs never straddle two pairs.
+    constexpr int MERGE_E = 8;
+    for (int w = 64; w < p; w <<= 1) {
+        for (int k0 = tid * MERGE_E; k0 < p; k0 += nth * MERGE_E) {
+            const int a0 = k0 / (2 * w) * (2 * w), b0 = a0 + w;
+            const int la = min(w, p - a0), lb = b0 < p ? min(w, p - b0) : 0;
+            const int k = k0 - a0;
+            int lo = max(0, k - lb), hi = min(k, la);
+            while (lo < hi) {
+                const int x = (lo + hi) >> 1;
+                if (K::less(s[lp<D>(a0 + x)], s[lp<D>(b0 + k - x - 1)])) lo = x + 1;
+                else hi = x;
+            }
+            int ia = a0 + lo, ib = b0 + (k - lo);
+            const int ea = a0 + la, eb = b0 + lb;
+            // clamped reads stay inside the two runs (la >= 1, b0 >= 64)
+            E va = s[lp<D>(min(ia, ea - 1))], vb = s[lp<D>(min(ib, eb - 1))];
+#pragma unroll
+            for (int j = 0; j < MERGE_E; ++j) {
+                const bool takea = ib >= eb || (ia < ea && K::less(va, vb));
+                d[lp<D>(k0 + j)] = K::pick(takea, va, vb);
+                ia += takea ? 1 : 0;
+                ib += takea ? 0 : 1;
+                if (j + 1 < MERGE_E) {
+                    const E nv = s[lp<D>(takea ? min(ia, ea - 1) : min(ib, eb - 1))];
+                    va = K::pick(takea, nv, va);
+                    vb = K::pick(takea, vb, nv);
+                }
+            }
+        }
+        sort_sync<WAVE>();
+        E *t = s;
+        s = d;
+        d = t;
+        in_b ^= 1;
+    }
+    return in_b;
+}
+
+// Stage entries [0, p) of a list in LDS (lp layout), padding keys past n:
+// each of the nth threads takes entries tid, tid + nth, ... (R of them at
+// most), loads them all before storing any, then their out-degrees, so the
+// loads overlap instead of queuing one behind the other.  Returns the sum
+// of this thread's out-degrees (0 without deg).
+template <typename D, int R>
+__device__ __forceinline__ int stage_list(const D *d, const int32_t *ids, int64_t n, int p, int tid,
+                                          int nth, typename SortKey<D>::E *a, const uint8_t *deg) {
+    D x[R];
+    uint32_t xi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = tid + r * nth;
+        x[r] = dmax<D>();
+        xi[r] = RR_EMPTY32 - (uint32_t)(i - n);
+        if (i < n) {
+            x[r] = d[i];
+            xi[r] = (uint32_t)ids[i];
+        }
+    }
+    int e = 0;
+    if (deg) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (tid + r * nth < n) e += deg[xi[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = tid + r * nth;
+        if (i < p) a[lp<D>(i)] = SortKey<D>::make(x[r], xi[r]);
+    }
+    return e;
+}
+
+// Sort one long segment by (d, id) with the whole workgroup: runs of run_len
+// keys are sorted in LDS by lds_sort (a and b hold run_len elements each,
+// lp layout), then merge passes through global memory double the runs,
+// ping-pong between (d, id) and (td, tid_).  In a merge pass each thread
+// writes MERGE_G consecutive outputs: one binary search on the merge path
+// (global reads) finds how many come from the left run, then a sequential
+// merge follows.  The result ends in (d, id).
 template <typename D>
-__device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int64_t n, D *sd,
-                                   uint32_t *si, int run_len) {
+__device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int64_t n,
+                                   typename SortKey<D>::E *a, typename SortKey<D>::E *b, int run_len) {
+    using K = SortKey<D>;
     const int t = threadIdx.x, nt = blockDim.x;
-    // 1) sort runs of run_len in LDS
     for (int64_t r0 = 0; r0 < n; r0 += run_len) {
         const int m = (int)min((int64_t)run_len, n - r0);
-        int p2 = 1;
-        while (p2 < m) p2 <<= 1;
-        for (int i = t; i < p2; i += nt) {
-            if (i < m) {
-                sd[i] = d[r0 + i];
-                si[i] = (uint32_t)id[r0 + i];
-            } else {
-                sd[i] = dmax<D>();
-                si[i] = RR_EMPTY32;
-            }
-        }
+        const int p = max(64, (m + 63) & ~63);
+        stage_list<D, sort_cap<D>() / SORT_THREADS>(d + r0, id + r0, m, p, t, nt, a, nullptr);
         __syncthreads();
-        for (int k = 2; k <= p2; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = t; i < p2; i += nt) {
-                    const int ixj = i ^ j;
-                    if (ixj > i) {
-                        const bool up = (i & k) == 0;
-                        const bool sw = up ? key_less(sd[ixj], si[ixj], sd[i], si[i])
-                                           : key_less(sd[i], si[i], sd[ixj], si[ixj]);
-                        if (sw) {
-                            D a = sd[i];
-                            sd[i] = sd[ixj];
-                            sd[ixj] = a;
-                            uint32_t b = si[i];
-                            si[i] = si[ixj];
-                            si[ixj] = b;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        const typename K::E *r = lds_sort<D>(a, b, p) ? b : a;
         for (int i = t; i < m; i += nt) {
-            d[r0 + i] = sd[i];
-            id[r0 + i] = (int32_t)si[i];
+            const typename K::E e = r[lp<D>(i)];
+            d[r0 + i] = K::dist(e);
+            id[r0 + i] = (int32_t)K::id(e);
         }
         __syncthreads();
     }
-    // 2) merge runs pairwise until one run remains (ping-pong d <-> td)
-    D *src_d = d, *dst_d = td;
-    int32_t *src_i = id, *dst_i = tid_;
+    constexpr int MERGE_G = 16; // run_len (a multiple of 64) is a multiple of it
+    D *sd = d, *dd = td;
+    int32_t *si = id, *di = tid_;
     bool in_tmp = false;
     for (int64_t w = run_len; w < n; w <<= 1) {
-        for (int64_t i = t; i < n; i += nt) {
-            const int64_t run = i / w;
-            const int64_t a0 = (run & ~1ll) * w;           // left run start
-            const int64_t b0 = a0 + w;                      // right run start
-            const int64_t a1 = min(n, b0), b1 = min(n, b0 + w);
-            const D x = src_d[i];
-            const uint32_t xi = (uint32_t)src_i[i];
-            int64_t pos;
-            if ((run & 1) == 0) {
-                // rank in the right run: elements strictly less
-                int64_t lo = b0, hi = b1;
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (key_less(src_d[mid], (uint32_t)src_i[mid], x, xi)) lo = mid + 1;
-                    else hi = mid;
-                }
-                pos = a0 + (i - a0) + (lo - b0);
-            } else {
-                int64_t lo = a0, hi = a1;
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (key_less(src_d[mid], (uint32_t)src_i[mid], x, xi)) lo = mid + 1;
-                    else hi = mid;
-                }
-                pos = a0 + (i - b0) + (lo - a0);
+        for (int64_t k0 = (int64_t)t * MERGE_G; k0 < n; k0 += (int64_t)nt * MERGE_G) {
+            const int64_t a0 = k0 / (2 * w) * (2 * w), b0 = a0 + w;
+            const int64_t la = min(w, n - a0), lb = b0 < n ? min(w, n - b0) : 0;
+            const int64_t k = k0 - a0, end = a0 + la + lb;
+            int64_t lo = max((int64_t)0, k - lb), hi = min(k, la);
+            while (lo < hi) {
+                const int64_t x = (lo + hi) >> 1;
+                if (key_less(sd[a0 + x], (uint32_t)si[a0 + x], sd[b0 + k - x - 1],
+                             (uint32_t)si[b0 + k - x - 1]))
+                    lo = x + 1;
+                else
+                    hi = x;
             }
-            dst_d[pos] = x;
-            dst_i[pos] = (int32_t)xi;
+            int64_t ia = a0 + lo, ib = b0 + (k - lo);
+            const int64_t ea = a0 + la, eb = b0 + lb;
+            for (int j = 0; j < MERGE_G && k0 + j < end; ++j) {
+                // clamped reads stay inside the segment (la >= 1; with
+                // lb = 0 every output comes from the left run)
+                const int64_t ca = min(ia, ea - 1), cb = min(ib, (lb ? eb : ea) - 1);
+                const bool takea = ib >= eb || (ia < ea && key_less(sd[ca], (uint32_t)si[ca], sd[cb],
+                                                                    (uint32_t)si[cb]));
+                const int64_t src = takea ? ia : ib;
+                dd[k0 + j] = sd[src];
+                di[k0 + j] = si[src];
+                ia += takea ? 1 : 0;
+                ib += takea ? 0 : 1;
+            }
         }
         __threadfence_block();
         __syncthreads();
-        D *sw = src_d;
-        src_d = dst_d;
-        dst_d = sw;
-        int32_t *swi = src_i;
-        src_i = dst_i;
-        dst_i = swi;
+        D *sw = sd;
+        sd = dd;
+        dd = sw;
+        int32_t *swi = si;
+        si = di;
+        di = swi;
         in_tmp = !in_tmp;
     }
     if (in_tmp) {
@@ -434,140 +611,186 @@ __device__ void block_sort_segment(D *d, int32_t *id, D *td, int32_t *tid_, int6
     }
 }
 
-// Segments of up to sort_cap keys are sorted in LDS: every wave sorts
-// 64-key chunks in registers, then merge passes double the sorted runs
-// (each key's output position is its index in its own run plus its rank in
-// the partner run, found by binary search), one barrier per pass.  Keys
-// (distance, id) are unique within a task; padding keys get distinct ids
-// so ranks stay unique.  Longer segments take the global merge path.
-template <typename D> constexpr int sort_cap() { return sizeof(D) == 4 ? 8192 : 4096; }
+// A task's counters, loaded when its sort starts so that the loads overlap
+// the sort (by thread or lane 0 of the sorting group).
+struct TaskInfo {
+    int32_t q = 0, prev_rechk = 0;
+    bool exp = true, trunc = false;
+    unsigned long long evals = 0, rechk = 0;
+};
 
-template <typename D>
-__device__ int lds_sort(D *ad, uint32_t *ai, D *bd, uint32_t *bi, int p) {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int lane = lane_id(), wid = tid >> 6, nw = nth >> 6;
-    for (int c = wid; c < (p >> 6); c += nw) {
-        D x = ad[c * 64 + lane];
-        uint32_t xi = ai[c * 64 + lane];
-        wave_sort(x, xi);
-        ad[c * 64 + lane] = x;
-        ai[c * 64 + lane] = xi;
-    }
-    __syncthreads();
-    D *sd = ad, *dd = bd;
-    uint32_t *si = ai, *di = bi;
-    int in_b = 0;
-    // merge passes: runs A = [a0, a0 + w) and B = [a0 + w, a0 + 2w) merge
-    // into the same range.  Each thread writes MERGE_E consecutive outputs:
-    // it finds how many of them come from A by a binary search on the merge
-    // path, then merges sequentially.  p and 2w are multiples of 64, so a
-    // thread's outputs never straddle two pairs.
-    constexpr int MERGE_E = 8;
-    for (int w = 64; w < p; w <<= 1) {
-        for (int k0 = tid * MERGE_E; k0 < p; k0 += nth * MERGE_E) {
-            const int a0 = k0 / (2 * w) * (2 * w), b0 = a0 + w;
-            const int la = min(w, p - a0), lb = b0 < p ? min(w, p - b0) : 0;
-            const int k = k0 - a0;
-            int lo = max(0, k - lb), hi = min(k, la);
-            while (lo < hi) {
-                const int x = (lo + hi) >> 1;
-                if (key_less(sd[a0 + x], si[a0 + x], sd[b0 + k - x - 1], si[b0 + k - x - 1])) lo = x + 1;
-                else hi = x;
-            }
-            int ia = a0 + lo, ib = b0 + (k - lo);
-            const int ea = a0 + la, eb = b0 + lb;
-#pragma unroll
-            for (int j = 0; j < MERGE_E; ++j) {
-                // clamped reads stay inside the two runs (la >= 1, b0 >= 64)
-                const int ca = min(ia, ea - 1), cb = min(ib, eb - 1);
-                const bool takea =
-                    ib >= eb || (ia < ea && key_less(sd[ca], si[ca], sd[cb], si[cb]));
-                const int src = takea ? ia : ib;
-                dd[k0 + j] = sd[src];
-                di[k0 + j] = si[src];
-                ia += takea ? 1 : 0;
-                ib += takea ? 0 : 1;
-            }
-        }
-        __syncthreads();
-        D *td = sd;
-        sd = dd;
-        dd = td;
-        uint32_t *ti = si;
-        si = di;
-        di = ti;
-        in_b ^= 1;
-    }
-    return in_b;
+__device__ TaskInfo load_task(const SearchBufs &sb, int64_t t) {
+    TaskInfo ti;
+    ti.q = sb.task_q[t];
+    ti.exp = sb.task_expand == nullptr || sb.task_expand[t] != 0;
+    ti.trunc = sb.task_trunc && sb.task_trunc[t];
+    ti.evals = sb.task_evals[t];
+    if (sb.task_rechk) ti.rechk = sb.task_rechk[t];
+    ti.prev_rechk = sb.stats[ti.q].rechecked;
+    return ti;
 }
 
+// per-task outputs of the finalization: where the task's list went and its
+// counters
+__device__ void emit_task(const SearchBufs &sb, const TaskInfo &ti, int64_t off, int64_t n,
+                          int64_t nout, bool ok, int edges) {
+    sb.res_off[ti.q] = off;
+    sb.res_cnt[ti.q] = ok ? (int32_t)nout : 0;
+    rr_query_stats *st = &sb.stats[ti.q];
+    st->count = ok ? (int32_t)nout : 0;
+    st->greedy_visits = ti.exp ? (int32_t)n : 0;
+    st->greedy_evals = (int32_t)ti.evals;
+    st->greedy_edges = ti.exp && sb.deg ? edges : 0;
+    st->rechecked = ti.prev_rechk + (int32_t)ti.rechk;
+    if (nout < n || ti.trunc) st->truncated = 1;
+    if (!ok) {
+        st->truncated = 1;
+        atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);
+    }
+}
+
+// Tasks of up to 64 items: one wave sorts each in registers and writes the
+// first max_results to the arena range k_task_scan reserved for the task.
+template <typename D> __global__ __launch_bounds__(256) void k_sort_short(SearchBufs sb) {
+    const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
+    const D *segd = (const D *)sb.seg_dists;
+    D *outd = (D *)sb.arena_dists;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t t = gw; t < nt; t += nwv) {
+        const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
+        if (n > 64) continue;
+        TaskInfo ti;
+        if (lane == 0) ti = load_task(sb, t);
+        D x = dmax<D>();
+        uint32_t xi = RR_EMPTY32 - (uint32_t)lane;
+        int e = 0;
+        if (lane < n) {
+            x = segd[s0 + lane];
+            xi = (uint32_t)sb.seg_ids[s0 + lane];
+            if (sb.deg) e = sb.deg[xi];
+        }
+        wave_sort(x, xi);
+        const int64_t off = sb.task_out[t], nout = min(n, sb.max_results);
+        const bool ok = off + nout <= sb.arena_cap;
+        if (ok && lane < nout) {
+            sb.arena_ids[off + lane] = (int32_t)xi;
+            outd[off + lane] = x;
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) e += __shfl_xor(e, m);
+        if (lane == 0) emit_task(sb, ti, off, n, nout, ok, e);
+    }
+}
+
+// take the next index of a queue of `n` entries, or -1 once it is empty
+// (a plain load first, so callers arriving after the end add no atomic)
+__device__ __forceinline__ int64_t queue_take(unsigned long long *q, int64_t n) {
+    if ((int64_t)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
+    const int64_t j = (int64_t)atomicAdd(q, 1ull);
+    return j < n ? j : -1;
+}
+
+// Tasks of more than 64 items, listed in task_long.  Those of up to
+// wave_sort_cap items are sorted first, each by one wave in its own LDS
+// slice.  Then the workgroups take the longer ones (longest first) from a
+// queue; the whole workgroup sorts each, in LDS up to sort_cap keys, else by
+// block_sort_segment.
 template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort_emit(SearchBufs sb) {
     extern __shared__ __align__(16) uint8_t sort_smem[];
-    constexpr int CAP = sort_cap<D>();
-    D *ad = (D *)sort_smem;
-    uint32_t *ai = (uint32_t *)(ad + CAP);
-    D *bd = (D *)(ai + CAP);
-    uint32_t *bi = (uint32_t *)(bd + CAP);
-    __shared__ int64_t s_off;
+    using K = SortKey<D>;
+    using E = typename K::E;
+    constexpr int CAP = sort_cap<D>(), WCAP = wave_sort_cap<D>();
+    constexpr int CAPL = lds_len<D, CAP>(), WCAPL = lds_len<D, WCAP>();
+    static_assert((SORT_THREADS / 64) * WCAPL <= CAPL, "wave slices exceed the LDS arrays");
+    E *la = (E *)sort_smem;
+    E *lb = la + CAPL;
     __shared__ int s_edges; // adjacency entries of the task's greedy visits
-    const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
+    __shared__ int64_t s_j;
+    const int64_t nlong = (int64_t)sb.counters[CTR_LONG_TASKS];
+    const int64_t nmid = (int64_t)sb.counters[CTR_MID_TASKS];
     D *segd = (D *)sb.seg_dists;
     D *tmpd = (D *)sb.item_dist;
     D *outd = (D *)sb.arena_dists;
+    // the medium lists first, one wave each, spread over the grid's waves
+    // in a fixed order (a shared queue would take one atomic per wave)
+    {
+        const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
+        E *wa = la + wid * WCAPL, *wb = lb + wid * WCAPL;
+        const int64_t nwv = (int64_t)gridDim.x * (SORT_THREADS / 64);
+        for (int64_t j = (int64_t)blockIdx.x * (SORT_THREADS / 64) + wid; j < nmid; j += nwv) {
+            const int64_t t = sb.task_long[nlong + j];
+            const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
+            const int64_t nout = min(n, sb.max_results), off = sb.task_out[t];
+            const bool ok = off + nout <= sb.arena_cap;
+            const int p = (int)((n + 63) & ~63ll);
+            TaskInfo ti;
+            if (lane == 0) ti = load_task(sb, t);
+            int e = stage_list<D, WCAP / 64>(segd + s0, sb.seg_ids + s0, n, p, lane, 64, wa, sb.deg);
+            wave_sync();
+            const E *r = lds_sort<D, true>(wa, wb, p) ? wb : wa;
+            if (ok)
+                for (int i = lane; i < nout; i += 64) {
+                    const E v = r[lp<D>(i)];
+                    sb.arena_ids[off + i] = (int32_t)K::id(v);
+                    outd[off + i] = K::dist(v);
+                }
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) e += __shfl_xor(e, m);
+            if (lane == 0) emit_task(sb, ti, off, n, nout, ok, e);
+            wave_sync();
+        }
+    }
+    // then the long lists, the whole workgroup on each, from a queue
     if (threadIdx.x == 0) s_edges = 0;
     __syncthreads();
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (;;) {
+        if (threadIdx.x == 0) s_j = queue_take(&sb.counters[CTR_SORT_QUEUE], nlong);
+        __syncthreads();
+        const int64_t j = s_j;
+        if (j < 0) break;
+        const int64_t t = sb.task_long[j];
         const int64_t s0 = sb.seg_off[t], n = sb.seg_off[t + 1] - s0;
-        // at most max_results_per_query are returned: the first of the sorted list
-        const int64_t nout = min(n, sb.max_results);
-        const int32_t q = sb.task_q[t];
-        // thread 0 issues the arena reservation and the loads of the task's
-        // counters up front; they complete while the segment is loaded
-        unsigned long long aoff = 0, evals = 0, rechk = 0;
-        int32_t prev_rechk = 0;
-        bool exp = true;
-        if (threadIdx.x == 0) {
-            aoff = atomicAdd(&sb.counters[CTR_ARENA], (unsigned long long)nout);
-            exp = sb.task_expand == nullptr || sb.task_expand[t] != 0;
-            evals = sb.task_evals[t];
-            if (sb.task_rechk) rechk = sb.task_rechk[t];
-            prev_rechk = sb.stats[q].rechecked;
-        }
-        const int p = max(64, (int)((n + 63) & ~63ll));
+        // at most max_results are returned: the first of the sorted list
+        const int64_t nout = min(n, sb.max_results), off = sb.task_out[t];
+        const bool ok = off + nout <= sb.arena_cap;
+        const int p = (int)((n + 63) & ~63ll);
+        TaskInfo ti;
+        if (threadIdx.x == 0) ti = load_task(sb, t);
         int my_edges = 0;
         if (n <= CAP) {
-            for (int i = threadIdx.x; i < p; i += blockDim.x) {
-                if (i < n) {
-                    ad[i] = segd[s0 + i];
-                    ai[i] = (uint32_t)sb.seg_ids[s0 + i];
-                    if (sb.deg) my_edges += sb.deg[ai[i]];
-                } else {
-                    ad[i] = dmax<D>();
-                    ai[i] = RR_EMPTY32 - (uint32_t)(i - n);
-                }
-            }
+            my_edges = stage_list<D, CAP / SORT_THREADS>(segd + s0, sb.seg_ids + s0, n, p, threadIdx.x,
+                                                         SORT_THREADS, la, sb.deg);
         } else if (sb.deg) {
-            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) my_edges += sb.deg[sb.seg_ids[s0 + i]];
+            // out-degrees only (the list is sorted in place): 8 loads in flight per thread
+            for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * SORT_THREADS) {
+                uint32_t v[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int64_t i = i0 + (int64_t)r * SORT_THREADS;
+                    v[r] = i < n ? (uint32_t)sb.seg_ids[s0 + i] : 0u;
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (i0 + (int64_t)r * SORT_THREADS < n) my_edges += sb.deg[v[r]];
+            }
         }
         if (my_edges) atomicAdd(&s_edges, my_edges);
-        if (threadIdx.x == 0) s_off = (int64_t)aoff;
         __syncthreads();
-        const int64_t off = s_off;
-        const bool ok = off + nout <= sb.arena_cap;
         if (n <= CAP) {
-            const int in_b = lds_sort<D>(ad, ai, bd, bi, p);
-            const D *rd = in_b ? bd : ad;
-            const uint32_t *ri = in_b ? bi : ai;
+            const E *r = lds_sort<D>(la, lb, p) ? lb : la;
             if (ok)
                 for (int i = threadIdx.x; i < nout; i += blockDim.x) {
-                    sb.arena_ids[off + i] = (int32_t)ri[i];
-                    outd[off + i] = rd[i];
+                    const E v = r[lp<D>(i)];
+                    sb.arena_ids[off + i] = (int32_t)K::id(v);
+                    outd[off + i] = K::dist(v);
                 }
         } else {
             // the item arrays are free once scattered: they serve as the
             // merge passes' scratch
             block_sort_segment<D>(segd + s0, sb.seg_ids + s0, tmpd + s0,
-                                  reinterpret_cast<int32_t *>(sb.item_key) + s0, n, ad, ai, CAP);
+                                  reinterpret_cast<int32_t *>(sb.item_key) + s0, n, la, lb, CAP);
             if (ok)
                 for (int64_t i = threadIdx.x; i < nout; i += blockDim.x) {
                     sb.arena_ids[off + i] = sb.seg_ids[s0 + i];
@@ -575,19 +798,7 @@ template <typename D> __global__ __launch_bounds__(SORT_THREADS) void k_seg_sort
                 }
         }
         if (threadIdx.x == 0) {
-            sb.res_off[q] = off;
-            sb.res_cnt[q] = ok ? (int32_t)nout : 0;
-            rr_query_stats *st = &sb.stats[q];
-            st->count = ok ? (int32_t)nout : 0;
-            st->greedy_visits = exp ? (int32_t)n : 0;
-            st->greedy_evals = (int32_t)evals;
-            st->greedy_edges = exp && sb.deg ? s_edges : 0;
-            st->rechecked = prev_rechk + (int32_t)rechk;
-            if (nout < n || (sb.task_trunc && sb.task_trunc[t])) st->truncated = 1;
-            if (!ok) {
-                st->truncated = 1;
-                atomicOr(&sb.counters[CTR_OVERFLOW], 32ull);
-            }
+            emit_task(sb, ti, off, n, nout, ok, s_edges);
             s_edges = 0;
         }
         __syncthreads();
@@ -613,19 +824,30 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 
 // group the items of every task by task, sort each group by (d, id) and
 // append it to the result arena (greedy phase and brute force)
-template <typename D> static hipError_t run_finalize(SearchBufs &sb, hipStream_t s) {
-    const size_t shmem = (size_t)2 * sort_cap<D>() * (sizeof(D) + 4);
+template <typename D> static hipError_t run_finalize(SearchBufs &sb, int num_cus, hipStream_t s) {
+    const size_t shmem = (size_t)2 * lds_len<D, sort_cap<D>()>() * sizeof(typename SortKey<D>::E);
     hipError_t e = hipFuncSetAttribute((const void *)k_seg_sort_emit<D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb);
+    // the long-list sort's workgroups loop over the tasks: as many as are
+    // resident at once (a workgroup's LDS fills most of a CU)
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_seg_sort_emit<D>, SORT_THREADS, shmem);
+    if (e != hipSuccess) return e;
+    const int grid = std::max(1, per_cu) * std::max(1, num_cus);
+    int short_per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&short_per_cu, k_sort_short<D>, 256, 0);
+    if (e != hipSuccess) return e;
+    const int short_grid = std::max(1, short_per_cu) * std::max(1, num_cus);
+    hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb, sort_cap<D>(), wave_sort_cap<D>());
     hipLaunchKernelGGL(k_scatter<D>, dim3(1024), dim3(256), 0, s, sb);
-    hipLaunchKernelGGL(k_seg_sort_emit<D>, dim3(2048), dim3(SORT_THREADS), shmem, s, sb);
+    hipLaunchKernelGGL(k_sort_short<D>, dim3(short_grid), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL(k_seg_sort_emit<D>, dim3(grid), dim3(SORT_THREADS), shmem, s, sb);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(int dtype, SearchBufs &sb, hipStream_t s) {
-    return dtype == RR_F32 ? run_finalize<double>(sb, s) : run_finalize<uint32_t>(sb, s);
+hipError_t launch_finalize(int dtype, SearchBufs &sb, int num_cus, hipStream_t s) {
+    return dtype == RR_F32 ? run_finalize<double>(sb, num_cus, s) : run_finalize<uint32_t>(sb, num_cus, s);
 }
 
 

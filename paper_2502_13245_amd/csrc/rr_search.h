@@ -2058,7 +2058,7 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
         e = hipEventRecord(after_kernel, s);
         if (e != hipSuccess) return e;
     }
-    return launch_finalize(ix.dtype, sb, s);
+    return launch_finalize(ix.dtype, sb, num_cus, s);
 }
 
 template <int DTYPE, int CPL, int G>

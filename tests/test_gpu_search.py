@@ -321,6 +321,26 @@ def test_heavy_expansion_float(rr):
         assert np.all(np.diff(d[off[qi]:off[qi + 1]]) >= 0), f"q{qi} not ordered"
 
 
+def test_result_capacity_overflow_is_reported(rr):
+    """A result capacity below what the search returns: the call reports
+    RR_ENOMEM (no list cut short passes as complete), and the same search
+    with room afterwards is whole and equal to the oracle's."""
+    w = synth.gaussian_mixture_unit(6000, 24, 16, 3, 0.3 / np.sqrt(16), 23, spread=0.3)
+    adj, entry = oracle.build_vamana(w.base, 16, 32, 1.2, synth.permutation(6000, 23))
+    r = oracle.percentile_radius(w.base, w.queries, 0.8)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=oracle.ADAPTIVE, beam=8)
+    total = int(o.offsets[-1])
+    for cap in (total // 4, total // 2):
+        flush_print(f"capacity overflow: {cap} of {total}")
+        with pytest.raises(rr.RRError) as ei:
+            rr.range_search(ix, q, r, mode="adaptive", beam=8, result_capacity=cap).numpy()
+        assert ei.value.status == rr.RR_ENOMEM
+    g = rr.range_search(ix, q, r, mode="adaptive", beam=8, result_capacity=500_000)
+    compare_float(g, o, r, label="after overflow")
+
+
 def test_random_graph_large(rr):
     """A seeded random graph (no locality) over 200,000 points: the beam
     search is exact on any graph, including ones where it wanders."""
