@@ -521,10 +521,40 @@ extern "C" void rr_index_free(rr_index *ix) {
 // results
 // --------------------------------------------------------------------------
 
+// Pinned host words for rr_results::h_pub: 64-byte slots carved from 4 KB
+// blocks (hipHostMalloc, coherent, so the kernel's writes go straight to
+// host memory), recycled by rr_results_free; the blocks stay allocated
+// until the process ends.  The search's last kernel writes its result count
+// and overflow flags there, and rr_results_total then waits for the stream
+// instead of issuing two blocking device-to-host copies.
+static std::mutex g_pub_mu;
+static std::vector<unsigned long long *> g_pub_free;
+
+static unsigned long long *pub_take() {
+    std::lock_guard<std::mutex> lk(g_pub_mu);
+    if (g_pub_free.empty()) {
+        void *blk = nullptr;
+        if (hipHostMalloc(&blk, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess || !blk)
+            return nullptr;
+        for (int i = 0; i < 4096 / 64; ++i)
+            g_pub_free.push_back((unsigned long long *)((char *)blk + 64 * i));
+    }
+    unsigned long long *p = g_pub_free.back();
+    g_pub_free.pop_back();
+    return p;
+}
+
+static void pub_give(unsigned long long *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pub_mu);
+    g_pub_free.push_back(p);
+}
+
 extern "C" void rr_results_free(rr_results *res) {
     if (!res) return;
     for (auto &e : res->ev)
         if (e) (void)hipEventDestroy(e);
+    pub_give(res->h_pub);
     res->alloc.release(res->block);
     res->alloc.release(res->extra);
     delete res;
@@ -862,6 +892,16 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
     if (greedy) HIP_TRY_R(launch_greedy(view, nq, cfg, sb, cus, s, res->timing ? res->ev[4] : nullptr));
     if (res->timing) HIP_TRY_R(hipEventRecord(res->ev[3], s));
     HIP_TRY_R(launch_scan_counts(sb.res_cnt, nq, res->offsets, res->scan_tmp, s));
+    // without a pinned slot rr_results_total copies the two words instead
+    if ((res->h_pub = pub_take()) != nullptr) {
+        unsigned long long *hd = nullptr;
+        if (hipHostGetDevicePointer((void **)&hd, res->h_pub, 0) == hipSuccess && hd) {
+            HIP_TRY_R(launch_publish(res->offsets + nq, sb.counters, hd, s));
+        } else {
+            pub_give(res->h_pub);
+            res->h_pub = nullptr;
+        }
+    }
 #undef HIP_TRY_R
     *out = res;
     return RR_OK;
@@ -1284,17 +1324,23 @@ extern "C" rr_status rr_probe_row_gather(const rr_index *ix, int64_t gathers, ui
 extern "C" rr_status rr_results_total(const rr_results *res, int64_t *total) {
     if (!res || !total) return fail(RR_EINVAL, "results or total is NULL");
     HIP_TRY(hipStreamSynchronize(res->stream));
-    unsigned long long ctr[CTR_COUNT];
-    HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
     int64_t tot = 0;
-    HIP_TRY(hipMemcpy(&tot, res->offsets + res->nq, sizeof tot, hipMemcpyDeviceToHost));
+    unsigned long long ovf = 0;
+    if (res->h_pub) {
+        tot = (int64_t)res->h_pub[0];
+        ovf = res->h_pub[1];
+    } else {
+        unsigned long long ctr[CTR_COUNT];
+        HIP_TRY(hipMemcpy(ctr, res->sb.counters, sizeof ctr, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&tot, res->offsets + res->nq, sizeof tot, hipMemcpyDeviceToHost));
+        ovf = ctr[CTR_OVERFLOW];
+    }
     *total = tot;
-    if (ctr[CTR_OVERFLOW] & OVERFLOW_BARRIER)
-        return fail(RR_EHIP, "the greedy phase's grid barrier timed out");
-    if (ctr[CTR_OVERFLOW])
+    if (ovf & OVERFLOW_BARRIER) return fail(RR_EHIP, "the greedy phase's grid barrier timed out");
+    if (ovf)
         return fail(RR_ENOMEM,
                     "a search capacity was exceeded (code %llu); raise result_capacity or "
-                    "max_results_per_query", (unsigned long long)ctr[CTR_OVERFLOW]);
+                    "max_results_per_query", ovf);
     return RR_OK;
 }
 

@@ -228,6 +228,10 @@ hipError_t launch_finalize(int dtype, SearchBufs &sb, int num_cus, hipStream_t s
 hipError_t launch_digit_hist(const void *keys, int key_bytes, int64_t n, unsigned long long prefix,
                              unsigned long long mask, int shift, unsigned long long *hist,
                              hipStream_t s);
+// one thread copies *total and counters[CTR_OVERFLOW] into host memory
+// (pinned, device-visible) at h[0] and h[1]
+hipError_t launch_publish(const int64_t *total, const unsigned long long *counters,
+                          unsigned long long *h, hipStream_t s);
 hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
                               hipStream_t s);
 
@@ -275,6 +279,9 @@ struct rr_results {
     // timing events: start, before beam, after beam, after the greedy phase,
     // after the greedy kernel
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // pinned host words the search's last kernel writes: [0] the total
+    // number of results, [1] the overflow flags (null: read them by copies)
+    unsigned long long *h_pub = nullptr;
 };
 
 namespace rr {

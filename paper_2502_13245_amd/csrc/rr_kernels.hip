@@ -1088,6 +1088,19 @@ __global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, 
     }
 }
 
+__global__ void k_publish(const int64_t *total, const unsigned long long *counters,
+                          unsigned long long *h) {
+    h[0] = (unsigned long long)*total;
+    h[1] = counters[CTR_OVERFLOW];
+    __threadfence_system();
+}
+
+hipError_t launch_publish(const int64_t *total, const unsigned long long *counters,
+                          unsigned long long *h, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, total, counters, h);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_counts(const int32_t *cnt, int64_t nq, int64_t *offsets, void *tmp,
                               hipStream_t s) {
     const int64_t tiles = (nq + SCAN_TILE - 1) / SCAN_TILE;

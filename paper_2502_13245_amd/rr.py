@@ -275,6 +275,13 @@ class Index:
         self._h = C.c_void_p(handle)
         self._alloc = None
         self.device = None
+        self._dt = None
+
+    def dtype_code(self) -> int:
+        """The element type code (fixed for the index's lifetime)."""
+        if self._dt is None:
+            self._dt = self.info()["dtype"]
+        return self._dt
 
     def free(self):
         """Release the host and device copies now (the index is unusable after)."""
@@ -486,7 +493,7 @@ def range_search_async(index: Index, queries, radius, params: SearchParams | Non
     out = C.c_void_p()
     _check(lib().rr_range_search(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev, C.byref(sp),
                                  index._alloc.ref(), _stream_handle(stream), C.byref(out)))
-    return PendingResults(out.value, nq, index.info()["dtype"], index._alloc, (q, keep))
+    return PendingResults(out.value, nq, index.dtype_code(), index._alloc, (q, keep))
 
 
 def range_search(index: Index, queries, radius, params: SearchParams | None = None, stream=None,
@@ -510,7 +517,7 @@ def range_search_noalloc(index: Index, queries, radius, capacity, params: Search
     nq = q.shape[0] if q.dim() == 2 else 0
     r0, rdev, keep = _radius_args(radius, nq, q.device)
     dev = q.device
-    dt = index.info()["dtype"]
+    dt = index.dtype_code()
     offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
     ids = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=dev)
     dists = torch.empty(max(int(capacity), 1), dtype=torch.float32 if dt == F32 else torch.int32,
@@ -539,7 +546,7 @@ def brute_force_async(index: Index, queries, radius, stream=None) -> PendingResu
     out = C.c_void_p()
     _check(lib().rr_brute_force(index._h, C.c_void_p(q.data_ptr()), nq, r0, rdev,
                                 index._alloc.ref(), _stream_handle(stream), C.byref(out)))
-    return PendingResults(out.value, nq, index.info()["dtype"], index._alloc, (q, keep))
+    return PendingResults(out.value, nq, index.dtype_code(), index._alloc, (q, keep))
 
 
 def brute_force(index: Index, queries, radius, stream=None) -> Results:
