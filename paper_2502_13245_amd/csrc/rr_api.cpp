@@ -874,11 +874,10 @@ extern "C" rr_status rr_range_search(const rr_index *ix, const void *queries_dev
             return fail(RR_ENOMEM, "device allocation of %zu bytes (doubling S regions) failed", pool);
         }
     }
-    HIP_TRY_R(launch_fill_u64(sb.counters, CTR_COUNT, 0ull, s));
-    if (greedy) {
-        HIP_TRY_R(launch_fill_u64(sb.level_cnt, sb.max_levels, 0ull, s));
-        HIP_TRY_R(launch_fill_u64(sb.hash, sb.hash_cap, ~0ull, s));
-    }
+    // counters, the greedy phase's level counts and (task, id) hash table
+    HIP_TRY_R(launch_fill3(FillRange{sb.counters, CTR_COUNT, 0ull},
+                           greedy ? FillRange{sb.level_cnt, sb.max_levels, 0ull} : FillRange{},
+                           greedy ? FillRange{sb.hash, sb.hash_cap, ~0ull} : FillRange{}, s));
     if (sp->timing) {
         res->timing = true;
         for (auto &e : res->ev) HIP_TRY_R(hipEventCreate(&e));

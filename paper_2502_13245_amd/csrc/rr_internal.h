@@ -206,6 +206,18 @@ hipError_t launch_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
 hipError_t launch_greedy(const DevIndex &ix, int64_t nq, const SearchCfg &cfg, SearchBufs &sb,
                          int num_cus, hipStream_t s, hipEvent_t after_kernel = nullptr);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+// Workgroups of `kern` resident per CU at this block size and dynamic LDS
+// (raising the kernel's LDS limit first when shmem is above 64 KB).  The
+// answers are remembered per device, so repeated launches make no runtime
+// queries.
+hipError_t kernel_occupancy(const void *kern, int block, size_t shmem, int *per_cu);
+// up to three fills in one launch (ranges with n = 0 or p = null are skipped)
+struct FillRange {
+    unsigned long long *p = nullptr;
+    int64_t n = 0;
+    unsigned long long v = 0;
+};
+hipError_t launch_fill3(FillRange a, FillRange b, FillRange c, hipStream_t s);
 hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, const uint8_t *qpad,
                                int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
                                const int32_t *arena_ids, const void *arena_dists, int32_t *ids,

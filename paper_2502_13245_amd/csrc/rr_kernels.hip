@@ -27,6 +27,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <utility>
 #include <cstdint>
 
 #include "rr_search.h"
@@ -811,6 +815,63 @@ __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
+hipError_t kernel_occupancy(const void *kern, int block, size_t shmem, int *per_cu) {
+    struct Key {
+        const void *kern;
+        int dev, block;
+        size_t shmem;
+        bool operator<(const Key &o) const {
+            return std::tie(kern, dev, block, shmem) < std::tie(o.kern, o.dev, o.block, o.shmem);
+        }
+    };
+    static std::mutex mu;
+    static std::map<Key, int> occ;
+    static std::map<std::pair<const void *, int>, size_t> lds_limit;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    const Key k{kern, dev, block, shmem};
+    auto it = occ.find(k);
+    if (it != occ.end()) {
+        *per_cu = it->second;
+        return hipSuccess;
+    }
+    if (shmem > 64 * 1024) {
+        size_t &lim = lds_limit[{kern, dev}];
+        if (shmem > lim) {
+            e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+            if (e != hipSuccess) return e;
+            lim = shmem;
+        }
+    }
+    int n = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, shmem);
+    if (e != hipSuccess) return e;
+    occ[k] = n;
+    *per_cu = n;
+    return hipSuccess;
+}
+
+__global__ void k_fill3(FillRange a, FillRange b, FillRange c) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < a.n; i += stride) a.p[i] = a.v;
+    for (int64_t i = i0; i < b.n; i += stride) b.p[i] = b.v;
+    for (int64_t i = i0; i < c.n; i += stride) c.p[i] = c.v;
+}
+
+hipError_t launch_fill3(FillRange a, FillRange b, FillRange c, hipStream_t s) {
+    if (!a.p) a.n = 0;
+    if (!b.p) b.n = 0;
+    if (!c.p) c.n = 0;
+    const int64_t n = std::max(a.n, std::max(b.n, c.n));
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill3, dim3(blocks), dim3(256), 0, s, a, b, c);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
@@ -826,17 +887,14 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 // append it to the result arena (greedy phase and brute force)
 template <typename D> static hipError_t run_finalize(SearchBufs &sb, int num_cus, hipStream_t s) {
     const size_t shmem = (size_t)2 * lds_len<D, sort_cap<D>()>() * sizeof(typename SortKey<D>::E);
-    hipError_t e = hipFuncSetAttribute((const void *)k_seg_sort_emit<D>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    if (e != hipSuccess) return e;
     // the long-list sort's workgroups loop over the tasks: as many as are
     // resident at once (a workgroup's LDS fills most of a CU)
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_seg_sort_emit<D>, SORT_THREADS, shmem);
+    hipError_t e = kernel_occupancy((const void *)k_seg_sort_emit<D>, SORT_THREADS, shmem, &per_cu);
     if (e != hipSuccess) return e;
     const int grid = std::max(1, per_cu) * std::max(1, num_cus);
     int short_per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&short_per_cu, k_sort_short<D>, 256, 0);
+    e = kernel_occupancy((const void *)k_sort_short<D>, 256, 0, &short_per_cu);
     if (e != hipSuccess) return e;
     const int short_grid = std::max(1, short_per_cu) * std::max(1, num_cus);
     hipLaunchKernelGGL(k_task_scan, dim3(1), dim3(1024), 0, s, sb, sort_cap<D>(), wave_sort_cap<D>());

@@ -2012,13 +2012,8 @@ static hipError_t run_beam(const DevIndex &ix, int64_t nq, const SearchCfg &cfg,
     const int waves = cfg.waves;
     const size_t shmem = (size_t)a.lds_per_wave * waves;
     auto kern = k_beam<DTYPE, CPL, G>;
-    if (shmem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (e != hipSuccess) return e;
-    }
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves * 64, shmem);
+    hipError_t e = kernel_occupancy((const void *)kern, waves * 64, shmem, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int64_t blocks = (int64_t)per_cu * num_cus;
@@ -2041,11 +2036,8 @@ static hipError_t run_greedy(const DevIndex &ix, const SearchCfg &cfg, SearchBuf
     auto kern = k_greedy<DTYPE, CPL, G>;
     constexpr int GW = greedy_waves<DTYPE, CPL>();
     const size_t shmem = sizeof(GreedyLds<D, O, GW>);
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, GW * 64, shmem);
+    hipError_t e = kernel_occupancy((const void *)kern, GW * 64, shmem, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     if (per_cu > 2) per_cu = 2;
@@ -2078,13 +2070,8 @@ static hipError_t run_doubling(const DevIndex &ix, int64_t nq, const SearchCfg &
     const int waves = cfg.waves;
     const size_t shmem = (size_t)a.lds_per_wave * waves;
     auto kern = k_doubling<DTYPE, CPL, G>;
-    if (shmem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (e != hipSuccess) return e;
-    }
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves * 64, shmem);
+    hipError_t e = kernel_occupancy((const void *)kern, waves * 64, shmem, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int64_t blocks = (int64_t)per_cu * num_cus;
