@@ -1360,8 +1360,7 @@ extern "C" rr_status rr_results_copy(const rr_results *res, int32_t *ids_dev, vo
         return RR_OK;
     }
     if (!ids_dev || !dists_dev || !offsets_dev) return fail(RR_EINVAL, "output buffers are NULL");
-    HIP_TRY(hipMemcpyAsync(offsets_dev, res->offsets, (res->nq + 1) * sizeof(int64_t),
-                           hipMemcpyDeviceToDevice, s));
+    // the copy scans the per-query counts into offsets_dev itself
     HIP_TRY(launch_results_copy(res->dtype, res->precision, res->ix, res->sb.qpad, res->nq,
                                 res->sb.res_off, res->sb.res_cnt, res->sb.arena_ids,
                                 res->sb.arena_dists, ids_dev, dists_dev, offsets_dev,
