@@ -1360,11 +1360,13 @@ extern "C" rr_status rr_results_copy(const rr_results *res, int32_t *ids_dev, vo
         return RR_OK;
     }
     if (!ids_dev || !dists_dev || !offsets_dev) return fail(RR_EINVAL, "output buffers are NULL");
-    // the copy scans the per-query counts into offsets_dev itself
+    // the search ended with the scan of the per-query counts: copy it
+    HIP_TRY(hipMemcpyAsync(offsets_dev, res->offsets, (res->nq + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_results_copy(res->dtype, res->precision, res->ix, res->sb.qpad, res->nq,
                                 res->sb.res_off, res->sb.res_cnt, res->sb.arena_ids,
                                 res->sb.arena_dists, ids_dev, dists_dev, offsets_dev,
-                                res->scan_tmp, s));
+                                res->scan_tmp, s, INT64_MAX, false));
     return RR_OK;
 }
 

@@ -222,7 +222,7 @@ hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, con
                                int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
                                const int32_t *arena_ids, const void *arena_dists, int32_t *ids,
                                void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s,
-                               int64_t capacity = INT64_MAX);
+                               int64_t capacity = INT64_MAX, bool scan_counts = true);
 size_t results_copy_tmp_bytes(int64_t nq);
 
 // brute force (rr_scan.hip)

@@ -283,12 +283,12 @@ hipError_t launch_prep_slots(const DevIndex &ix, const void *queries, int64_t k,
 // (the global merge path), then above wave_cap (a workgroup's LDS sort),
 // then the rest (one wave's LDS sort).
 __global__ void k_task_scan(SearchBufs sb, int lds_cap, int wave_cap) {
-    __shared__ unsigned long long part[1024];  // items
-    __shared__ unsigned long long opart[1024]; // listed results
-    __shared__ uint32_t cpart[3][1024];        // tasks per size class
+    constexpr int MAXW = 16; // waves of the (1024-thread) workgroup
+    __shared__ unsigned long long w_items[MAXW], w_outs[MAXW];
+    __shared__ uint32_t w_cls[3][MAXW];
     __shared__ unsigned long long s_base;
     const int64_t nt = (int64_t)sb.counters[CTR_TASKS];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6, nw = (int)(blockDim.x >> 6);
     const int64_t per = (nt + blockDim.x - 1) / blockDim.x;
     const int64_t lo = min(nt, (int64_t)tid * per), hi = min(nt, lo + per);
     const unsigned long long cap = (unsigned long long)sb.max_results;
@@ -305,34 +305,56 @@ __global__ void k_task_scan(SearchBufs sb, int lds_cap, int wave_cap) {
         const int z = cls(c);
         if (z < 3) ++k[z];
     }
-    part[tid] = s;
-    opart[tid] = o;
-    for (int z = 0; z < 3; ++z) cpart[z][tid] = k[z];
-    __syncthreads();
-    // the inclusive scans share their barriers (Hillis-Steele)
-    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
-        const bool in = tid >= d;
-        const unsigned long long v = in ? part[tid - d] : 0ull;
-        const unsigned long long w = in ? opart[tid - d] : 0ull;
-        uint32_t x[3];
-        for (int z = 0; z < 3; ++z) x[z] = in ? cpart[z][tid - d] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        opart[tid] += w;
-        for (int z = 0; z < 3; ++z) cpart[z][tid] += x[z];
-        __syncthreads();
+    // inclusive scans within the wave (shuffles), then over the wave totals
+    unsigned long long vs = s, vo = o;
+    uint32_t vk[3] = {k[0], k[1], k[2]};
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long ys = __shfl_up(vs, d), yo = __shfl_up(vo, d);
+        uint32_t yk[3];
+#pragma unroll
+        for (int z = 0; z < 3; ++z) yk[z] = __shfl_up(vk[z], d);
+        if (lane >= d) {
+            vs += ys;
+            vo += yo;
+#pragma unroll
+            for (int z = 0; z < 3; ++z) vk[z] += yk[z];
+        }
     }
-    const int last = (int)blockDim.x - 1;
-    const uint32_t n0 = cpart[0][last], n1 = cpart[1][last];
-    if (tid == last) {
-        sb.seg_off[nt] = (int64_t)part[tid];
-        sb.counters[CTR_LONG_TASKS] = (unsigned long long)(n0 + n1);
-        sb.counters[CTR_MID_TASKS] = (unsigned long long)cpart[2][last];
-        s_base = atomicAdd(&sb.counters[CTR_ARENA], opart[tid]);
+    if (lane == 63) {
+        w_items[wid] = vs;
+        w_outs[wid] = vo;
+        for (int z = 0; z < 3; ++z) w_cls[z][wid] = vk[z];
     }
     __syncthreads();
-    unsigned long long run = part[tid] - s, orun = s_base + opart[tid] - o;
-    uint32_t pos[3] = {cpart[0][tid] - k[0], n0 + cpart[1][tid] - k[1], n0 + n1 + cpart[2][tid] - k[2]};
+    unsigned long long ps = 0, po = 0, ts = 0, to = 0;
+    uint32_t pk[3] = {0u, 0u, 0u}, tk[3] = {0u, 0u, 0u};
+    for (int w = 0; w < nw; ++w) {
+        const bool before = w < wid;
+        ts += w_items[w];
+        to += w_outs[w];
+        if (before) {
+            ps += w_items[w];
+            po += w_outs[w];
+        }
+        for (int z = 0; z < 3; ++z) {
+            tk[z] += w_cls[z][w];
+            if (before) pk[z] += w_cls[z][w];
+        }
+    }
+    if (tid == 0) {
+        sb.seg_off[nt] = (int64_t)ts;
+        sb.counters[CTR_LONG_TASKS] = (unsigned long long)(tk[0] + tk[1]);
+        sb.counters[CTR_MID_TASKS] = (unsigned long long)tk[2];
+        // the tasks' sorted lists (at most max_results each) take one arena
+        // range, reserved here with a single atomic
+        s_base = atomicAdd(&sb.counters[CTR_ARENA], to);
+    }
+    __syncthreads();
+    // exclusive prefixes of this thread's tasks
+    unsigned long long run = ps + vs - s, orun = s_base + po + vo - o;
+    uint32_t pos[3] = {pk[0] + vk[0] - k[0], tk[0] + pk[1] + vk[1] - k[1],
+                       tk[0] + tk[1] + pk[2] + vk[2] - k[2]};
     for (int64_t i = lo; i < hi; ++i) {
         const unsigned long long c = sb.task_cnt[i];
         sb.seg_off[i] = (int64_t)run;
@@ -1122,6 +1144,23 @@ __device__ int64_t last_le(const int64_t *offsets, int64_t lo, int64_t hi, int64
 
 // integer keys are key_off + d: subtracting key_off modulo 2^32 gives d
 // (which fits int32) for both metrics
+// last_le by one whole wave: each round the 64 lanes probe 64 evenly spaced
+// candidates at once, so the search takes log64 rounds of dependent loads
+// instead of log2 (every lane gets the answer)
+__device__ int64_t wave_last_le(const int64_t *offsets, int64_t lo, int64_t hi, int64_t x) {
+    const int lane = lane_id();
+    while (hi > lo) {
+        const int64_t step = (hi - lo + 64) / 64; // ceil((hi - lo + 1) / 64)
+        const int64_t q = lo + (int64_t)lane * step;
+        const bool ok = q <= hi && offsets[q] <= x;
+        const unsigned long long m = __ballot(ok); // lane 0 holds (offsets[lo] <= x)
+        const int j = 63 - __clzll((long long)m);
+        lo += (int64_t)j * step;
+        hi = min(hi, lo + step - 1);
+    }
+    return lo;
+}
+
 template <typename DIN, typename DOUT>
 __global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, int64_t nq,
                                 const int32_t *aid, const DIN *ad, int32_t *ids, DOUT *dists,
@@ -1132,8 +1171,12 @@ __global__ void k_copy_segments(const int64_t *res_off, const int64_t *offsets, 
     for (int64_t b0 = (int64_t)blockIdx.x * COPY_SPAN; b0 < total;
          b0 += (int64_t)gridDim.x * COPY_SPAN) {
         const int64_t b1 = min(total, b0 + COPY_SPAN);
-        if (threadIdx.x == 0) s_q[0] = last_le(offsets, 0, nq - 1, b0);
-        if (threadIdx.x == 1) s_q[1] = last_le(offsets, 0, nq - 1, b1 - 1);
+        // the span's first and last queries, one wave each
+        if (threadIdx.x < 128) {
+            const int64_t qx = wave_last_le(offsets, 0, nq - 1, threadIdx.x < 64 ? b0 : b1 - 1);
+            if (threadIdx.x == 0) s_q[0] = qx;
+            if (threadIdx.x == 64) s_q[1] = qx;
+        }
         __syncthreads();
         const int64_t qlo = s_q[0], qhi = s_q[1];
         for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
@@ -1179,13 +1222,16 @@ hipError_t launch_results_copy(int dtype, int precision, const DevIndex &ix, con
                                int64_t nq, const int64_t *res_off, const int32_t *res_cnt,
                                const int32_t *arena_ids, const void *arena_dists, int32_t *ids,
                                void *dists, int64_t *offsets, void *scan_tmp, hipStream_t s,
-                               int64_t capacity) {
+                               int64_t capacity, bool scan_counts) {
     (void)precision;
     (void)ix;
     (void)qpad;
-    hipError_t e = launch_scan_counts(res_cnt, nq, offsets, scan_tmp, s);
-    if (e != hipSuccess || nq == 0) return e;
-    (void)res_cnt;
+    // scan_counts false: offsets already hold the scanned counts
+    if (scan_counts) {
+        hipError_t e = launch_scan_counts(res_cnt, nq, offsets, scan_tmp, s);
+        if (e != hipSuccess) return e;
+    }
+    if (nq == 0) return hipSuccess;
     const int blocks = 2048;
     if (dtype == RR_F32)
         hipLaunchKernelGGL((k_copy_segments<double, float>), dim3(blocks), dim3(256), 0, s,
