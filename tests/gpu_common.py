@@ -31,6 +31,21 @@ def compare_exact(gpu, orc, check_evals=True, label=""):
                                       err_msg=f"{label} greedy evals")
 
 
+def check_greedy_edges(gpu, adj, label=""):
+    """greedy_edges of a query that expanded counts the adjacency entries its
+    greedy phase scanned: each in-ball point it visited is expanded once
+    (Algorithm 2), and with nothing truncated those points are exactly the
+    returned list, so the count is the sum of their out-degrees in the graph;
+    a query that did not expand reports 0."""
+    off, ids, _ = gpu.numpy()
+    deg = (np.asarray(adj) >= 0).sum(axis=1).astype(np.int64)
+    st = gpu.stats
+    assert not st["truncated"].any(), f"{label} truncated"
+    for q in range(len(off) - 1):
+        want = int(deg[ids[off[q]:off[q + 1]]].sum()) if st["expanded"][q] else 0
+        assert int(st["greedy_edges"][q]) == want, f"{label} q{q} greedy_edges"
+
+
 def compare_float(gpu, orc, radius, rel=1e-5, label=""):
     """Float data: distances within `rel` (relative) of the FP64 oracle and
     equal result sets outside a +-rel band around the radius."""

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2502_13245_amd import synth
-from tests.gpu_common import compare_exact, compare_float, flush_print
+from tests.gpu_common import check_greedy_edges, compare_exact, compare_float, flush_print
 
 pytestmark = pytest.mark.gpu
 
@@ -84,6 +84,7 @@ def test_adaptive_bit_exact(rr, small_u8, beam, es):
                         beam=beam, **kw)
     o = _orc(small_u8, mode=oracle.ADAPTIVE, beam=beam, **kw)
     compare_exact(g, o, label=f"adaptive b={beam}")
+    check_greedy_edges(g, small_u8["adj"], label=f"adaptive b={beam}")
     if beam <= 16:
         assert g.stats["expanded"].sum() > 0
 
@@ -299,6 +300,7 @@ def test_heavy_expansion(rr, pct, min_max):
     g = rr.range_search(ix, q, r, mode="adaptive", beam=8, result_capacity=2_000_000)
     o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=oracle.ADAPTIVE, beam=8)
     compare_exact(g, o, label="heavy")
+    check_greedy_edges(g, adj, label="heavy")
     assert np.diff(o.offsets).max() > min_max
 
 
