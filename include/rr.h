@@ -242,6 +242,10 @@ void rr_index_free(rr_index *idx);
  * clearing costs more than they save): further queries use a hash table
  * instead.  The environment variable RR_BITMAP_BYTES sets another cap, and 0
  * disables the bitmaps.
+ * Host memory held by *out: 64 bytes of pinned host memory, into which the
+ * search's last kernel writes the result count and overflow flags for
+ * rr_results_total.  The slots come from 4 KB hipHostMalloc blocks that the
+ * library keeps and reuses until the process ends.
  * Errors: RR_EINVAL (beam < 1, vl < 1 with early stopping, NaN radius, mode
  * or precision unknown, BF16 or SQ8 precision on integer data), RR_ESTATE
  * (index not on the device), RR_ENOMEM, RR_EHIP. */
