@@ -304,6 +304,32 @@ def test_heavy_expansion(rr, pct, min_max):
     assert np.diff(o.offsets).max() > min_max
 
 
+@pytest.mark.parametrize("k", [50, 600, 9000])
+def test_max_results_on_long_lists(rr, k):
+    """max_results_per_query on lists from tens to beyond 8,192 entries (every
+    size class of the result sort, the global merge passes included): each
+    list is cut to its first k entries in the (d, id) order, and exactly the
+    longer ones are flagged truncated."""
+    w = synth.gaussian_mixture_int(20000, 64, 32, 4, 30.0, 21)
+    adj, entry = oracle.build_vamana(w.base, 16, 32, 1.2, synth.permutation(20000, 3))
+    r = oracle.percentile_radius(w.base, w.queries, 0.5)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=oracle.ADAPTIVE, beam=8)
+    counts = np.diff(o.offsets)
+    assert (counts > k).any() and counts.max() > 8192
+    flush_print(f"max results {k} on lists up to {counts.max()}")
+    g = rr.range_search(ix, q, r, mode="adaptive", beam=8, max_results_per_query=k,
+                        result_capacity=2_000_000)
+    off, ids, d = g.numpy()
+    for qi in range(len(counts)):
+        oi, od = o.query(qi)
+        m = min(len(oi), k)
+        np.testing.assert_array_equal(ids[off[qi]:off[qi + 1]], oi[:m], err_msg=f"q{qi}")
+        np.testing.assert_array_equal(d[off[qi]:off[qi + 1]].astype(np.int64), od[:m].astype(np.int64))
+        assert g.stats["truncated"][qi] == (1 if len(oi) > k else 0), f"q{qi} flag"
+
+
 def test_heavy_expansion_float(rr):
     """float32 data with more than 4096 results per query (the float LDS
     sort limit): the global merge path keeps lists ordered and complete."""
