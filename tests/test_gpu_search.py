@@ -369,6 +369,34 @@ def test_result_capacity_overflow_is_reported(rr):
     compare_float(g, o, r, label="after overflow")
 
 
+@pytest.mark.parametrize("k", [100, 5000])
+def test_max_results_on_long_float_lists(rr, k):
+    """The same cut on float data, whose lists are sorted by FP64 distance
+    (16-byte keys; lists above 4,096 entries take the merge passes): the
+    first k entries of each list are the oracle's first k, ids exact and
+    distances within float32 rounding, and exactly the longer lists are
+    flagged truncated."""
+    w = synth.gaussian_mixture_unit(6000, 24, 16, 3, 0.3 / np.sqrt(16), 23, spread=0.3)
+    adj, entry = oracle.build_vamana(w.base, 16, 32, 1.2, synth.permutation(6000, 23))
+    r = oracle.percentile_radius(w.base, w.queries, 0.8)
+    ix = rr.Index.from_graph(w.base, adj, entry).to_device("cuda:0")
+    q = torch.from_numpy(w.queries).cuda()
+    o = oracle.range_search(w.base, adj, entry, w.queries, r, mode=oracle.ADAPTIVE, beam=8)
+    counts = np.diff(o.offsets)
+    assert (counts > k).any() and counts.max() > 4096
+    flush_print(f"max results {k} on float lists up to {counts.max()}")
+    g = rr.range_search(ix, q, r, mode="adaptive", beam=8, max_results_per_query=k,
+                        result_capacity=500_000)
+    off, ids, d = g.numpy()
+    for qi in range(len(counts)):
+        oi, od = o.query(qi)
+        m = min(len(oi), k)
+        np.testing.assert_array_equal(ids[off[qi]:off[qi + 1]], oi[:m], err_msg=f"q{qi}")
+        np.testing.assert_allclose(d[off[qi]:off[qi + 1]].astype(np.float64), od[:m], rtol=1e-6,
+                                   err_msg=f"q{qi}")
+        assert g.stats["truncated"][qi] == (1 if len(oi) > k else 0), f"q{qi} flag"
+
+
 def test_random_graph_large(rr):
     """A seeded random graph (no locality) over 200,000 points: the beam
     search is exact on any graph, including ones where it wanders."""
